@@ -1,0 +1,152 @@
+"""CPU oracle for batched big-integer addition and multiplication.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only code that may import this package.  It shares no
+code with the HIP library (``paper_2405_14642_amd``) and neither imports the
+other; the seeded input generator in ``workloads`` is the only module both use.
+
+What it computes (plain definitions, Section 2 and eq. (1) of Section 3.1):
+
+* ``add(a, b)``  -> ((a + b) mod 2^(n w), carry out), limb by limb with a
+  double-width sum; the carry out is the extra result the library returns
+  beside the paper's same-length sum.
+* ``mul(a, b)``  -> the full 2n-limb product a * b (schoolbook rows); the
+  paper's same-length product is its low n limbs.
+
+Arrays are numpy (batch, n) of uint32 or uint64 limbs, little-endian,
+instance-major.  uint64 limbs are processed as twice as many uint32 limbs,
+which is the same byte string on a little-endian host.
+
+Pins (tests/test_oracle_pins.py): brute force against Python integers on all
+small limb combinations, Python's own bignum at every workload size, closed
+forms (all-ones + 1, (2^N - 1)^2, 2^i * 2^j), invariants (commutativity,
+(a+b)^2 = a^2 + 2ab + b^2, residues modulo small primes and 2^32 +- 1), and
+planted mistakes in a copy of the C source that the pins must catch.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCE = os.path.join(_HERE, "bigint_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def compile_source(src: str, out: str) -> str:
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", src, "-o", tmp])
+    os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(SOURCE):
+        compile_source(SOURCE, _LIB)
+    return _LIB
+
+
+def _bind(path: str):
+    lib = ctypes.CDLL(path)
+    P, U64, I = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+    lib.oracle_add.argtypes = [P, P, P, P, U64, U64, I]
+    lib.oracle_mul.argtypes = [P, P, P, U64, U64, I]
+    lib.oracle_mul_ragged.argtypes = [P, P, P, P, P, P, P, U64, I]
+    lib.oracle_add_ragged.argtypes = [P, P, P, P, P, P, P, P, U64, I]
+    for f in (lib.oracle_add, lib.oracle_mul, lib.oracle_mul_ragged, lib.oracle_add_ragged):
+        f.restype = I
+    return lib
+
+
+class Oracle:
+    """Bound oracle library (a planted-mistake copy can be bound the same way)."""
+
+    def __init__(self, path: str):
+        self.lib = _bind(path)
+        self.last_threads = 0
+
+    @staticmethod
+    def _u32(x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x)
+        if x.dtype not in (np.uint32, np.uint64):
+            raise TypeError("limbs must be uint32 or uint64")
+        if x.ndim == 1:
+            x = x[None, :]
+        return x.view(np.uint32)
+
+    def add(self, a: np.ndarray, b: np.ndarray, threads: int = 0):
+        dtype = np.asarray(a).dtype
+        a32, b32 = self._u32(a), self._u32(b)
+        if a32.shape != b32.shape:
+            raise ValueError("operand shapes differ")
+        batch, n = a32.shape
+        out = np.empty_like(a32)
+        carry = np.empty(batch, dtype=np.uint8)
+        self.last_threads = self.lib.oracle_add(a32.ctypes.data, b32.ctypes.data, out.ctypes.data,
+                                                carry.ctypes.data, n, batch, threads)
+        return out.view(dtype).reshape(batch, -1), carry
+
+    def mul(self, a: np.ndarray, b: np.ndarray, threads: int = 0):
+        dtype = np.asarray(a).dtype
+        a32, b32 = self._u32(a), self._u32(b)
+        if a32.shape != b32.shape:
+            raise ValueError("operand shapes differ")
+        batch, n = a32.shape
+        out = np.empty((batch, 2 * n), dtype=np.uint32)
+        self.last_threads = self.lib.oracle_mul(a32.ctypes.data, b32.ctypes.data, out.ctypes.data,
+                                                n, batch, threads)
+        return out.view(dtype).reshape(batch, -1)
+
+    def mul_ragged(self, pairs, threads: int = 0):
+        """pairs: list of (a, b) uint32 1-D arrays of equal length per pair."""
+        ns = np.array([len(p[0]) for p in pairs], dtype=np.uint32)
+        off = np.zeros(len(pairs), dtype=np.uint64)
+        if len(pairs) > 1:
+            off[1:] = np.cumsum(ns[:-1].astype(np.uint64))
+        A = np.concatenate([np.asarray(p[0], dtype=np.uint32) for p in pairs]) if pairs else np.zeros(0, np.uint32)
+        B = np.concatenate([np.asarray(p[1], dtype=np.uint32) for p in pairs]) if pairs else np.zeros(0, np.uint32)
+        out = np.empty(int(2 * ns.astype(np.uint64).sum()), dtype=np.uint32)
+        ooff = (2 * off).astype(np.uint64)
+        self.last_threads = self.lib.oracle_mul_ragged(A.ctypes.data, B.ctypes.data, out.ctypes.data,
+                                                       off.ctypes.data, off.ctypes.data, ooff.ctypes.data,
+                                                       ns.ctypes.data, len(pairs), threads)
+        return [out[int(o):int(o) + 2 * int(k)] for o, k in zip(ooff, ns)]
+
+
+_default: Oracle | None = None
+
+
+def get() -> Oracle:
+    global _default
+    if _default is None:
+        if not os.path.exists(_LIB):
+            build()
+        _default = Oracle(_LIB)
+    return _default
+
+
+def add(a, b, threads: int = 0):
+    return get().add(a, b, threads)
+
+
+def mul(a, b, threads: int = 0):
+    return get().mul(a, b, threads)
+
+
+def mul_ragged(pairs, threads: int = 0):
+    return get().mul_ragged(pairs, threads)
+
+
+# ------------------------------------------------------------ conversions
+def to_int(limbs) -> int:
+    """Python integer of one little-endian limb vector (uint32 or uint64)."""
+    x = np.ascontiguousarray(np.asarray(limbs))
+    return int.from_bytes(x.tobytes(), "little")
+
+
+def from_int(v: int, n: int, dtype=np.uint32) -> np.ndarray:
+    w = np.dtype(dtype).itemsize
+    return np.frombuffer(v.to_bytes(n * w, "little"), dtype=dtype).copy()
