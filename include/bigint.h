@@ -1,0 +1,138 @@
+/*
+ * bigint.h -- C ABI of the MI355X (gfx950) batched big-integer library.
+ *
+ * Method: Oancea & Watt, "GPU Implementations for Midsize Integer Addition
+ * and Multiplication" (arXiv 2405.14642).  One integer (or a few small ones)
+ * per wavefront/workgroup, operands held in VGPRs and LDS.
+ *
+ * Representation (Section 2): an integer of n limbs of w bits is the
+ * little-endian limb array a_0 .. a_{n-1}, value sum a_i 2^(w i).  A batch is
+ * instance-major and contiguous: instance p occupies limbs [p n, (p+1) n).
+ * w is 32 or 64 per call; n * w may not exceed BI_MAX_BITS.
+ *
+ * Memory and ownership: every data pointer is a device pointer (HBM) owned by
+ * the caller, who must keep it alive until the work queued on `stream` has
+ * completed.  Pointers must be aligned to the limb size.  The library never
+ * frees or retains them.  A context owns only its own tables and scratch.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  Every compute
+ * entry point only validates and enqueues; results are ready once the stream
+ * has been synchronised.
+ *
+ * Errors: return codes only; nothing aborts and no C++ exception crosses the
+ * ABI.  Argument validation is synchronous, touches no GPU state, runs before
+ * any HIP call and leaves outputs untouched when it fails.  Launch failures
+ * are reported as BI_EHIP; asynchronous device faults surface at the caller's
+ * next synchronisation.  bi_last_error() gives a message for the last failing
+ * call on the calling host thread.  A context is not thread-safe: use one per
+ * host thread or serialise calls.
+ */
+#ifndef BIGINT_MI355X_H
+#define BIGINT_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BI_MAX_BITS (1u << 18) /* largest integer, in bits (Section 1: up to ~2^18 bits) */
+
+typedef enum bi_status {
+    BI_OK = 0,
+    BI_EINVAL = -1, /* null pointer, null context, zero size, unknown option  */
+    BI_ESIZE = -2,  /* n_limbs * limb_bits > BI_MAX_BITS, or batch too large  */
+    BI_ELIMB = -3,  /* limb_bits not 32 or 64, or a pointer not limb-aligned  */
+    BI_EALIAS = -4, /* output overlaps an input where the operation forbids it */
+    BI_EHIP = -5,   /* a HIP runtime call or kernel launch failed             */
+    BI_ENOMEM = -6, /* device allocation of context scratch failed            */
+    BI_EALGO = -7,  /* the requested multiplication algorithm cannot run this size */
+    BI_ENODEV = -8  /* no usable gfx950 device                                 */
+} bi_status;
+
+typedef enum bi_mul_algo {
+    BI_MUL_AUTO = 0,         /* the context's tuned choice for (n, batch)            */
+    BI_MUL_SCHOOL_VALU = 1,  /* load-balanced schoolbook on the VALU (Section 3)     */
+    BI_MUL_SCHOOL_MFMA = 2,  /* schoolbook on int8 MFMA, signed 8-bit digits         */
+    BI_MUL_NTT = 3           /* NTT over two word-size primes + CRT (Section 4)       */
+} bi_mul_algo;
+
+typedef struct bi_ctx bi_ctx;
+
+/* Create a context on HIP device `device` (the device is made current for
+ * the call).  Allocates the context's device tables (NTT twiddles).
+ * Returns BI_ENODEV if the device does not exist or is not gfx950,
+ * BI_ENOMEM / BI_EHIP on allocation or copy failure; *out is NULL then. */
+bi_status bi_ctx_create(int device, bi_ctx **out);
+
+/* Release a context and its device tables.  Waits for nothing: the caller
+ * must have synchronised every stream that used it.  NULL is ignored. */
+void bi_ctx_destroy(bi_ctx *ctx);
+
+/* Static description of a status code.  Never NULL. */
+const char *bi_status_str(int status);
+
+/* Message for the last failing call on this host thread ("" if none). */
+const char *bi_last_error(void);
+
+/*
+ * bigadd -- Section 2 (addition as a carry-propagation scan, Fig. 2) and its
+ * batched form bbadd.  For each of `batch` instances:
+ *     out[p]       = (a[p] + b[p]) mod 2^(n_limbs * limb_bits)
+ *     carry_out[p] = floor((a[p] + b[p]) / 2^(n_limbs * limb_bits))  (0 or 1)
+ * a, b, out: batch * n_limbs limbs each.  carry_out: batch bytes, or NULL.
+ * out may be identical to a or to b (in-place); any other overlap of out or
+ * carry_out with the inputs is BI_EALIAS.
+ */
+bi_status bigadd(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t *carry_out,
+                 uint32_t n_limbs, uint32_t limb_bits, uint64_t batch, void *stream);
+
+/*
+ * bigmul -- full product, eq. (1) of Section 3.1 without truncation: for each
+ * instance out[p] (2 * n_limbs limbs) = a[p] * b[p].  The paper's same-length
+ * product (Figs. 4-6) is the low n_limbs limbs of out[p].
+ * a, b: batch * n_limbs limbs; out: batch * 2 * n_limbs limbs, which must not
+ * overlap a or b (BI_EALIAS).  algo selects the method:
+ *   BI_MUL_SCHOOL_VALU   Section 3: each thread owns load-balanced output
+ *                        coefficients, accumulating double-width products and
+ *                        an overflow count; then a carry scan (Section 2).
+ *   BI_MUL_SCHOOL_MFMA   the same convolution on int8 matrix cores, over
+ *                        balanced signed base-256 digits with int32 sums that
+ *                        cannot overflow, then a signed carry normalisation.
+ *   BI_MUL_NTT           Section 4: number-theoretic transforms modulo primes
+ *                        k 2^m + 1 over 16-bit coefficients, recombined by the
+ *                        Chinese remainder theorem, then a carry scan.
+ *   BI_MUL_AUTO          the fastest of the above for (n_limbs, batch).
+ * Results are exact (bit-identical across algorithms).
+ */
+bi_status bigmul(bi_ctx *ctx, const void *a, const void *b, void *out,
+                 uint32_t n_limbs, uint32_t limb_bits, uint64_t batch, int algo, void *stream);
+
+/*
+ * Ragged batches: instance p has desc[p].n_limbs limbs (>= 1) starting at limb
+ * offset desc[p].a_off in a and desc[p].b_off in b; its result starts at limb
+ * offset desc[p].out_off in out (n_limbs limbs for bigadd_v, 2 n_limbs for
+ * bigmul_v) and its carry (bigadd_v) at carry_out[p].  `desc` is a DEVICE
+ * array of `count` descriptors; its contents are not validated on the host
+ * (offsets must stay inside the caller's buffers).  Output ranges of different
+ * instances must not overlap each other or any input range.
+ * Batching across sizes is the library's own extension (the paper's batches
+ * are uniform, Section 6.1).
+ */
+typedef struct bi_desc {
+    uint64_t a_off, b_off, out_off; /* in limbs */
+    uint32_t n_limbs;
+    uint32_t reserved;              /* must be 0 */
+} bi_desc;
+
+bi_status bigadd_v(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t *carry_out,
+                   const bi_desc *desc, uint64_t count, uint32_t limb_bits, void *stream);
+
+bi_status bigmul_v(bi_ctx *ctx, const void *a, const void *b, void *out,
+                   const bi_desc *desc, uint64_t count, uint32_t limb_bits, int algo, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIGINT_MI355X_H */

@@ -1,0 +1,154 @@
+"""Batched midsize big-integer arithmetic on MI355X (gfx950).
+
+Thin Python binding over the C ABI in ``include/bigint.h`` (library
+``libbigint.so`` next to this file).  It only marshals arguments: every step
+of addition and multiplication runs in the library's HIP kernels.  Device
+memory and streams come from PyTorch (tensors are used as raw limb buffers).
+
+The names follow the C ABI: ``bigadd``, ``bigmul``, ``bigadd_v``,
+``bigmul_v``; ``Context`` wraps ``bi_ctx``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["Context", "BigIntError", "bigadd", "bigmul", "bigadd_v", "bigmul_v", "lib", "library_path",
+           "MUL_AUTO", "MUL_SCHOOL_VALU", "MUL_SCHOOL_MFMA", "MUL_NTT", "MAX_BITS", "STATUS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libbigint.so")
+
+MUL_AUTO, MUL_SCHOOL_VALU, MUL_SCHOOL_MFMA, MUL_NTT = 0, 1, 2, 3
+MAX_BITS = 1 << 18
+STATUS = {0: "BI_OK", -1: "BI_EINVAL", -2: "BI_ESIZE", -3: "BI_ELIMB", -4: "BI_EALIAS", -5: "BI_EHIP",
+          -6: "BI_ENOMEM", -7: "BI_EALGO", -8: "BI_ENODEV"}
+
+EXPORTS = ("bi_ctx_create", "bi_ctx_destroy", "bi_status_str", "bi_last_error",
+           "bigadd", "bigmul", "bigadd_v", "bigmul_v")
+
+
+class BigIntError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{self.name}: {message}")
+
+
+def _load():
+    if not os.path.exists(library_path):
+        raise ImportError(f"{library_path} is missing: the HIP library has not been built "
+                          "(run __graft_entry__.build() or python -m paper_2405_14642_amd.build)")
+    L = ctypes.CDLL(library_path)
+    P, U32, U64, I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    L.bi_ctx_create.argtypes = [I, ctypes.POINTER(P)]
+    L.bi_ctx_destroy.argtypes = [P]
+    L.bi_ctx_destroy.restype = None
+    L.bi_status_str.argtypes = [I]
+    L.bi_status_str.restype = ctypes.c_char_p
+    L.bi_last_error.argtypes = []
+    L.bi_last_error.restype = ctypes.c_char_p
+    L.bigadd.argtypes = [P, P, P, P, P, U32, U32, U64, P]
+    L.bigmul.argtypes = [P, P, P, P, U32, U32, U64, I, P]
+    L.bigadd_v.argtypes = [P, P, P, P, P, P, U64, U32, P]
+    L.bigmul_v.argtypes = [P, P, P, P, P, U64, U32, I, P]
+    for f in (L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v):
+        f.restype = I
+    return L
+
+
+lib = _load()
+
+
+def _check(st: int):
+    if st != 0:
+        raise BigIntError(st, lib.bi_last_error().decode())
+
+
+def _ptr(x):
+    """Device address of a tensor, an int address, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream, ref=None):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    dev = ref.device if ref is not None and hasattr(ref, "device") else None
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _limb_bits(t, limb_bits):
+    if limb_bits is not None:
+        return limb_bits
+    size = t.element_size()
+    if size not in (4, 8):
+        raise ValueError("limb tensors must have 4- or 8-byte elements")
+    return 8 * size
+
+
+class Context:
+    """A library context (bi_ctx) on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib.bi_ctx_create(device, ctypes.byref(h)))
+        self.handle = h.value
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib.bi_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _h(ctx):
+    return None if ctx is None else (ctx if isinstance(ctx, int) else ctx.handle)
+
+
+def bigadd(ctx, a, b, out, carry=None, n_limbs=None, limb_bits=None, batch=None, stream=None):
+    """out = a + b per instance (and carry bytes).  Tensors are (batch, n) limb arrays."""
+    lb = _limb_bits(a, limb_bits)
+    n = n_limbs if n_limbs is not None else a.shape[-1]
+    bt = batch if batch is not None else (a.numel() // n if n else 0)
+    _check(lib.bigadd(_h(ctx), _ptr(a), _ptr(b), _ptr(out), _ptr(carry), n, lb, bt, _stream(stream, a)))
+    return out
+
+
+def bigmul(ctx, a, b, out, algo=MUL_AUTO, n_limbs=None, limb_bits=None, batch=None, stream=None):
+    """out (batch, 2n) = a * b per instance."""
+    lb = _limb_bits(a, limb_bits)
+    n = n_limbs if n_limbs is not None else a.shape[-1]
+    bt = batch if batch is not None else (a.numel() // n if n else 0)
+    _check(lib.bigmul(_h(ctx), _ptr(a), _ptr(b), _ptr(out), n, lb, bt, int(algo), _stream(stream, a)))
+    return out
+
+
+def bigadd_v(ctx, a, b, out, carry, desc, count, limb_bits, stream=None):
+    """Ragged addition; desc is a device buffer of `count` bi_desc records
+    (uint64 a_off, b_off, out_off; uint32 n_limbs, reserved)."""
+    _check(lib.bigadd_v(_h(ctx), _ptr(a), _ptr(b), _ptr(out), _ptr(carry), _ptr(desc), count, limb_bits,
+                        _stream(stream, a)))
+    return out
+
+
+def bigmul_v(ctx, a, b, out, desc, count, limb_bits, algo=MUL_AUTO, stream=None):
+    _check(lib.bigmul_v(_h(ctx), _ptr(a), _ptr(b), _ptr(out), _ptr(desc), count, limb_bits, int(algo),
+                        _stream(stream, a)))
+    return out

@@ -1,0 +1,215 @@
+// C ABI of the library: argument validation (host only, before any HIP call)
+// and dispatch to the kernel launchers.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "bi_internal.hpp"
+
+struct bi_ctx {
+    int device = 0;
+    bi::Ctx impl;
+};
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+namespace bi {
+bi_status set_error(bi_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+}  // namespace bi
+
+namespace {
+
+template <typename... Args>
+bi_status fail(bi_status s, const char *fmt, Args... args) {
+    return bi::set_error(s, fmt, args...);
+}
+
+bi_status hip_fail(hipError_t e, const char *what) {
+    return fail(BI_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool overlaps(const void *p, uint64_t pn, const void *q, uint64_t qn) {
+    if (!p || !q || pn == 0 || qn == 0) return false;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p), b = reinterpret_cast<uintptr_t>(q);
+    return a < b + qn && b < a + pn;
+}
+
+// Common shape checks for uniform batches.  On success *bytes = bytes per operand.
+bi_status check_shape(uint32_t n_limbs, uint32_t limb_bits, uint64_t batch, uint64_t *inst_bytes) {
+    if (limb_bits != 32 && limb_bits != 64) return fail(BI_ELIMB, "limb_bits must be 32 or 64 (got %u)", limb_bits);
+    if (n_limbs == 0) return fail(BI_EINVAL, "n_limbs must be >= 1");
+    if (uint64_t(n_limbs) * limb_bits > BI_MAX_BITS)
+        return fail(BI_ESIZE, "n_limbs * limb_bits = %llu exceeds %u bits",
+                    (unsigned long long)(uint64_t(n_limbs) * limb_bits), BI_MAX_BITS);
+    *inst_bytes = uint64_t(n_limbs) * (limb_bits / 8);
+    if (batch > (uint64_t(1) << 40) / *inst_bytes) return fail(BI_ESIZE, "batch too large");
+    return BI_OK;
+}
+
+bi_status check_ptr(const void *p, uint32_t limb_bits, const char *name) {
+    if (!p) return fail(BI_EINVAL, "%s is NULL", name);
+    if (reinterpret_cast<uintptr_t>(p) % (limb_bits / 8))
+        return fail(BI_ELIMB, "%s is not aligned to %u-bit limbs", name, limb_bits);
+    return BI_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev) {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *bi_status_str(int s) {
+    switch (s) {
+        case BI_OK: return "ok";
+        case BI_EINVAL: return "invalid argument";
+        case BI_ESIZE: return "size out of range";
+        case BI_ELIMB: return "bad limb width or alignment";
+        case BI_EALIAS: return "output overlaps an input";
+        case BI_EHIP: return "HIP runtime error";
+        case BI_ENOMEM: return "device allocation failed";
+        case BI_EALGO: return "algorithm unavailable for this size";
+        case BI_ENODEV: return "no usable gfx950 device";
+        default: return "unknown status";
+    }
+}
+
+const char *bi_last_error(void) { return g_err; }
+
+bi_status bi_ctx_create(int device, bi_ctx **out) {
+    if (!out) return fail(BI_EINVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(BI_ENODEV, "no HIP device");
+    if (device < 0 || device >= count) return fail(BI_ENODEV, "device %d out of range (%d devices)", device, count);
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(BI_ENODEV, "device %d is %s, not gfx950", device, prop.gcnArchName);
+    bi_ctx *c = new (std::nothrow) bi_ctx;
+    if (!c) return fail(BI_ENOMEM, "host allocation failed");
+    c->device = device;
+    DeviceGuard g(device);
+    if (g.err != hipSuccess) {
+        delete c;
+        return hip_fail(g.err, "hipSetDevice");
+    }
+    bi_status st = bi::ctx_init(c->impl, device, prop);
+    if (st != BI_OK) {
+        bi::ctx_release(c->impl);
+        delete c;
+        return st == BI_ENOMEM ? fail(st, "device table allocation failed") : fail(st, "context set-up failed");
+    }
+    *out = c;
+    return BI_OK;
+}
+
+void bi_ctx_destroy(bi_ctx *ctx) {
+    if (!ctx) return;
+    {
+        DeviceGuard g(ctx->device);
+        bi::ctx_release(ctx->impl);
+    }
+    delete ctx;
+}
+
+bi_status bigadd(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t *carry_out, uint32_t n_limbs,
+                 uint32_t limb_bits, uint64_t batch, void *stream) {
+    uint64_t ib = 0;
+    bi_status s = check_shape(n_limbs, limb_bits, batch, &ib);
+    if (s != BI_OK) return s;
+    if (batch == 0) return ctx ? BI_OK : fail(BI_EINVAL, "ctx is NULL");
+    if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
+    if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;
+    if ((s = check_ptr(out, limb_bits, "out")) != BI_OK) return s;
+    const uint64_t tot = ib * batch;
+    if (out != a && overlaps(out, tot, a, tot)) return fail(BI_EALIAS, "out partially overlaps a");
+    if (out != b && overlaps(out, tot, b, tot)) return fail(BI_EALIAS, "out partially overlaps b");
+    if (overlaps(carry_out, batch, a, tot) || overlaps(carry_out, batch, b, tot) || overlaps(carry_out, batch, out, tot))
+        return fail(BI_EALIAS, "carry_out overlaps an operand");
+    if (!ctx) return fail(BI_EINVAL, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = bi::launch_bigadd(a, b, out, carry_out, ib, batch, static_cast<hipStream_t>(stream), ctx->impl.add);
+    if (e != hipSuccess) return hip_fail(e, "bigadd launch");
+    return BI_OK;
+}
+
+bi_status bigmul(bi_ctx *ctx, const void *a, const void *b, void *out, uint32_t n_limbs, uint32_t limb_bits,
+                 uint64_t batch, int algo, void *stream) {
+    uint64_t ib = 0;
+    bi_status s = check_shape(n_limbs, limb_bits, batch, &ib);
+    if (s != BI_OK) return s;
+    if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT) return fail(BI_EINVAL, "unknown algorithm %d", algo);
+    if (batch == 0) return ctx ? BI_OK : fail(BI_EINVAL, "ctx is NULL");
+    if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
+    if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;
+    if ((s = check_ptr(out, limb_bits, "out")) != BI_OK) return s;
+    const uint64_t tot = ib * batch;
+    if (overlaps(out, 2 * tot, a, tot) || overlaps(out, 2 * tot, b, tot)) return fail(BI_EALIAS, "out overlaps an input");
+    if (!ctx) return fail(BI_EINVAL, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    // The multiplication kernels work on 32-bit limbs; 64-bit limbs are the
+    // same byte string with twice as many limbs.
+    const uint32_t n32 = n_limbs * (limb_bits / 32);
+    return bi::dispatch_bigmul(ctx->impl, a, b, out, n32, batch, algo, static_cast<hipStream_t>(stream));
+}
+
+bi_status bigadd_v(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t *carry_out, const bi_desc *desc,
+                   uint64_t count, uint32_t limb_bits, void *stream) {
+    if (limb_bits != 32 && limb_bits != 64) return fail(BI_ELIMB, "limb_bits must be 32 or 64 (got %u)", limb_bits);
+    if (count == 0) return ctx ? BI_OK : fail(BI_EINVAL, "ctx is NULL");
+    if (!desc) return fail(BI_EINVAL, "desc is NULL");
+    bi_status s;
+    if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
+    if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;
+    if ((s = check_ptr(out, limb_bits, "out")) != BI_OK) return s;
+    if (reinterpret_cast<uintptr_t>(desc) % alignof(bi_desc)) return fail(BI_EINVAL, "desc is not 8-byte aligned");
+    if (!ctx) return fail(BI_EINVAL, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    return bi::dispatch_bigadd_v(ctx->impl, a, b, out, carry_out, desc, count, limb_bits, static_cast<hipStream_t>(stream));
+}
+
+bi_status bigmul_v(bi_ctx *ctx, const void *a, const void *b, void *out, const bi_desc *desc, uint64_t count,
+                   uint32_t limb_bits, int algo, void *stream) {
+    if (limb_bits != 32 && limb_bits != 64) return fail(BI_ELIMB, "limb_bits must be 32 or 64 (got %u)", limb_bits);
+    if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT) return fail(BI_EINVAL, "unknown algorithm %d", algo);
+    if (count == 0) return ctx ? BI_OK : fail(BI_EINVAL, "ctx is NULL");
+    if (!desc) return fail(BI_EINVAL, "desc is NULL");
+    bi_status s;
+    if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
+    if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;
+    if ((s = check_ptr(out, limb_bits, "out")) != BI_OK) return s;
+    if (reinterpret_cast<uintptr_t>(desc) % alignof(bi_desc)) return fail(BI_EINVAL, "desc is not 8-byte aligned");
+    if (!ctx) return fail(BI_EINVAL, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    return bi::dispatch_bigmul_v(ctx->impl, a, b, out, desc, count, limb_bits, algo, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,214 @@
+// Batched big-integer addition (Section 2, Fig. 2: bbadd = map badd).
+//
+// Addition is byte-width agnostic: a little-endian integer of n limbs of w
+// bits is the same byte string whatever w is, so the kernels work on "chunks"
+// of W 32-bit words (W = 4, 2 or 1; 16, 8 or 4 bytes), one chunk per lane.
+// A chunk is the paper's efficient-sequentialisation unit (Q consecutive
+// limbs per thread): the lane adds its chunk sequentially with carry-in 0 and
+// reduces it to a generate bit (the chunk sum overflowed) and a propagate bit
+// (the chunk sum is all-ones), which never hold together.  The carries across
+// the 64 chunks of a wavefront "row" then come out of one 64-bit addition of
+// the ballot masks (bi::wave_carry); a final map adds the carry into the chunk.
+//
+// Two schedules, both with one wavefront per independent piece of work and no
+// LDS or barriers at all:
+//  * packed rows (an instance has m <= 64 chunks): a row holds
+//    ipr = floor(64/m) whole instances.  The segmented scan of Fig. 2 becomes
+//    masking: generate/propagate bits of the last chunk of every instance are
+//    cleared, so no carry crosses an instance boundary and each instance starts
+//    with carry-in 0.  (Clearing them is what makes the exclusive segmented
+//    scan correct at segment starts.)
+//  * streamed rows (m > 64): one wavefront walks an instance from the least
+//    significant row upward, carrying the scalar carry-out of each row into the
+//    next.  Loads of U rows are issued before any of them is consumed.
+#include "bi_common.hpp"
+#include "bi_internal.hpp"
+
+namespace bi {
+
+template <int W, int U>
+__global__ __launch_bounds__(256) void bigadd_packed_kernel(const uint32_t *__restrict__ a,
+                                                            const uint32_t *__restrict__ b,
+                                                            uint32_t *out, uint8_t *carry,
+                                                            uint32_t m, uint32_t ipr, uint64_t batch) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
+    const uint32_t slot = lane / m;           // instance within the row
+    const uint32_t pos = lane - slot * m;     // chunk within the instance
+    const bool in_row = slot < ipr;
+    const uint64_t E = ballot(in_row && pos == m - 1);  // last chunk of each instance
+    const uint64_t nrows = (batch + ipr - 1) / ipr;
+
+    for (uint64_t r0 = wave * U; r0 < nrows; r0 += nwaves * U) {
+        uint32_t va[U][W], vb[U][W];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t inst = (r0 + u) * ipr + slot;
+            ok[u] = in_row && (r0 + u) < nrows && inst < batch;
+            if (ok[u]) {
+                const uint64_t off = (inst * m + pos) * W;
+                load_words<W>(a + off, va[u]);
+                load_words<W>(b + off, vb[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            uint32_t s[W];
+            const uint32_t g = add_words<W>(va[u], vb[u], s);
+            const bool p = all_ones<W>(s);
+            const uint64_t G = ballot(ok[u] && g) & ~E;
+            const uint64_t P = ballot(ok[u] && p) & ~E;
+            const WaveCarry wc = wave_carry(G, P, 0u);
+            const uint32_t cin = uint32_t(wc.into >> lane) & 1u;
+            if (ok[u]) {
+                const uint64_t inst = (r0 + u) * ipr + slot;
+                if (carry && pos == m - 1) carry[inst] = uint8_t(g | (p & cin));
+                add_carry_words<W>(s, cin);
+                store_words<W>(out + (inst * m + pos) * W, s);
+            }
+        }
+    }
+}
+
+// One wavefront adds one instance of m chunks, least significant row first.
+// Returns (in every lane) the carry out of the instance.
+template <int W, int U>
+__device__ __forceinline__ uint32_t add_instance_streamed(const uint32_t *__restrict__ ai,
+                                                          const uint32_t *__restrict__ bi_, uint32_t *oi,
+                                                          uint32_t m, uint32_t lane) {
+    const uint32_t rows = (m + 63) / 64;
+    uint32_t cin_row = 0;
+    for (uint32_t r0 = 0; r0 < rows; r0 += U) {
+        uint32_t va[U][W], vb[U][W];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t c = (r0 + u) * 64 + lane;
+            if (c < m) {
+                load_words<W>(ai + uint64_t(c) * W, va[u]);
+                load_words<W>(bi_ + uint64_t(c) * W, vb[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (r0 + u < rows) {  // uniform
+                const uint32_t c = (r0 + u) * 64 + lane;
+                const bool ok = c < m;
+                uint32_t s[W];
+                const uint32_t g = add_words<W>(va[u], vb[u], s);
+                const bool p = all_ones<W>(s);
+                const uint64_t G = ballot(ok && g);
+                const uint64_t P = ballot(ok && p);
+                const WaveCarry wc = wave_carry(G, P, cin_row);
+                const uint32_t cin = uint32_t(wc.into >> lane) & 1u;
+                if (ok) {
+                    add_carry_words<W>(s, cin);
+                    store_words<W>(oi + uint64_t(c) * W, s);
+                }
+                // Carry out of this row: out of lane 63 for a full row,
+                // otherwise the carry into the first unused lane.
+                const uint32_t valid = m - (r0 + u) * 64;
+                cin_row = valid >= 64 ? wc.out : uint32_t(wc.into >> valid) & 1u;
+            }
+        }
+    }
+    return cin_row;
+}
+
+template <int W, int U>
+__global__ __launch_bounds__(256) void bigadd_stream_kernel(const uint32_t *__restrict__ a,
+                                                            const uint32_t *__restrict__ b,
+                                                            uint32_t *out, uint8_t *carry,
+                                                            uint32_t m, uint64_t batch) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
+    for (uint64_t inst = wave; inst < batch; inst += nwaves) {
+        const uint64_t off = inst * m * W;
+        const uint32_t c = add_instance_streamed<W, U>(a + off, b + off, out + off, m, lane);
+        if (carry && lane == 0) carry[inst] = uint8_t(c);
+    }
+}
+
+// Ragged batch: one wavefront per descriptor, chunks of one limb (W words).
+template <int W, int U>
+__global__ __launch_bounds__(256) void bigadd_ragged_kernel(const uint32_t *__restrict__ a,
+                                                            const uint32_t *__restrict__ b,
+                                                            uint32_t *out, uint8_t *carry,
+                                                            const bi_desc *__restrict__ desc, uint64_t count) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
+    for (uint64_t i = wave; i < count; i += nwaves) {
+        const bi_desc d = desc[i];
+        const uint32_t c = add_instance_streamed<W, U>(a + d.a_off * W, b + d.b_off * W, out + d.out_off * W,
+                                                       d.n_limbs, lane);
+        if (carry && lane == 0) carry[i] = uint8_t(c);
+    }
+}
+
+// Largest chunk (in bytes) that divides the instance length and all pointers.
+static int pick_chunk_bytes(uint64_t inst_bytes, const void *a, const void *b, const void *o) {
+    const uint64_t al = uint64_t(reinterpret_cast<uintptr_t>(a)) | uint64_t(reinterpret_cast<uintptr_t>(b)) |
+                        uint64_t(reinterpret_cast<uintptr_t>(o)) | inst_bytes;
+    if ((al & 15) == 0) return 16;
+    if ((al & 7) == 0) return 8;
+    return 4;
+}
+
+template <int W>
+static hipError_t launch_w(const uint32_t *a, const uint32_t *b, uint32_t *o, uint8_t *carry, uint64_t m,
+                           uint64_t batch, hipStream_t st, const AddTune &t) {
+    const int threads = 256;
+    if (m <= 64) {
+        const uint32_t ipr = uint32_t(64 / m);
+        const uint64_t nrows = (batch + ipr - 1) / ipr;
+        constexpr int U = 4;
+        uint64_t waves = (nrows + U - 1) / U;
+        if (waves > t.max_waves) waves = t.max_waves;
+        const uint64_t blocks = (waves + 3) / 4;
+        hipLaunchKernelGGL((bigadd_packed_kernel<W, U>), dim3(uint32_t(blocks)), dim3(threads), 0, st, a, b, o, carry,
+                           uint32_t(m), ipr, batch);
+    } else {
+        constexpr int U = 4;
+        uint64_t waves = batch;
+        if (waves > t.max_waves) waves = t.max_waves;
+        const uint64_t blocks = (waves + 3) / 4;
+        hipLaunchKernelGGL((bigadd_stream_kernel<W, U>), dim3(uint32_t(blocks)), dim3(threads), 0, st, a, b, o, carry,
+                           uint32_t(m), batch);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bigadd_ragged(const void *a, const void *b, void *out, uint8_t *carry, const bi_desc *desc,
+                                uint64_t count, uint32_t limb_bits, hipStream_t st, const AddTune &t) {
+    if (count == 0) return hipSuccess;
+    uint64_t waves = count < t.max_waves ? count : t.max_waves;
+    const uint64_t blocks = (waves + 3) / 4;
+    auto A = static_cast<const uint32_t *>(a);
+    auto B = static_cast<const uint32_t *>(b);
+    auto O = static_cast<uint32_t *>(out);
+    if (limb_bits == 64)
+        hipLaunchKernelGGL((bigadd_ragged_kernel<2, 4>), dim3(uint32_t(blocks)), dim3(256), 0, st, A, B, O, carry, desc, count);
+    else
+        hipLaunchKernelGGL((bigadd_ragged_kernel<1, 4>), dim3(uint32_t(blocks)), dim3(256), 0, st, A, B, O, carry, desc, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_bigadd(const void *a, const void *b, void *out, uint8_t *carry, uint64_t inst_bytes,
+                         uint64_t batch, hipStream_t st, const AddTune &t) {
+    if (batch == 0) return hipSuccess;
+    const int cb = pick_chunk_bytes(inst_bytes, a, b, out);
+    const uint64_t m = inst_bytes / cb;
+    auto A = static_cast<const uint32_t *>(a);
+    auto B = static_cast<const uint32_t *>(b);
+    auto O = static_cast<uint32_t *>(out);
+    switch (cb) {
+        case 16: return launch_w<4>(A, B, O, carry, m, batch, st, t);
+        case 8: return launch_w<2>(A, B, O, carry, m, batch, st, t);
+        default: return launch_w<1>(A, B, O, carry, m, batch, st, t);
+    }
+}
+
+}  // namespace bi

@@ -1,0 +1,101 @@
+"""Host-side checks of the C ABI (no GPU needed): exported symbols, status
+strings and argument validation, which runs before any HIP call."""
+from __future__ import annotations
+
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    import paper_2405_14642_amd as B
+    return B
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "bigint.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w]+\s*\*?\s*(bi\w+|big\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_symbols_exported(B):
+    names = _declared_functions()
+    assert set(names) >= {"bigadd", "bigmul", "bigadd_v", "bigmul_v", "bi_ctx_create"}
+    for n in names:
+        assert hasattr(B.lib, n), f"{n} declared in include/bigint.h but not exported"
+    assert set(B.EXPORTS) == set(names)
+
+
+def test_status_strings(B):
+    for code in range(-8, 1):
+        assert B.lib.bi_status_str(code)
+    assert B.lib.bi_status_str(-99) == b"unknown status"
+
+
+FAKE = 0x10000  # never dereferenced: every call below fails validation first
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(limb_bits=16), -3),
+    (dict(limb_bits=0), -3),
+    (dict(n=0), -1),
+    (dict(n=(1 << 18) // 32 + 1), -2),
+    (dict(n=(1 << 18) // 64 + 1, limb_bits=64), -2),
+    (dict(batch=1 << 40), -2),
+    (dict(a=None), -1),
+    (dict(b=None), -1),
+    (dict(out=None), -1),
+    (dict(a=FAKE + 2), -3),
+    (dict(out=FAKE + 4, limb_bits=64), -3),
+    (dict(out=FAKE + 4), -4),                     # out partially overlaps a
+    (dict(carry=FAKE + 8), -4),                   # carry bytes inside a
+    (dict(), -1),                                 # all valid, but ctx is NULL
+    (dict(out=FAKE), -1),                         # in-place is allowed: fails only on ctx
+])
+def test_bigadd_validation(B, args, status):
+    p = dict(a=FAKE, b=FAKE + (1 << 24), out=FAKE + (2 << 24), carry=None, n=4, limb_bits=32, batch=8)
+    p.update(args)
+    st = B.lib.bigadd(None, p["a"], p["b"], p["out"], p["carry"], p["n"], p["limb_bits"], p["batch"], None)
+    assert st == status, B.lib.bi_last_error()
+    assert B.lib.bi_last_error()
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(limb_bits=8), -3),
+    (dict(n=0), -1),
+    (dict(n=8193), -2),
+    (dict(algo=9), -1),
+    (dict(algo=-1), -1),
+    (dict(out=FAKE), -4),                         # product may not alias a
+    (dict(out=FAKE + (1 << 24) - 8), -4),         # overlaps b
+    (dict(a=FAKE + 1), -3),
+    (dict(), -1),
+])
+def test_bigmul_validation(B, args, status):
+    p = dict(a=FAKE, b=FAKE + (1 << 24), out=FAKE + (2 << 24), n=4, limb_bits=32, batch=8, algo=0)
+    p.update(args)
+    st = B.lib.bigmul(None, p["a"], p["b"], p["out"], p["n"], p["limb_bits"], p["batch"], p["algo"], None)
+    assert st == status, B.lib.bi_last_error()
+
+
+def test_empty_batch_needs_only_ctx(B):
+    assert B.lib.bigadd(None, None, None, None, None, 4, 32, 0, None) == -1
+    assert B.lib.bigmul(None, None, None, None, 4, 32, 0, 0, None) == -1
+
+
+def test_ragged_validation(B):
+    assert B.lib.bigadd_v(None, FAKE, FAKE, FAKE, None, FAKE, 1, 48, None) == -3
+    assert B.lib.bigadd_v(None, FAKE, FAKE, FAKE, None, None, 1, 32, None) == -1
+    assert B.lib.bigadd_v(None, FAKE, FAKE, FAKE, None, FAKE + 4, 1, 32, None) == -1
+    assert B.lib.bigmul_v(None, FAKE, FAKE, FAKE, FAKE, 1, 32, 7, None) == -1
+    assert B.lib.bigmul_v(None, FAKE, FAKE, FAKE, FAKE, 1, 32, 0, None) == -1
+
+
+def test_binding_raises(B):
+    with pytest.raises(B.BigIntError) as e:
+        B.bigadd(None, FAKE, FAKE, FAKE + 4, n_limbs=4, limb_bits=32, batch=8, stream=0)
+    assert e.value.status == -4
