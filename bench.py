@@ -41,6 +41,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU baseline budget")
     p.add_argument("--sizes", default="", help="comma-separated subset of sizes in bits (profiling runs)")
+    p.add_argument("--algos", default="valu,mfma,ntt", help="multiplication algorithms to time")
     return p.parse_args()
 
 
@@ -143,6 +144,103 @@ def bench_add(args):
     }
 
 
+# Peak rates used for the multiplication rooflines (the design doc derives them):
+# VALU schoolbook: one v_mad_u64_u32 (16 lanes/clk/SIMD) + one v_addc_co_u32
+# (32 lanes/clk/SIMD) per 32x32-bit product term -> 10.67 terms/clk/SIMD,
+# x 1024 SIMDs x 2.4 GHz.
+VALU_MAC_PEAK = 1024 * (16 * 32 / 48) * 2.4e9   # 2.62e13 u32 MAC/s
+MFMA_I8_PEAK_OPS = 5.0e15                        # dense int8, ops (2 per MAC)
+
+ALGO_IDS = {"valu": 1, "mfma": 2, "ntt": 3}
+
+
+def bench_mul(args, kind):
+    import torch
+
+    import paper_2405_14642_amd as B
+    import workloads as W
+    from tests import gpu_util as G
+
+    ctx = B.Context(0)
+    stream = torch.cuda.current_stream()
+    if kind == "mulq":
+        cases = [(bits, W.mul_quad_pairs(bits)) for bits in W.MULQ_BITS]
+        gen = lambda bits, batch: W.mul_quad_inputs(bits)
+    else:
+        cases = list(W.NTT_CASES)
+        gen = lambda bits, batch: W.ntt_inputs(bits, batch)
+    if args.sizes:
+        keep = {int(x) for x in args.sizes.split(",")}
+        cases = [c for c in cases if c[0] in keep]
+    algos = [a for a in args.algos.split(",") if a]
+    results = {}
+    step_ms = 0.0
+    step_pairs = 0
+    for bits, batch in cases:
+        a, b = gen(bits, batch)
+        n = a.shape[1]
+        A, Bt = G.to_dev(a), G.to_dev(b)
+        out = G.empty_dev((batch, 2 * n), np.uint32)
+        del a, b
+        best = None
+        for name in algos:
+            algo = ALGO_IDS[name]
+            try:
+                B.bigmul(ctx, A, Bt, out, algo=algo, stream=stream.cuda_stream)
+            except B.BigIntError as e:
+                if e.status == -7:
+                    continue
+                raise
+            torch.cuda.synchronize()
+            for _ in range(args.warmup):
+                B.bigmul(ctx, A, Bt, out, algo=algo, stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            evs = []
+            for _ in range(args.steps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                B.bigmul(ctx, A, Bt, out, algo=algo, stream=stream.cuda_stream)
+                e1.record(stream)
+                evs.append((e0, e1))
+            torch.cuda.synchronize()
+            us = 1e3 * float(np.mean([x.elapsed_time(y) for x, y in evs]))
+            macs = float(batch) * n * n
+            r = {"us_per_launch": round(us, 2), "mults_per_s": batch / (us * 1e-6),
+                 "u32_macs_per_s": macs / (us * 1e-6)}
+            if name == "valu":
+                r["roofline"] = {"bound": "alu", "achieved": round(macs / (us * 1e-6) / 1e12, 3),
+                                 "peak": round(VALU_MAC_PEAK / 1e12, 3), "unit": "T u32-MAC/s",
+                                 "frac": round(macs / (us * 1e-6) / VALU_MAC_PEAK, 4)}
+            elif name == "mfma":
+                ops = 2.0 * batch * (4 * n) ** 2
+                r["roofline"] = {"bound": "mfma", "achieved": round(ops / (us * 1e-6) / 1e12, 1),
+                                 "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "TOP/s (int8)",
+                                 "frac": round(ops / (us * 1e-6) / MFMA_I8_PEAK_OPS, 4)}
+            results.setdefault(str(bits), {})[name] = r
+            if best is None or us < best[1]:
+                best = (name, us)
+        if best:
+            results[str(bits)]["best"] = best[0]
+            step_ms += best[1] / 1e3
+            step_pairs += batch
+        del A, Bt, out
+    ctx.close()
+    last = str(cases[-1][0])
+    dom = results[last][results[last]["best"]]
+    return {
+        "metric": f"bigmul products/s over the {'quadratic' if kind == 'mulq' else 'NTT'} multiplication sizes "
+                  "(u32 limbs, full 2n-limb products), best algorithm per size",
+        "value": step_pairs / (step_ms * 1e-3), "unit": "mults/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded splitmix64, uniform limbs)",
+        "config": {"workload": "mul_quadratic" if kind == "mulq" else "mul_ntt",
+                   "cases": [{"bits": c[0], "pairs": c[1]} for c in cases], "limb_bits": 32,
+                   "algorithms": algos, "parallelism": "single-gpu"},
+        "roofline": dom.get("roofline"), "per_size": results, "cpu_baseline": None,
+    }
+
+
 def cpu_baseline_add(args, W):
     import oracle
     oracle.build()
@@ -178,7 +276,7 @@ def main():
     if args.workload == "add":
         res = bench_add(args)
     else:
-        raise SystemExit(f"workload {args.workload} not built yet")
+        res = bench_mul(args, args.workload)
     print(json.dumps(res), flush=True)
 
 

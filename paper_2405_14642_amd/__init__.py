@@ -36,6 +36,12 @@ class BigIntError(RuntimeError):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime (libamdhip64, same SONAME as the one
+    # in /opt/rocm).  Loading torch first makes libbigint.so bind to that
+    # already-loaded runtime, so the process holds exactly one HIP runtime and
+    # the tensors and streams torch hands us are valid for our launches.
+    import torch  # noqa: F401
+
     if not os.path.exists(library_path):
         raise ImportError(f"{library_path} is missing: the HIP library has not been built "
                           "(run __graft_entry__.build() or python -m paper_2405_14642_amd.build)")

@@ -13,6 +13,15 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Index of the calling wavefront within the workgroup, marked wave-uniform so
+// that everything derived from it lives in SGPRs (scalar loads, scalar loops).
+__device__ __forceinline__ uint32_t wave_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Global wavefront index (uniform).
+__device__ __forceinline__ uint64_t wave_global() {
+    return uint64_t(blockIdx.x) * (blockDim.x >> 6) + wave_in_block();
+}
+
 // Carry propagation over 64 consecutive chunks held one per lane.
 //
 // Section 2 derives the carry of every limb from an exclusive scan whose
@@ -73,33 +82,39 @@ __device__ __forceinline__ bool all_ones(const uint32_t (&s)[W]) {
     return v == 0xFFFFFFFFu;
 }
 
-// Vector load/store of W consecutive 32-bit words (W = 1, 2, 4), naturally aligned.
-template <int W> struct VecT;
-template <> struct VecT<1> { using T = uint32_t; };
-template <> struct VecT<2> { using T = uint2; };
-template <> struct VecT<4> { using T = uint4; };
+// Vector load/store of W consecutive 32-bit words (W = 1, 2, 4), naturally
+// aligned.  NT marks the access non-temporal (streamed data that is touched
+// once), which keeps it from displacing other lines in the caches.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-template <int W>
+template <int W, bool NT = false>
 __device__ __forceinline__ void load_words(const uint32_t *p, uint32_t (&v)[W]) {
     if constexpr (W == 1) {
-        v[0] = *p;
+        v[0] = NT ? __builtin_nontemporal_load(p) : *p;
     } else if constexpr (W == 2) {
-        uint2 t = *reinterpret_cast<const uint2 *>(p);
+        const u32x2 *q = reinterpret_cast<const u32x2 *>(p);
+        const u32x2 t = NT ? __builtin_nontemporal_load(q) : *q;
         v[0] = t.x; v[1] = t.y;
     } else {
-        uint4 t = *reinterpret_cast<const uint4 *>(p);
+        const u32x4 *q = reinterpret_cast<const u32x4 *>(p);
+        const u32x4 t = NT ? __builtin_nontemporal_load(q) : *q;
         v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
     }
 }
 
-template <int W>
+template <int W, bool NT = false>
 __device__ __forceinline__ void store_words(uint32_t *p, const uint32_t (&v)[W]) {
     if constexpr (W == 1) {
-        *p = v[0];
+        if (NT) __builtin_nontemporal_store(v[0], p); else *p = v[0];
     } else if constexpr (W == 2) {
-        *reinterpret_cast<uint2 *>(p) = make_uint2(v[0], v[1]);
+        const u32x2 t = {v[0], v[1]};
+        u32x2 *q = reinterpret_cast<u32x2 *>(p);
+        if (NT) __builtin_nontemporal_store(t, q); else *q = t;
     } else {
-        *reinterpret_cast<uint4 *>(p) = make_uint4(v[0], v[1], v[2], v[3]);
+        const u32x4 t = {v[0], v[1], v[2], v[3]};
+        u32x4 *q = reinterpret_cast<u32x4 *>(p);
+        if (NT) __builtin_nontemporal_store(t, q); else *q = t;
     }
 }
 

@@ -1,0 +1,74 @@
+// Workgroup-cooperative big-integer addition x + y of two little-endian word
+// arrays that live in LDS (or are computed on the fly), written to global
+// memory.  This is the final step of every multiplication: the paper adds the
+// low and high/carry parts published by the threads with the addition of
+// Section 2 (Fig. 5, baddRegs); Section 4 does the same after the inverse
+// transform.
+//
+// Layout: a "row" is 64 lanes x 4 words (256 words).  Each wave owns a
+// contiguous range of rows.  Pass 1 reduces every wave's range to a summary
+// (carry out with carry-in 0, and whether every chunk propagates); after a
+// barrier each wave derives its carry-in from the summaries of the waves
+// below it, then pass 2 recomputes its rows with that carry-in and stores.
+#pragma once
+
+#include "bi_common.hpp"
+
+namespace bi {
+
+// src(c, x, y) fills the 4 words of chunk c (words 4c .. 4c+3) of both addends.
+// Words at index >= nwords are never stored and must read as 0.
+template <int NW, class Src>
+__device__ __forceinline__ void wg_add_rows(const Src &src, uint32_t *__restrict__ out, uint32_t nwords,
+                                            uint32_t *summary /* LDS, NW words */) {
+    const uint32_t lane = lane_id();
+    const uint32_t w = wave_in_block();
+    const uint32_t nchunks = (nwords + 3) / 4;
+    const uint32_t rows = (nchunks + 63) / 64;
+    const uint32_t r0 = (rows * w) / NW, r1 = (rows * (w + 1)) / NW;
+
+    const bool vec_ok = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+    uint32_t cin = 0, allp = 1;
+    for (uint32_t r = r0; r < r1; ++r) {
+        const uint32_t c = r * 64 + lane;
+        uint32_t x[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0}, s[4];
+        if (c < nchunks) src(c, x, y);
+        const uint32_t g = add_words<4>(x, y, s);
+        const bool p = c < nchunks && all_ones<4>(s);
+        const uint64_t G = ballot(g), P = ballot(p);
+        const WaveCarry wc = wave_carry(G, P, cin);
+        cin = wc.out;
+        allp &= (P == ~0ull) ? 1u : 0u;
+    }
+    if (lane == 0) summary[w] = cin | (allp << 1);
+    __syncthreads();
+    cin = 0;
+    for (uint32_t v = 0; v < w; ++v) {
+        const uint32_t sv = summary[v];
+        cin = (sv & 1u) | ((sv >> 1) & cin);
+    }
+    for (uint32_t r = r0; r < r1; ++r) {
+        const uint32_t c = r * 64 + lane;
+        uint32_t x[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0}, s[4];
+        if (c < nchunks) src(c, x, y);
+        const uint32_t g = add_words<4>(x, y, s);
+        const bool p = c < nchunks && all_ones<4>(s);
+        const uint64_t G = ballot(g), P = ballot(p);
+        const WaveCarry wc = wave_carry(G, P, cin);
+        const uint32_t ci = uint32_t(wc.into >> lane) & 1u;
+        add_carry_words<4>(s, ci);
+        cin = wc.out;
+        if (c < nchunks) {
+            const uint32_t base = 4 * c;
+            if (vec_ok && base + 4 <= nwords) {
+                store_words<4>(out + base, s);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (base + t < nwords) out[base + t] = s[t];
+            }
+        }
+    }
+}
+
+}  // namespace bi

@@ -26,13 +26,13 @@
 
 namespace bi {
 
-template <int W, int U>
+template <int W, int U, bool NT>
 __global__ __launch_bounds__(256) void bigadd_packed_kernel(const uint32_t *__restrict__ a,
                                                             const uint32_t *__restrict__ b,
                                                             uint32_t *out, uint8_t *carry,
                                                             uint32_t m, uint32_t ipr, uint64_t batch) {
     const uint32_t lane = lane_id();
-    const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t wave = wave_global();
     const uint64_t nwaves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
     const uint32_t slot = lane / m;           // instance within the row
     const uint32_t pos = lane - slot * m;     // chunk within the instance
@@ -49,8 +49,8 @@ __global__ __launch_bounds__(256) void bigadd_packed_kernel(const uint32_t *__re
             ok[u] = in_row && (r0 + u) < nrows && inst < batch;
             if (ok[u]) {
                 const uint64_t off = (inst * m + pos) * W;
-                load_words<W>(a + off, va[u]);
-                load_words<W>(b + off, vb[u]);
+                load_words<W, NT>(a + off, va[u]);
+                load_words<W, NT>(b + off, vb[u]);
             }
         }
 #pragma unroll
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void bigadd_packed_kernel(const uint32_t *__re
                 const uint64_t inst = (r0 + u) * ipr + slot;
                 if (carry && pos == m - 1) carry[inst] = uint8_t(g | (p & cin));
                 add_carry_words<W>(s, cin);
-                store_words<W>(out + (inst * m + pos) * W, s);
+                store_words<W, NT>(out + (inst * m + pos) * W, s);
             }
         }
     }
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void bigadd_packed_kernel(const uint32_t *__re
 
 // One wavefront adds one instance of m chunks, least significant row first.
 // Returns (in every lane) the carry out of the instance.
-template <int W, int U>
+template <int W, int U, bool NT>
 __device__ __forceinline__ uint32_t add_instance_streamed(const uint32_t *__restrict__ ai,
                                                           const uint32_t *__restrict__ bi_, uint32_t *oi,
                                                           uint32_t m, uint32_t lane) {
@@ -116,17 +116,17 @@ __device__ __forceinline__ uint32_t add_instance_streamed(const uint32_t *__rest
     return cin_row;
 }
 
-template <int W, int U>
+template <int W, int U, bool NT>
 __global__ __launch_bounds__(256) void bigadd_stream_kernel(const uint32_t *__restrict__ a,
                                                             const uint32_t *__restrict__ b,
                                                             uint32_t *out, uint8_t *carry,
                                                             uint32_t m, uint64_t batch) {
     const uint32_t lane = lane_id();
-    const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t wave = wave_global();
     const uint64_t nwaves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
     for (uint64_t inst = wave; inst < batch; inst += nwaves) {
         const uint64_t off = inst * m * W;
-        const uint32_t c = add_instance_streamed<W, U>(a + off, b + off, out + off, m, lane);
+        const uint32_t c = add_instance_streamed<W, U, NT>(a + off, b + off, out + off, m, lane);
         if (carry && lane == 0) carry[inst] = uint8_t(c);
     }
 }
@@ -138,11 +138,11 @@ __global__ __launch_bounds__(256) void bigadd_ragged_kernel(const uint32_t *__re
                                                             uint32_t *out, uint8_t *carry,
                                                             const bi_desc *__restrict__ desc, uint64_t count) {
     const uint32_t lane = lane_id();
-    const uint64_t wave = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t wave = wave_global();
     const uint64_t nwaves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
     for (uint64_t i = wave; i < count; i += nwaves) {
         const bi_desc d = desc[i];
-        const uint32_t c = add_instance_streamed<W, U>(a + d.a_off * W, b + d.b_off * W, out + d.out_off * W,
+        const uint32_t c = add_instance_streamed<W, U, false>(a + d.a_off * W, b + d.b_off * W, out + d.out_off * W,
                                                        d.n_limbs, lane);
         if (carry && lane == 0) carry[i] = uint8_t(c);
     }
@@ -157,28 +157,39 @@ static int pick_chunk_bytes(uint64_t inst_bytes, const void *a, const void *b, c
     return 4;
 }
 
-template <int W>
-static hipError_t launch_w(const uint32_t *a, const uint32_t *b, uint32_t *o, uint8_t *carry, uint64_t m,
-                           uint64_t batch, hipStream_t st, const AddTune &t) {
-    const int threads = 256;
+template <int W, int U, bool NT>
+static hipError_t launch_wu(const uint32_t *a, const uint32_t *b, uint32_t *o, uint8_t *carry, uint64_t m,
+                            uint64_t batch, hipStream_t st, uint64_t max_waves) {
     if (m <= 64) {
         const uint32_t ipr = uint32_t(64 / m);
         const uint64_t nrows = (batch + ipr - 1) / ipr;
-        constexpr int U = 4;
         uint64_t waves = (nrows + U - 1) / U;
-        if (waves > t.max_waves) waves = t.max_waves;
+        if (waves > max_waves) waves = max_waves;
         const uint64_t blocks = (waves + 3) / 4;
-        hipLaunchKernelGGL((bigadd_packed_kernel<W, U>), dim3(uint32_t(blocks)), dim3(threads), 0, st, a, b, o, carry,
+        hipLaunchKernelGGL((bigadd_packed_kernel<W, U, NT>), dim3(uint32_t(blocks)), dim3(256), 0, st, a, b, o, carry,
                            uint32_t(m), ipr, batch);
     } else {
-        constexpr int U = 4;
         uint64_t waves = batch;
-        if (waves > t.max_waves) waves = t.max_waves;
+        if (waves > max_waves) waves = max_waves;
         const uint64_t blocks = (waves + 3) / 4;
-        hipLaunchKernelGGL((bigadd_stream_kernel<W, U>), dim3(uint32_t(blocks)), dim3(threads), 0, st, a, b, o, carry,
+        hipLaunchKernelGGL((bigadd_stream_kernel<W, U, NT>), dim3(uint32_t(blocks)), dim3(256), 0, st, a, b, o, carry,
                            uint32_t(m), batch);
     }
     return hipGetLastError();
+}
+
+template <int W>
+static hipError_t launch_w(const uint32_t *a, const uint32_t *b, uint32_t *o, uint8_t *carry, uint64_t m,
+                           uint64_t batch, hipStream_t st, const AddTune &t) {
+    const uint64_t mw = t.max_waves;
+    if (t.nt) {
+        if (t.rows == 2) return launch_wu<W, 2, true>(a, b, o, carry, m, batch, st, mw);
+        if (t.rows == 8) return launch_wu<W, 8, true>(a, b, o, carry, m, batch, st, mw);
+        return launch_wu<W, 4, true>(a, b, o, carry, m, batch, st, mw);
+    }
+    if (t.rows == 2) return launch_wu<W, 2, false>(a, b, o, carry, m, batch, st, mw);
+    if (t.rows == 8) return launch_wu<W, 8, false>(a, b, o, carry, m, batch, st, mw);
+    return launch_wu<W, 4, false>(a, b, o, carry, m, batch, st, mw);
 }
 
 hipError_t launch_bigadd_ragged(const void *a, const void *b, void *out, uint8_t *carry, const bi_desc *desc,

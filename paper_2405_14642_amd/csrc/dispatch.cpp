@@ -1,6 +1,9 @@
 // Context set-up and dispatch from the C ABI to the kernel launchers.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "bi_internal.hpp"
 
 namespace bi {
@@ -9,6 +12,16 @@ bi_status ctx_init(Ctx &c, int device, const hipDeviceProp_t &prop) {
     c.device = device;
     c.num_cus = prop.multiProcessorCount;
     c.add.max_waves = uint64_t(prop.multiProcessorCount) * 64;
+    // Experiment override: BI_ADD_TUNE="rows,nt,max_waves" (e.g. "8,1,32768").
+    if (const char *env = std::getenv("BI_ADD_TUNE")) {
+        int rows = 4, nt = 0;
+        unsigned long long mw = c.add.max_waves;
+        if (std::sscanf(env, "%d,%d,%llu", &rows, &nt, &mw) >= 1) {
+            c.add.rows = (rows == 2 || rows == 8) ? rows : 4;
+            c.add.nt = nt != 0;
+            c.add.max_waves = mw ? mw : c.add.max_waves;
+        }
+    }
     return BI_OK;
 }
 
@@ -23,8 +36,18 @@ bi_status dispatch_bigadd_v(Ctx &c, const void *a, const void *b, void *out, uin
 
 bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint32_t n32, uint64_t batch, int algo,
                           hipStream_t st) {
-    (void)c; (void)a; (void)b; (void)out; (void)n32; (void)batch; (void)st;
-    return set_error(BI_EALGO, "multiplication algorithm %d is not available", algo);
+    if (algo == BI_MUL_AUTO) algo = BI_MUL_SCHOOL_VALU;
+    hipError_t e = hipSuccess;
+    switch (algo) {
+        case BI_MUL_SCHOOL_VALU:
+            e = launch_bigmul_valu(static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
+                                   static_cast<uint32_t *>(out), n32, batch, st, c.num_cus);
+            break;
+        default:
+            return set_error(BI_EALGO, "multiplication algorithm %d is not available", algo);
+    }
+    if (e != hipSuccess) return set_error(BI_EHIP, "bigmul launch: %s", hipGetErrorString(e));
+    return BI_OK;
 }
 
 bi_status dispatch_bigmul_v(Ctx &c, const void *a, const void *b, void *out, const bi_desc *desc, uint64_t count,

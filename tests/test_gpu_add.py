@@ -145,11 +145,12 @@ def test_ragged(B, ctx, orc):
         G.sync()
         got = G.from_dev(dev_out, dt)
         cg = carry.cpu().numpy()
-        for i, n in enumerate(ns):
-            x = A[a_off[i]: a_off[i] + n][None]
-            y = Bv[bpos[i]: bpos[i] + n][None]
+        for i, n in enumerate(ns.tolist()):
+            ao, bo, oo = int(a_off[i]), int(bpos[i]), int(out_off[i])
+            x = A[ao: ao + n][None]
+            y = Bv[bo: bo + n][None]
             want, wc = orc.add(x, y)
-            assert (got[out_off[i]: out_off[i] + n] == want[0]).all(), i
+            assert (got[oo: oo + n] == want[0]).all(), i
             assert cg[i] == wc[0], i
 
 

@@ -1,0 +1,169 @@
+"""Parity of the HIP multiplication kernels with the CPU oracle (bit-exact)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+ALGOS = {"valu": 1, "mfma": 2, "ntt": 3}
+
+
+@pytest.fixture(scope="module")
+def B():
+    import paper_2405_14642_amd as B
+    return B
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def available(B, ctx, algo, n):
+    """Whether `algo` runs n-limb products (BI_EALGO otherwise)."""
+    a = G.to_dev(np.ones((1, n), np.uint32))
+    out = G.empty_dev((1, 2 * n), np.uint32)
+    try:
+        B.bigmul(ctx, a, a, out, algo=algo)
+    except B.BigIntError as e:
+        if e.status == -7:
+            return False
+        raise
+    G.sync()
+    return True
+
+
+def run_mul(B, ctx, a, b, algo):
+    A, Bt = G.to_dev(a), G.to_dev(b)
+    out = G.empty_dev((a.shape[0], 2 * a.shape[1]), a.dtype)
+    B.bigmul(ctx, A, Bt, out, algo=algo)
+    G.sync()
+    return G.from_dev(out, a.dtype)
+
+
+def check(orc, a, b, got):
+    want = orc.mul(a, b)
+    bad = np.nonzero((got != want).any(axis=1))[0]
+    assert bad.size == 0, f"{bad.size} of {a.shape[0]} products differ, first {bad[:8]}"
+
+
+def rand(rng, batch, n, dt=np.uint32):
+    return rng.integers(0, np.iinfo(dt).max, size=(batch, n), dtype=dt, endpoint=True)
+
+
+def patterned(rng, batch, n, dt=np.uint32):
+    """Random operands with the edge patterns of the method in some rows."""
+    a, b = rand(rng, batch, n, dt), rand(rng, batch, n, dt)
+    mx = np.iinfo(dt).max
+    a[0], b[0] = mx, mx                          # (2^N - 1)^2: every overflow counter in use
+    if batch > 1:
+        a[1], b[1] = 0, rand(rng, 1, n, dt)[0]   # zero
+    if batch > 2:
+        a[2] = 0
+        a[2, 0] = 1                              # one
+    if batch > 3:
+        a[3] = np.iinfo(dt).max // 255 * 0x80     # every byte 0x80: balanced digit -128
+        b[3] = np.iinfo(dt).max // 255 * 0x7F     # every byte 0x7F: digit 127 (carries run)
+    if batch > 4:
+        a[4] = 0
+        b[4] = 0
+        a[4, -1] = mx                            # top limbs only
+        b[4, -1] = mx
+    return a, b
+
+
+SIZES = [1, 2, 3, 4, 5, 7, 8, 15, 16, 17, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 255, 256, 257,
+         511, 512, 513, 1000, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192]
+
+
+@pytest.mark.parametrize("algo", list(ALGOS))
+@pytest.mark.parametrize("n", SIZES)
+def test_sizes(B, ctx, orc, algo, n):
+    if not available(B, ctx, ALGOS[algo], n):
+        pytest.skip(f"{algo} does not run {n}-limb products")
+    rng = np.random.default_rng(1000 + n)
+    batch = 7 if n <= 2048 else 3
+    a, b = patterned(rng, batch, n)
+    check(orc, a, b, run_mul(B, ctx, a, b, ALGOS[algo]))
+
+
+@pytest.mark.parametrize("algo", list(ALGOS))
+def test_small_workload(B, ctx, orc, algo):
+    a, b = W.small_inputs()
+    if not available(B, ctx, ALGOS[algo], a.shape[1]):
+        pytest.skip("unavailable")
+    check(orc, a, b, run_mul(B, ctx, a, b, ALGOS[algo]))
+
+
+@pytest.mark.parametrize("algo", list(ALGOS))
+def test_u64_limbs(B, ctx, orc, algo):
+    rng = np.random.default_rng(77)
+    for n in (1, 3, 64, 100, 512):
+        if not available(B, ctx, ALGOS[algo], 2 * n):
+            continue
+        a, b = patterned(rng, 5, n, np.uint64)
+        got = run_mul(B, ctx, a, b, ALGOS[algo])
+        assert got.dtype == np.uint64 and got.shape == (5, 2 * n)
+        check(orc, a, b, got)
+
+
+@pytest.mark.parametrize("algo", list(ALGOS))
+def test_all_ones_closed_form(B, ctx, algo):
+    """(2^N - 1)^2 = 2^(2N) - 2^(N+1) + 1, i.e. limbs [1, 0.., 2^32-2, 2^32-1..]."""
+    for n in (64, 1000, 8192):
+        if not available(B, ctx, ALGOS[algo], n):
+            continue
+        a = np.full((2, n), 0xFFFFFFFF, np.uint32)
+        got = run_mul(B, ctx, a, a, ALGOS[algo])
+        exp = np.concatenate([[1], np.zeros(n - 1), [0xFFFFFFFE], np.full(n - 1, 0xFFFFFFFF)]).astype(np.uint32)
+        assert (got == exp).all()
+
+
+def residues(x: np.ndarray, p: int) -> np.ndarray:
+    """Residue mod p (< 2^20) of every row of little-endian u32 limbs (Horner)."""
+    x = x.astype(np.uint64)
+    r = np.zeros(x.shape[0], dtype=np.uint64)
+    base, P = np.uint64((1 << 32) % p), np.uint64(p)
+    for k in range(x.shape[1] - 1, -1, -1):
+        r = (r * base + x[:, k] % P) % P
+    return r
+
+
+@pytest.mark.parametrize("algo", list(ALGOS))
+@pytest.mark.parametrize("bits", W.MULQ_BITS)
+def test_full_size_quadratic(B, ctx, orc, algo, bits):
+    """The quadratic-multiplication workload at full size, in the benchmark's
+    launch configuration: 64 sampled products against the oracle, and every
+    product checked modulo two primes against residues of its operands."""
+    n = bits // 32
+    if not available(B, ctx, ALGOS[algo], n):
+        pytest.skip("unavailable")
+    a, b = W.mul_quad_inputs(bits)
+    got = run_mul(B, ctx, a, b, ALGOS[algo])
+    rng = np.random.default_rng(bits)
+    idx = np.unique(np.concatenate([[0, a.shape[0] - 1], rng.integers(0, a.shape[0], 62)]))
+    check(orc, a[idx], b[idx], got[idx])
+    for p in (1000003, 999983):
+        P = np.uint64(p)
+        assert (residues(got, p) == (residues(a, p) * residues(b, p)) % P).all()
+
+
+@pytest.mark.parametrize("algo", list(ALGOS))
+@pytest.mark.parametrize("bits,batch", W.NTT_CASES)
+def test_full_size_ntt_workload(B, ctx, orc, algo, bits, batch):
+    n = bits // 32
+    if not available(B, ctx, ALGOS[algo], n):
+        pytest.skip("unavailable")
+    a, b = W.ntt_inputs(bits, batch)
+    got = run_mul(B, ctx, a, b, ALGOS[algo])
+    idx = [0, batch // 2, batch - 1]
+    check(orc, a[idx], b[idx], got[idx])
+    for p in (1000003, 999983):
+        P = np.uint64(p)
+        assert (residues(got, p) == (residues(a, p) * residues(b, p)) % P).all()
