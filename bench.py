@@ -58,6 +58,17 @@ def cpu_info():
     return model
 
 
+def add_kernel_name(n_limbs, limb_bits):
+    """Name of the addition kernel the library launches for this shape (16-byte
+    chunks; mirrors the size classes of the launcher in csrc/bigadd.hip)."""
+    m = n_limbs * limb_bits // 128
+    if m <= 64:
+        return "bi::bigadd_packed_kernel<4, 4, true>"
+    rows = (m + 63) // 64
+    u, nw = (1, 2) if rows <= 2 else (1, 4) if rows <= 4 else (2, 4) if rows <= 8 else (2, 8) if rows <= 16 else (4, 8)
+    return f"bi::bigadd_coop_kernel<4, {u}, {nw}, true>"
+
+
 def bench_add(args):
     import torch
 
@@ -116,12 +127,12 @@ def bench_add(args):
         gbs = bytes_per_launch / (us * 1e-6) / 1e9
         per_size[str(bits)] = {"pairs": pairs, "us_per_launch": round(us, 2), "adds_per_s": pairs / (us * 1e-6),
                                "GB_per_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-    # Dominant kernel: the streamed-row kernel, which serves 2^14..2^18 bits
-    # (every launch moves the same 1.5 GiB, so its launches share one average).
-    dom = [b for b in sizes if b >= (1 << 14)] or list(sizes)
-    dom_us = float(np.mean([per_size[str(b)]["us_per_launch"] for b in dom]))
+    # Dominant kernel: the one behind the slowest launch of the step (every
+    # launch moves the same 1.5 GiB).
+    dom_bits = max(sizes, key=lambda b: per_size[str(b)]["us_per_launch"])
+    dom_us = per_size[str(dom_bits)]["us_per_launch"]
     achieved = bytes_per_launch / (dom_us * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "kernel": "bi::bigadd_stream_kernel<4,4> (2^14..2^18 bits, u64 limbs)",
+    roofline = {"bound": "hbm", "kernel": add_kernel_name(dom_bits // 64, 64) + f" at 2^{dom_bits.bit_length() - 1} bits",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "avg_launch_us": round(dom_us, 2), "algorithmic_bytes_per_launch": bytes_per_launch}
@@ -149,6 +160,9 @@ def bench_add(args):
 # (32 lanes/clk/SIMD) per 32x32-bit product term -> 10.67 terms/clk/SIMD,
 # x 1024 SIMDs x 2.4 GHz.
 VALU_MAC_PEAK = 1024 * (16 * 32 / 48) * 2.4e9   # 2.62e13 u32 MAC/s
+# NTT: a radix-2 butterfly with a Shoup twiddle is 3 multiply-class
+# (16 lanes/clk/SIMD) + 7 add-class (32 lanes/clk/SIMD) instructions.
+NTT_BFLY_PEAK = 1024 * 2.4e9 / (3 / 16 + 7 / 32)  # 6.05e12 butterflies/s
 MFMA_I8_PEAK_OPS = 5.0e15                        # dense int8, ops (2 per MAC)
 
 ALGO_IDS = {"valu": 1, "mfma": 2, "ntt": 3}
@@ -212,6 +226,15 @@ def bench_mul(args, kind):
                 r["roofline"] = {"bound": "alu", "achieved": round(macs / (us * 1e-6) / 1e12, 3),
                                  "peak": round(VALU_MAC_PEAK / 1e12, 3), "unit": "T u32-MAC/s",
                                  "frac": round(macs / (us * 1e-6) / VALU_MAC_PEAK, 4)}
+            elif name == "ntt":
+                m = 11
+                while (1 << m) < 4 * n:
+                    m += 1
+                bfly = 2.0 * 3 * batch * (1 << m) / 2 * m
+                r["butterflies_per_launch"] = bfly
+                r["roofline"] = {"bound": "alu", "achieved": round(bfly / (us * 1e-6) / 1e12, 3),
+                                 "peak": round(NTT_BFLY_PEAK / 1e12, 3), "unit": "T butterflies/s",
+                                 "frac": round(bfly / (us * 1e-6) / NTT_BFLY_PEAK, 4)}
             elif name == "mfma":
                 ops = 2.0 * batch * (4 * n) ** 2
                 r["roofline"] = {"bound": "mfma", "achieved": round(ops / (us * 1e-6) / 1e12, 1),

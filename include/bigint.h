@@ -131,6 +131,22 @@ bi_status bigadd_v(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t
 bi_status bigmul_v(bi_ctx *ctx, const void *a, const void *b, void *out,
                    const bi_desc *desc, uint64_t count, uint32_t limb_bits, int algo, void *stream);
 
+/*
+ * bi_ntt_field -- host-only helper for the prime-field construction of
+ * Section 4.1: for an odd prime p = k 2^n + 1 (p < 2^63), returns k, the
+ * two-adicity n, and the first a = 2, 3, ... for which g = a^k is a primitive
+ * 2^n-th root of unity (g^(2^(n-1)) != 1), which is how the library derives
+ * the roots of its NTT primes.  Makes no HIP call.  BI_EINVAL if p is not an
+ * odd prime below 2^63 or out is NULL.
+ */
+typedef struct bi_ntt_field_info {
+    uint64_t p, k;
+    uint32_t two_adicity, reserved;
+    uint64_t a, g;
+} bi_ntt_field_info;
+
+bi_status bi_ntt_field(uint64_t p, bi_ntt_field_info *out);
+
 #ifdef __cplusplus
 }
 #endif

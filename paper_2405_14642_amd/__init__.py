@@ -13,7 +13,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["Context", "BigIntError", "bigadd", "bigmul", "bigadd_v", "bigmul_v", "lib", "library_path",
+__all__ = ["Context", "BigIntError", "bigadd", "bigmul", "bigadd_v", "bigmul_v", "ntt_field", "lib", "library_path",
            "MUL_AUTO", "MUL_SCHOOL_VALU", "MUL_SCHOOL_MFMA", "MUL_NTT", "MAX_BITS", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,7 +25,14 @@ STATUS = {0: "BI_OK", -1: "BI_EINVAL", -2: "BI_ESIZE", -3: "BI_ELIMB", -4: "BI_E
           -6: "BI_ENOMEM", -7: "BI_EALGO", -8: "BI_ENODEV"}
 
 EXPORTS = ("bi_ctx_create", "bi_ctx_destroy", "bi_status_str", "bi_last_error",
-           "bigadd", "bigmul", "bigadd_v", "bigmul_v")
+           "bigadd", "bigmul", "bigadd_v", "bigmul_v", "bi_ntt_field")
+
+
+class NttFieldInfo(ctypes.Structure):
+    """bi_ntt_field_info: p = k 2^two_adicity + 1, g = a^k a primitive
+    2^two_adicity-th root of unity (Section 4.1)."""
+    _fields_ = [("p", ctypes.c_uint64), ("k", ctypes.c_uint64), ("two_adicity", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("a", ctypes.c_uint64), ("g", ctypes.c_uint64)]
 
 
 class BigIntError(RuntimeError):
@@ -58,7 +65,8 @@ def _load():
     L.bigmul.argtypes = [P, P, P, P, U32, U32, U64, I, P]
     L.bigadd_v.argtypes = [P, P, P, P, P, P, U64, U32, P]
     L.bigmul_v.argtypes = [P, P, P, P, P, U64, U32, I, P]
-    for f in (L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v):
+    L.bi_ntt_field.argtypes = [U64, P]
+    for f in (L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field):
         f.restype = I
     return L
 
@@ -152,6 +160,13 @@ def bigadd_v(ctx, a, b, out, carry, desc, count, limb_bits, stream=None):
     _check(lib.bigadd_v(_h(ctx), _ptr(a), _ptr(b), _ptr(out), _ptr(carry), _ptr(desc), count, limb_bits,
                         _stream(stream, a)))
     return out
+
+
+def ntt_field(p: int) -> NttFieldInfo:
+    """Host-side prime-field search of Section 4.1 (no GPU needed)."""
+    info = NttFieldInfo()
+    _check(lib.bi_ntt_field(p, ctypes.byref(info)))
+    return info
 
 
 def bigmul_v(ctx, a, b, out, desc, count, limb_bits, algo=MUL_AUTO, stream=None):

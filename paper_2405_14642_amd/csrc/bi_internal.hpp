@@ -11,7 +11,36 @@ namespace bi {
 struct AddTune {
     uint64_t max_waves = 1u << 16;  // grid cap (waves); kernels grid-stride beyond it
     int rows = 4;                   // rows of 64 chunks each wave loads before consuming (2, 4, 8)
-    bool nt = false;                // non-temporal loads and stores
+    bool nt = true;                 // non-temporal loads and stores
+};
+
+// NTT field constants (two primes below 2^31) and device twiddle tables.
+constexpr int kNttPrimes = 2;
+constexpr int kNttLogLmax = 15;                  // transforms of up to 2^15 points
+constexpr uint32_t kNttLmax = 1u << kNttLogLmax;
+
+struct NttConst {
+    uint32_t p[kNttPrimes], pneg[kNttPrimes];     // modulus, -p^-1 mod 2^32
+    uint32_t scale[kNttPrimes][kNttLogLmax + 1];  // 2^-l * 2^32 mod p
+    uint32_t scale_sh[kNttPrimes][kNttLogLmax + 1];
+    uint32_t crt, crt_sh;                         // p1^-1 mod p2 and its Shoup companion
+    const uint2 *fwd[kNttPrimes];                 // (w^e, Shoup) for e < Lmax, w of order Lmax
+    const uint2 *inv[kNttPrimes];                 // (w^-e, Shoup)
+};
+
+struct NttTables {
+    NttConst c{};
+    uint2 *dev = nullptr;
+};
+
+bi_status ntt_setup(NttTables &t);
+void ntt_release(NttTables &t);
+bi_status field_info(uint64_t p, bi_ntt_field_info *out);
+
+// Device scratch owned by a context (grown on demand).
+struct Scratch {
+    void *ptr = nullptr;
+    size_t bytes = 0;
 };
 
 // Per-device state owned by a context.
@@ -19,7 +48,13 @@ struct Ctx {
     int device = 0;
     int num_cus = 256;
     AddTune add;
+    NttTables ntt;
+    Scratch scratch;
 };
+
+// Returns a device buffer of at least `bytes` owned by the context; growing it
+// synchronises `st` first so no queued kernel still uses the old buffer.
+bi_status ctx_scratch(Ctx &c, size_t bytes, hipStream_t st, void **out);
 
 bi_status ctx_init(Ctx &c, int device, const hipDeviceProp_t &prop);
 void ctx_release(Ctx &c);
@@ -38,6 +73,14 @@ struct ValuPlan {
 ValuPlan valu_plan(uint32_t n);
 hipError_t launch_bigmul_valu(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n, uint64_t batch,
                               hipStream_t st, int num_cus);
+
+// NTT multiplication of n32-limb operands: the four transforms of every pair
+// (2 operands x 2 primes, L words each) go to the scratch `tr`
+// (ntt_scratch_bytes), then CRT and carry produce the product.
+uint32_t ntt_log_len(uint32_t n32);  // log2 of the transform length, 0 if too large
+size_t ntt_scratch_bytes(uint32_t n32, uint64_t batch);
+hipError_t launch_bigmul_ntt(const NttConst &k, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32,
+                             uint64_t batch, uint32_t *tr, hipStream_t st);
 
 bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint32_t n32, uint64_t batch, int algo,
                           hipStream_t st);

@@ -71,4 +71,25 @@ __device__ __forceinline__ void wg_add_rows(const Src &src, uint32_t *__restrict
     }
 }
 
+// Addends of a product in "low / high" form with groups of 4 words: L holds
+// the 4 low words of every group at their positions, H[g] the high word and
+// carry word of group g, which belong at word positions 4 (g+1) and 4 (g+1)+1.
+struct LHSrc4 {
+    const uint32_t *L;  // LDS, 4 * ngroups words
+    const uint2 *H;     // LDS, ngroups entries
+    uint32_t nwords;
+    __device__ __forceinline__ void operator()(uint32_t c, uint32_t (&x)[4], uint32_t (&y)[4]) const {
+        const uint4 l = *reinterpret_cast<const uint4 *>(L + 4 * c);
+        x[0] = l.x; x[1] = l.y; x[2] = l.z; x[3] = l.w;
+        if (c >= 1) {
+            const uint2 h = H[c - 1];
+            y[0] = h.x; y[1] = h.y;
+        }
+        const uint32_t base = 4 * c;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (base + t >= nwords) { x[t] = 0; y[t] = 0; }
+    }
+};
+
 }  // namespace bi

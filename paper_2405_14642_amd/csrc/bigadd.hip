@@ -148,6 +148,91 @@ __global__ __launch_bounds__(256) void bigadd_ragged_kernel(const uint32_t *__re
     }
 }
 
+// Workgroup-cooperative schedule for instances longer than one row: the NW
+// waves of a workgroup load disjoint runs of U rows of the same instance at
+// once (NW*U rows per tile), reduce each run to a carry summary (carry out
+// with carry-in 0, and whether every chunk propagates), exchange the
+// summaries through LDS, and then apply their true carry-in.  This is the
+// thread -> wave -> block hierarchy of the paper's block scan, with one
+// ballot-adder step per level.
+template <int W, int U, int NW, bool NT>
+__global__ __launch_bounds__(64 * NW) void bigadd_coop_kernel(const uint32_t *__restrict__ a,
+                                                              const uint32_t *__restrict__ b,
+                                                              uint32_t *out, uint8_t *carry, uint32_t m,
+                                                              uint64_t batch) {
+    __shared__ uint32_t summ[NW];
+    const uint32_t lane = lane_id();
+    const uint32_t wave = wave_in_block();
+    const uint32_t rows = (m + 63) / 64;
+    const uint32_t tiles = (rows + NW * U - 1) / (NW * U);
+
+    for (uint64_t inst = blockIdx.x; inst < batch; inst += gridDim.x) {
+        const uint64_t off = inst * m * W;
+        const uint32_t *ai = a + off;
+        const uint32_t *bi_ = b + off;
+        uint32_t *oi = out + off;
+        uint32_t tile_cin = 0;
+        for (uint32_t tile = 0; tile < tiles; ++tile) {
+            const uint32_t r0 = (tile * NW + wave) * U;
+            uint32_t s[U][W];
+            uint64_t G[U], P[U];
+            uint32_t gl[U], pl[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t c = (r0 + u) * 64 + lane;
+                uint32_t va[W], vb[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) { va[w] = 0; vb[w] = 0; }
+                if (c < m) {
+                    load_words<W, NT>(ai + uint64_t(c) * W, va);
+                    load_words<W, NT>(bi_ + uint64_t(c) * W, vb);
+                }
+                gl[u] = add_words<W>(va, vb, s[u]);
+                pl[u] = (c < m && all_ones<W>(s[u])) ? 1u : 0u;
+            }
+            // Summary of this wave's run (rows past the instance end are the
+            // identity: they neither kill nor generate).
+            uint32_t cout = 0, allp = 1;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                G[u] = ballot(gl[u] != 0);
+                P[u] = ballot(pl[u] != 0);
+                if (r0 + u < rows) {  // uniform
+                    const uint32_t valid = min(m - (r0 + u) * 64, 64u);
+                    const uint64_t vmask = valid >= 64 ? ~0ull : ((1ull << valid) - 1);
+                    const WaveCarry wc = wave_carry(G[u], P[u], cout);
+                    cout = valid >= 64 ? wc.out : uint32_t(wc.into >> valid) & 1u;
+                    allp &= (P[u] == vmask) ? 1u : 0u;
+                }
+            }
+            if (lane == 0) summ[wave] = cout | (allp << 1);
+            __syncthreads();
+            uint32_t cin = tile_cin, tcout = tile_cin;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) {
+                const uint32_t sv = summ[v];
+                if (v < int(wave)) cin = (sv & 1u) | ((sv >> 1) & cin);
+                tcout = (sv & 1u) | ((sv >> 1) & tcout);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (r0 + u < rows) {  // uniform
+                    const uint32_t c = (r0 + u) * 64 + lane;
+                    const uint32_t valid = min(m - (r0 + u) * 64, 64u);
+                    const WaveCarry wc = wave_carry(G[u], P[u], cin);
+                    const uint32_t ci = uint32_t(wc.into >> lane) & 1u;
+                    add_carry_words<W>(s[u], ci);
+                    if (c < m) store_words<W, NT>(oi + uint64_t(c) * W, s[u]);
+                    cin = valid >= 64 ? wc.out : uint32_t(wc.into >> valid) & 1u;
+                }
+            }
+            tile_cin = tcout;
+            __syncthreads();  // summ is rewritten by the next tile
+        }
+        if (carry && threadIdx.x == 0) carry[inst] = uint8_t(tile_cin);
+    }
+}
+
 // Largest chunk (in bytes) that divides the instance length and all pointers.
 static int pick_chunk_bytes(uint64_t inst_bytes, const void *a, const void *b, const void *o) {
     const uint64_t al = uint64_t(reinterpret_cast<uintptr_t>(a)) | uint64_t(reinterpret_cast<uintptr_t>(b)) |
@@ -169,11 +254,24 @@ static hipError_t launch_wu(const uint32_t *a, const uint32_t *b, uint32_t *o, u
         hipLaunchKernelGGL((bigadd_packed_kernel<W, U, NT>), dim3(uint32_t(blocks)), dim3(256), 0, st, a, b, o, carry,
                            uint32_t(m), ipr, batch);
     } else {
-        uint64_t waves = batch;
-        if (waves > max_waves) waves = max_waves;
-        const uint64_t blocks = (waves + 3) / 4;
-        hipLaunchKernelGGL((bigadd_stream_kernel<W, U, NT>), dim3(uint32_t(blocks)), dim3(256), 0, st, a, b, o, carry,
-                           uint32_t(m), batch);
+        // One workgroup per instance: NW waves x UC rows cover the instance
+        // in one tile when it has at most 32 rows.
+        const uint64_t rows = (m + 63) / 64;
+        uint64_t wgs = batch;
+        const uint64_t cap = max_waves / 4;
+        if (wgs > cap) wgs = cap;
+        const dim3 g{uint32_t(wgs), 1, 1};
+        if (rows <= 2) {
+            hipLaunchKernelGGL((bigadd_coop_kernel<W, 1, 2, NT>), g, dim3(128), 0, st, a, b, o, carry, uint32_t(m), batch);
+        } else if (rows <= 4) {
+            hipLaunchKernelGGL((bigadd_coop_kernel<W, 1, 4, NT>), g, dim3(256), 0, st, a, b, o, carry, uint32_t(m), batch);
+        } else if (rows <= 8) {
+            hipLaunchKernelGGL((bigadd_coop_kernel<W, 2, 4, NT>), g, dim3(256), 0, st, a, b, o, carry, uint32_t(m), batch);
+        } else if (rows <= 16) {
+            hipLaunchKernelGGL((bigadd_coop_kernel<W, 2, 8, NT>), g, dim3(512), 0, st, a, b, o, carry, uint32_t(m), batch);
+        } else {
+            hipLaunchKernelGGL((bigadd_coop_kernel<W, 4, 8, NT>), g, dim3(512), 0, st, a, b, o, carry, uint32_t(m), batch);
+        }
     }
     return hipGetLastError();
 }

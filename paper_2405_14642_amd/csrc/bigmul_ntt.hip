@@ -1,0 +1,427 @@
+// NTT multiplication (Section 4): number-theoretic transforms over two primes
+// p < 2^31 with Chinese-remainder recombination, then carry normalisation.
+//
+// Operands are split into 16-bit coefficients (the 16-bit digits of the
+// limbs), zero-padded to L = 2^M >= 2 * (number of coefficients) so the cyclic
+// convolution does not wrap.  Per (pair, prime) one workgroup of L/32 threads:
+//
+//   forward DIF transform of a, forward DIF transform of b (natural order in,
+//   bit-reversed order out, so no permutation step is needed), pointwise
+//   Montgomery product, inverse DIT transform (bit-reversed in, natural out),
+//   scaling by L^-1 (times 2^32 to undo the Montgomery factor).
+//
+// Each transform runs as three passes over the LDS-resident vector.  A pass
+// covers R radix-2 stages at once: every thread loads 32 elements forming
+// groups of 2^R, runs the 2^R-point DIF network in registers (twiddles are
+// powers of the 2^R-th root, identical for all lanes, so they come through
+// scalar loads), and multiplies output position k of a group by
+// w^(2^s * lo * bitrev_R(k)) where lo is the group's offset (the four-step
+// factorisation of the radix-2 stages of Fig. 8).  The inverse applies the
+// inverse of each pass in reverse order.  LDS words are padded (one per 32)
+// so that the strided element sets of all passes are bank-conflict free.
+//
+// A second kernel per pair recombines the two residues of every coefficient
+// (Garner), folds each thread's 8 coefficients (16-bit positions) into 4 low
+// words plus 2 high words, and adds the low and high arrays with the
+// workgroup ballot-adder, as for the schoolbook product.
+#include "bi_common.hpp"
+#include "bi_internal.hpp"
+#include "bi_wgadd.hpp"
+
+namespace bi {
+
+namespace {
+
+constexpr int E = 32;  // elements per thread
+
+__device__ __forceinline__ uint32_t add_mod(uint32_t a, uint32_t b, uint32_t p) {
+    const uint32_t s = a + b;  // < 2p < 2^32
+    return min(s, s - p);
+}
+__device__ __forceinline__ uint32_t sub_mod(uint32_t a, uint32_t b, uint32_t p) {
+    const uint32_t d = a - b;
+    return min(d, d + p);
+}
+// a * w mod p with the precomputed w' = floor(w 2^32 / p) (Shoup).
+__device__ __forceinline__ uint32_t mul_shoup(uint32_t a, uint32_t w, uint32_t wsh, uint32_t p) {
+    const uint32_t q = __umulhi(a, wsh);
+    const uint32_t r = a * w - q * p;  // in [0, 2p)
+    return min(r, r - p);
+}
+// a * b * 2^-32 mod p (Montgomery, pneg = -p^-1 mod 2^32).
+__device__ __forceinline__ uint32_t mul_mont(uint32_t a, uint32_t b, uint32_t p, uint32_t pneg) {
+    const uint64_t t = uint64_t(a) * b;
+    const uint32_t tl = uint32_t(t), th = uint32_t(t >> 32);
+    const uint32_t m = tl * pneg;
+    const uint32_t u = th + __umulhi(m, p) + (tl != 0u ? 1u : 0u);  // < 2p
+    return min(u, u - p);
+}
+
+__device__ __forceinline__ uint32_t padx(uint32_t i) { return i + (i >> 5); }
+
+template <int R>
+__device__ __forceinline__ uint32_t bitrev(uint32_t k) { return __brev(k) >> (32 - R); }
+
+// 2^R-point DIF network on x[base .. base + 2^R): stage t pairs (k, k + h),
+// h = 2^(R-t-1), twiddle w_{2^R}^((k mod h) 2^t); w_{2^R} = table[Lmax / 2^R].
+template <int R>
+__device__ __forceinline__ void small_dif(uint32_t *x, const uint2 *__restrict__ tw, uint32_t p) {
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const int h = 1 << (R - t - 1);
+#pragma unroll
+        for (int k = 0; k < (1 << R); ++k) {
+            if (k & h) continue;
+            const int j = (k & (h - 1)) << t;  // exponent of the 2^R-th root
+            const uint32_t u = x[k], v = x[k + h];
+            x[k] = add_mod(u, v, p);
+            const uint32_t d = sub_mod(u, v, p);
+            if (j == 0) {
+                x[k + h] = d;
+            } else {
+                const uint2 w = tw[j * (kNttLmax >> R)];
+                x[k + h] = mul_shoup(d, w.x, w.y, p);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);  // one stage at a time: bounds live registers
+    }
+}
+
+// Inverse of small_dif up to the factor 2^R: stages in reverse order,
+// (a, b) -> (a + b w^-j, a - b w^-j).
+template <int R>
+__device__ __forceinline__ void small_dit_inv(uint32_t *x, const uint2 *__restrict__ itw, uint32_t p) {
+#pragma unroll
+    for (int t = R - 1; t >= 0; --t) {
+        const int h = 1 << (R - t - 1);
+#pragma unroll
+        for (int k = 0; k < (1 << R); ++k) {
+            if (k & h) continue;
+            const int j = (k & (h - 1)) << t;
+            const uint32_t a = x[k];
+            uint32_t b = x[k + h];
+            if (j != 0) {
+                const uint2 w = itw[j * (kNttLmax >> R)];
+                b = mul_shoup(b, w.x, w.y, p);
+            }
+            x[k] = add_mod(a, b, p);
+            x[k + h] = sub_mod(a, b, p);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Position k of a group with offset lo in a pass starting at stage s gets the
+// factor w_L^(2^s lo bitrev_R(k)); tables are indexed in units of w_Lmax.
+template <int M, int R>
+__device__ __forceinline__ void twiddle_group(uint32_t *x, const uint2 *__restrict__ tbl, uint32_t lo_s, uint32_t p) {
+#pragma unroll
+    for (int k = 1; k < (1 << R); ++k) {
+        const uint32_t e = lo_s * bitrev<R>(k);  // < L
+        const uint2 w = tbl[e << (kNttLogLmax - M)];
+        x[k] = mul_shoup(x[k], w.x, w.y, p);
+        // Bound the twiddle loads in flight (each costs 4 registers with its
+        // address): 8 when registers allow, 4 for the 1024-thread transform.
+        if ((k & (M >= 15 ? 3 : 7)) == (M >= 15 ? 3 : 7)) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// LDS layout: element i of the transform vector lives at word padx(i) =
+// i + i/32.  For the three element sets a thread touches the addresses are a
+// per-thread base plus a compile-time multiple of k:
+//   pass 0  (k 2^10 + gidx, gidx < 2^10):       padx(gidx) + 1056 k
+//   pass 1  (hi 2^10 + 32 k + lo, lo < 32):     33 hi + 1024 hi + lo + 33 k
+//   pass 2  (32 t + k, k < 32):                 33 t + k
+__device__ __forceinline__ uint32_t base_pass1(uint32_t t) {
+    const uint32_t lo = t & 31u, hi = t >> 5;
+    return (hi << 10) + (hi << 5) + lo;
+}
+
+// Forward transform of the 16-bit coefficients of `src` (n32 limbs); on return
+// x[k] holds position 32 t + k of the bit-reversed-order transform.
+template <int M>
+__device__ __forceinline__ void ntt_forward(const uint32_t *__restrict__ src, uint32_t n32, uint32_t (&x)[E],
+                                            uint32_t *sh, const uint2 *__restrict__ fw, uint32_t p) {
+    constexpr int R0 = M - 10;
+    constexpr int G0 = E >> R0;
+    constexpr uint32_t T = (1u << M) / E;
+    const uint32_t t = threadIdx.x;
+    // Stage the limbs (zero-padded to L/2 words = L coefficients) in LDS.
+    __syncthreads();  // the previous user of sh is done
+    for (uint32_t w = t; w < (1u << M) / 2; w += T) sh[w] = w < n32 ? src[w] : 0u;
+    __syncthreads();
+    const uint16_t *coef = reinterpret_cast<const uint16_t *>(sh);
+    // pass 0: stages [0, R0); group g: elements k 2^10 + gidx, gidx = t + T g
+#pragma unroll
+    for (int g = 0; g < G0; ++g) {
+        const uint32_t gidx = t + T * g;
+#pragma unroll
+        for (int k = 0; k < (1 << R0); ++k) x[g * (1 << R0) + k] = coef[gidx + (uint32_t(k) << 10)];
+    }
+    __syncthreads();  // staging is overwritten below
+#pragma unroll
+    for (int g = 0; g < G0; ++g) {
+        const uint32_t gidx = t + T * g;
+        small_dif<R0>(x + g * (1 << R0), fw, p);
+        twiddle_group<M, R0>(x + g * (1 << R0), fw, gidx, p);
+        uint32_t *q = sh + padx(gidx);
+#pragma unroll
+        for (int k = 0; k < (1 << R0); ++k) q[1056 * k] = x[g * (1 << R0) + k];
+    }
+    __syncthreads();
+    // pass 1: stages [R0, R0 + 5); lo = t mod 32, hi = t / 32
+    {
+        uint32_t *q = sh + base_pass1(t);
+#pragma unroll
+        for (int k = 0; k < 32; ++k) x[k] = q[33 * k];
+        small_dif<5>(x, fw, p);
+        twiddle_group<M, 5>(x, fw, (t & 31u) << R0, p);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 32; ++k) q[33 * k] = x[k];
+        __syncthreads();
+    }
+    // pass 2: stages [R0 + 5, M); groups are the contiguous runs 32 t .. 32 t + 31
+    {
+        const uint32_t *q = sh + 33 * t;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) x[k] = q[k];
+        small_dif<5>(x, fw, p);
+    }
+}
+
+// Inverse of ntt_forward applied to x (position 32 t + k), times L^-1 2^32;
+// the natural-order results for i < nout go to dst[i].
+template <int M>
+__device__ __forceinline__ void ntt_inverse(uint32_t (&x)[E], uint32_t *__restrict__ dst, uint32_t nout, uint32_t *sh,
+                                            const uint2 *__restrict__ iw, uint32_t p, uint32_t scale,
+                                            uint32_t scale_sh) {
+    constexpr int R0 = M - 10;
+    constexpr int G0 = E >> R0;
+    constexpr uint32_t T = (1u << M) / E;
+    const uint32_t t = threadIdx.x;
+    small_dit_inv<5>(x, iw, p);
+    __syncthreads();
+    {
+        uint32_t *q = sh + 33 * t;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) q[k] = x[k];
+    }
+    __syncthreads();
+    {
+        uint32_t *q = sh + base_pass1(t);
+#pragma unroll
+        for (int k = 0; k < 32; ++k) x[k] = q[33 * k];
+        twiddle_group<M, 5>(x, iw, (t & 31u) << R0, p);
+        small_dit_inv<5>(x, iw, p);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 32; ++k) q[33 * k] = x[k];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int g = 0; g < G0; ++g) {
+        const uint32_t gidx = t + T * g;
+        uint32_t *y = x + g * (1 << R0);
+        const uint32_t *q = sh + padx(gidx);
+#pragma unroll
+        for (int k = 0; k < (1 << R0); ++k) y[k] = q[1056 * k];
+        twiddle_group<M, R0>(y, iw, gidx, p);
+        small_dit_inv<R0>(y, iw, p);
+#pragma unroll
+        for (int k = 0; k < (1 << R0); ++k) y[k] = mul_shoup(y[k], scale, scale_sh, p);
+    }
+    __syncthreads();
+    // natural order, unpadded, then contiguous copy-out
+#pragma unroll
+    for (int g = 0; g < G0; ++g) {
+        const uint32_t gidx = t + T * g;
+#pragma unroll
+        for (int k = 0; k < (1 << R0); ++k) sh[gidx + (uint32_t(k) << 10)] = x[g * (1 << R0) + k];
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < nout; i += T) dst[i] = sh[i];
+}
+
+}  // namespace
+
+// One workgroup per (pair, operand, prime): the forward transform, stored in
+// bit-reversed order to tr[work * L ...] (thread t owns positions 32 t .. 32 t + 31).
+template <int M>
+__global__ __launch_bounds__((1 << M) / E) void ntt_fwd_kernel(NttConst K, const uint32_t *__restrict__ A,
+                                                               const uint32_t *__restrict__ B, uint32_t n32,
+                                                               uint64_t batch, uint32_t *__restrict__ tr) {
+    extern __shared__ __align__(16) uint32_t sh[];
+    constexpr uint32_t L = 1u << M;
+    for (uint64_t work = blockIdx.x; work < 4 * batch; work += gridDim.x) {
+        const uint64_t pair = work >> 2;
+        const int pr = int(work & 1), op = int((work >> 1) & 1);
+        const uint32_t *src = (op ? B : A) + pair * n32;
+        uint32_t x[E];
+        ntt_forward<M>(src, n32, x, sh, K.fwd[pr], K.p[pr]);
+        uint4 *dst = reinterpret_cast<uint4 *>(tr + work * L + E * threadIdx.x);
+#pragma unroll
+        for (int q = 0; q < E / 4; ++q) dst[q] = make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+        __syncthreads();
+    }
+}
+
+// One workgroup per (pair, prime): pointwise product of the two transforms,
+// inverse transform, scaling; the coefficient residues overwrite the first
+// operand's transform.
+template <int M>
+__global__ __launch_bounds__((1 << M) / E) void ntt_inv_kernel(NttConst K, uint32_t n32, uint64_t batch,
+                                                               uint32_t *__restrict__ tr) {
+    extern __shared__ __align__(16) uint32_t sh[];
+    constexpr uint32_t L = 1u << M;
+    const uint32_t nout = 4 * n32;  // coefficients of the product (the last is 0)
+    for (uint64_t work = blockIdx.x; work < 2 * batch; work += gridDim.x) {
+        const uint64_t pair = work >> 1;
+        const int pr = int(work & 1);
+        const uint32_t p = K.p[pr], pneg = K.pneg[pr];
+        uint32_t *ta = tr + (4 * pair + pr) * L;      // operand a, prime pr
+        const uint32_t *tb = ta + 2 * L;              // operand b, prime pr
+        uint32_t x[E];
+        const uint4 *va = reinterpret_cast<const uint4 *>(ta + E * threadIdx.x);
+        const uint4 *vb = reinterpret_cast<const uint4 *>(tb + E * threadIdx.x);
+#pragma unroll
+        for (int q = 0; q < E / 4; ++q) {
+            const uint4 u = va[q], v = vb[q];
+            x[4 * q] = mul_mont(u.x, v.x, p, pneg);
+            x[4 * q + 1] = mul_mont(u.y, v.y, p, pneg);
+            x[4 * q + 2] = mul_mont(u.z, v.z, p, pneg);
+            x[4 * q + 3] = mul_mont(u.w, v.w, p, pneg);
+        }
+        __syncthreads();  // every thread has read its part of ta before residues overwrite it
+        ntt_inverse<M>(x, ta, nout, sh, K.inv[pr], p, K.scale[pr][M], K.scale_sh[pr][M]);
+        __syncthreads();
+    }
+}
+
+// One workgroup per pair: CRT, per-thread combine of 8 coefficients, L + H.
+// Residues of prime i for pair q are at tr + (4 q + i) L.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void ntt_crt_carry_kernel(NttConst K, const uint32_t *__restrict__ tr,
+                                                                uint32_t L, uint32_t *__restrict__ C, uint32_t n32,
+                                                                uint64_t batch) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    const uint32_t nout = 4 * n32;
+    const uint32_t nwords = 2 * n32;
+    const uint32_t ngroups = (nwords + 3) / 4;
+    uint32_t *Lsh = lds;                                          // [4 ngroups]
+    uint2 *Hsh = reinterpret_cast<uint2 *>(Lsh + 4 * ngroups);    // [ngroups]
+    uint32_t *summary = reinterpret_cast<uint32_t *>(Hsh + ngroups);
+    const uint32_t p1 = K.p[0], p2 = K.p[1];
+    for (uint64_t pair = blockIdx.x; pair < batch; pair += gridDim.x) {
+        const uint32_t *r1 = tr + (4 * pair) * L;
+        const uint32_t *r2 = r1 + L;
+        for (uint32_t g = threadIdx.x; g < ngroups; g += 64 * NW) {
+            // column sums of sum_e c_{8g+e} 2^(16 e), one 64-bit column per word
+            uint64_t col[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t k = 8 * g + e;
+                uint64_t c = 0;
+                if (k < nout) {
+                    const uint32_t a1 = r1[k], a2 = r2[k];
+                    const uint32_t tq = mul_shoup(sub_mod(a2, a1, p2), K.crt, K.crt_sh, p2);
+                    c = uint64_t(p1) * tq + a1;  // < p1 p2; equals the coefficient (< 2^46)
+                }
+                const uint64_t v = c << (16 * (e & 1));  // < 2^62
+                col[e >> 1] += uint32_t(v);
+                col[(e >> 1) + 1] += uint32_t(v >> 32);
+            }
+            uint64_t carry = 0;
+            uint32_t R[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                const uint64_t s = col[j] + carry;
+                R[j] = uint32_t(s);
+                carry = s >> 32;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Lsh[4 * g + j] = R[j];
+            Hsh[g] = make_uint2(R[4], R[5]);
+        }
+        __syncthreads();
+        wg_add_rows<NW>(LHSrc4{Lsh, Hsh, nwords}, C + pair * nwords, nwords, summary);
+        __syncthreads();
+    }
+}
+
+uint32_t ntt_log_len(uint32_t n32) {
+    uint32_t m = 11;  // smallest supported transform (64 threads)
+    while ((1u << m) < 4 * n32) ++m;
+    return m <= uint32_t(kNttLogLmax) ? m : 0;
+}
+
+template <int M>
+static hipError_t launch_transforms(const NttConst &K, const uint32_t *a, const uint32_t *b, uint32_t n32,
+                                    uint64_t batch, uint32_t *tr, hipStream_t st) {
+    const size_t lds = sizeof(uint32_t) * ((1u << M) + (1u << M) / 32);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_fwd_kernel<M>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_inv_kernel<M>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const uint32_t T = (1u << M) / E;
+    uint64_t w = 4 * batch;
+    hipLaunchKernelGGL((ntt_fwd_kernel<M>), dim3(uint32_t(w < 65536 ? w : 65536)), dim3(T), lds, st, K, a, b, n32,
+                       batch, tr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    w = 2 * batch;
+    hipLaunchKernelGGL((ntt_inv_kernel<M>), dim3(uint32_t(w < 65536 ? w : 65536)), dim3(T), lds, st, K, n32, batch,
+                       tr);
+    return hipGetLastError();
+}
+
+template <int NW>
+static hipError_t launch_crt(const NttConst &K, const uint32_t *tr, uint32_t L, uint32_t *c, uint32_t n32,
+                             uint64_t batch, hipStream_t st) {
+    const uint32_t ngroups = (2 * n32 + 3) / 4;
+    const size_t lds = sizeof(uint32_t) * (4 * ngroups + 2 * ngroups + NW);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_crt_carry_kernel<NW>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const uint32_t grid = uint32_t(batch < 65536 ? batch : 65536);
+    hipLaunchKernelGGL((ntt_crt_carry_kernel<NW>), dim3(grid), dim3(64 * NW), lds, st, K, tr, L, c, n32, batch);
+    return hipGetLastError();
+}
+
+size_t ntt_scratch_bytes(uint32_t n32, uint64_t batch) {
+    const uint32_t m = ntt_log_len(n32);
+    return m ? size_t(batch) * 4 * (size_t(1) << m) * sizeof(uint32_t) : 0;
+}
+
+hipError_t launch_bigmul_ntt(const NttConst &K, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32,
+                             uint64_t batch, uint32_t *tr, hipStream_t st) {
+    if (batch == 0) return hipSuccess;
+    const uint32_t m = ntt_log_len(n32);
+    hipError_t e;
+    switch (m) {
+        case 11: e = launch_transforms<11>(K, a, b, n32, batch, tr, st); break;
+        case 12: e = launch_transforms<12>(K, a, b, n32, batch, tr, st); break;
+        case 13: e = launch_transforms<13>(K, a, b, n32, batch, tr, st); break;
+        case 14: e = launch_transforms<14>(K, a, b, n32, batch, tr, st); break;
+        case 15: e = launch_transforms<15>(K, a, b, n32, batch, tr, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    const uint32_t L = 1u << m;
+    const uint32_t ngroups = (2 * n32 + 3) / 4;
+    if (ngroups <= 256) return launch_crt<4>(K, tr, L, c, n32, batch, st);
+    if (ngroups <= 1024) return launch_crt<8>(K, tr, L, c, n32, batch, st);
+    return launch_crt<16>(K, tr, L, c, n32, batch, st);
+}
+
+}  // namespace bi

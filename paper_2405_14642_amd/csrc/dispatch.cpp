@@ -11,10 +11,10 @@ namespace bi {
 bi_status ctx_init(Ctx &c, int device, const hipDeviceProp_t &prop) {
     c.device = device;
     c.num_cus = prop.multiProcessorCount;
-    c.add.max_waves = uint64_t(prop.multiProcessorCount) * 64;
+    c.add.max_waves = uint64_t(prop.multiProcessorCount) * 256;
     // Experiment override: BI_ADD_TUNE="rows,nt,max_waves" (e.g. "8,1,32768").
     if (const char *env = std::getenv("BI_ADD_TUNE")) {
-        int rows = 4, nt = 0;
+        int rows = 4, nt = 1;
         unsigned long long mw = c.add.max_waves;
         if (std::sscanf(env, "%d,%d,%llu", &rows, &nt, &mw) >= 1) {
             c.add.rows = (rows == 2 || rows == 8) ? rows : 4;
@@ -22,10 +22,34 @@ bi_status ctx_init(Ctx &c, int device, const hipDeviceProp_t &prop) {
             c.add.max_waves = mw ? mw : c.add.max_waves;
         }
     }
-    return BI_OK;
+    return ntt_setup(c.ntt);
 }
 
-void ctx_release(Ctx &c) { (void)c; }
+void ctx_release(Ctx &c) {
+    ntt_release(c.ntt);
+    if (c.scratch.ptr) (void)hipFree(c.scratch.ptr);
+    c.scratch = Scratch{};
+}
+
+bi_status ctx_scratch(Ctx &c, size_t bytes, hipStream_t st, void **out) {
+    if (bytes <= c.scratch.bytes) {
+        *out = c.scratch.ptr;
+        return BI_OK;
+    }
+    if (c.scratch.ptr) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return set_error(BI_EHIP, "scratch resize: %s", hipGetErrorString(e));
+        (void)hipFree(c.scratch.ptr);
+        c.scratch = Scratch{};
+    }
+    const size_t want = bytes + bytes / 4;  // headroom against repeated growth
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) return set_error(BI_ENOMEM, "scratch allocation of %zu bytes failed", want);
+    c.scratch.ptr = p;
+    c.scratch.bytes = want;
+    *out = p;
+    return BI_OK;
+}
 
 bi_status dispatch_bigadd_v(Ctx &c, const void *a, const void *b, void *out, uint8_t *carry, const bi_desc *desc,
                             uint64_t count, uint32_t limb_bits, hipStream_t st) {
@@ -43,6 +67,16 @@ bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint3
             e = launch_bigmul_valu(static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
                                    static_cast<uint32_t *>(out), n32, batch, st, c.num_cus);
             break;
+        case BI_MUL_NTT: {
+            if (ntt_log_len(n32) == 0) return set_error(BI_EALGO, "NTT supports up to %u limbs", kNttLmax / 4);
+            void *resid = nullptr;
+            const size_t bytes = ntt_scratch_bytes(n32, batch);
+            bi_status s = ctx_scratch(c, bytes, st, &resid);
+            if (s != BI_OK) return s;
+            e = launch_bigmul_ntt(c.ntt.c, static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
+                                  static_cast<uint32_t *>(out), n32, batch, static_cast<uint32_t *>(resid), st);
+            break;
+        }
         default:
             return set_error(BI_EALGO, "multiplication algorithm %d is not available", algo);
     }

@@ -1,0 +1,154 @@
+// Host-side prime-field set-up for the NTT multiplication (Section 4.1).
+//
+// A prime p = k 2^n + 1 admits 2^n-th roots of unity.  The paper's search:
+// for a = 2, 3, ..., take g = a^k; by Fermat's little theorem g^(2^n) = 1, and
+// g is a primitive 2^n-th root exactly when g^(2^(n-1)) != 1.  A primitive
+// L-th root for L = 2^l <= 2^n is then omega = g^(2^(n-l)).
+//
+// The library works with two primes below 2^31, so that sums of two residues
+// fit in 32 bits and the Chinese remainder theorem recovers every product
+// coefficient exactly (see bi_ntt_prime below).  Twiddle factors are stored
+// with their Shoup companions w' = floor(w 2^32 / p), so a product by a fixed
+// twiddle needs one high and two low 32-bit multiplies; the pointwise product
+// of two transforms uses Montgomery reduction with R = 2^32.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "bi_internal.hpp"
+
+namespace bi {
+
+namespace {
+
+using u128 = unsigned __int128;
+
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t p) { return uint64_t(u128(a) * b % p); }
+
+uint64_t powmod(uint64_t a, uint64_t e, uint64_t p) {
+    uint64_t r = 1 % p;
+    a %= p;
+    while (e) {
+        if (e & 1) r = mulmod(r, a, p);
+        a = mulmod(a, a, p);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Deterministic Miller-Rabin for 64-bit integers (the first 12 prime bases).
+bool is_prime(uint64_t n) {
+    if (n < 2) return false;
+    static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    for (uint64_t b : bases)
+        if (n % b == 0) return n == b;
+    uint64_t d = n - 1;
+    int s = 0;
+    while ((d & 1) == 0) { d >>= 1; ++s; }
+    for (uint64_t a : bases) {
+        uint64_t x = powmod(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int r = 1; r < s; ++r) {
+            x = mulmod(x, x, n);
+            if (x == n - 1) { comp = false; break; }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+uint32_t shoup(uint32_t w, uint32_t p) { return uint32_t((uint64_t(w) << 32) / p); }
+
+uint32_t neg_inv32(uint32_t p) {  // -p^-1 mod 2^32 (p odd), by Newton iteration
+    uint32_t x = p;               // correct to 3 bits
+    for (int i = 0; i < 5; ++i) x *= 2u - p * x;
+    return 0u - x;
+}
+
+}  // namespace
+
+bi_status field_info(uint64_t p, bi_ntt_field_info *out) {
+    if (!out) return BI_EINVAL;
+    std::memset(out, 0, sizeof *out);
+    if (p < 3 || (p & 1) == 0 || p >= (uint64_t(1) << 63) || !is_prime(p)) return BI_EINVAL;
+    uint64_t k = p - 1;
+    uint32_t n = 0;
+    while ((k & 1) == 0) { k >>= 1; ++n; }
+    for (uint64_t a = 2; a < p; ++a) {
+        const uint64_t g = powmod(a, k, p);
+        if (powmod(g, uint64_t(1) << (n - 1), p) != 1) {
+            out->p = p;
+            out->k = k;
+            out->two_adicity = n;
+            out->a = a;
+            out->g = g;
+            return BI_OK;
+        }
+    }
+    return BI_EINVAL;
+}
+
+// Primes of the form k 2^n + 1 below 2^31 (product ~2^61.9): every coefficient
+// of a product of two integers of up to 2^18 bits split into 16-bit digits is
+// below 2^14 (2^16 - 1)^2 < 2^46, so it is recovered exactly from its residues.
+static const uint32_t kPrimes[kNttPrimes] = {2113929217u /* 63 2^25 + 1 */, 2130706433u /* 127 2^24 + 1 */};
+
+bi_status ntt_setup(NttTables &t) {
+    std::vector<uint2> host(size_t(kNttPrimes) * 2 * kNttLmax);
+    for (int i = 0; i < kNttPrimes; ++i) {
+        bi_ntt_field_info fi;
+        if (field_info(kPrimes[i], &fi) != BI_OK || fi.two_adicity < kNttLogLmax) return BI_EINVAL;
+        const uint32_t p = kPrimes[i];
+        const uint64_t w = powmod(fi.g, uint64_t(1) << (fi.two_adicity - kNttLogLmax), p);  // order Lmax
+        const uint64_t wi = powmod(w, p - 2, p);
+        t.c.p[i] = p;
+        t.c.pneg[i] = neg_inv32(p);
+        uint64_t f = 1, g = 1;
+        uint2 *fw = host.data() + size_t(2 * i) * kNttLmax;
+        uint2 *iw = fw + kNttLmax;
+        for (uint32_t e = 0; e < kNttLmax; ++e) {
+            fw[e] = make_uint2(uint32_t(f), shoup(uint32_t(f), p));
+            iw[e] = make_uint2(uint32_t(g), shoup(uint32_t(g), p));
+            f = mulmod(f, w, p);
+            g = mulmod(g, wi, p);
+        }
+        // Output scale for transform length 2^l: L^-1 * R mod p (R = 2^32 undoes
+        // the R^-1 left by the Montgomery pointwise product).
+        const uint64_t R = (uint64_t(1) << 32) % p;
+        for (uint32_t l = 0; l <= kNttLogLmax; ++l) {
+            const uint64_t linv = powmod(uint64_t(1) << l, p - 2, p);
+            const uint32_t s = uint32_t(mulmod(linv, R, p));
+            t.c.scale[i][l] = s;
+            t.c.scale_sh[i][l] = shoup(s, p);
+        }
+    }
+    // Garner: c = r1 + p1 * ((r2 - r1) * p1^-1 mod p2)
+    const uint32_t c12 = uint32_t(powmod(kPrimes[0], kPrimes[1] - 2, kPrimes[1]));
+    t.c.crt = c12;
+    t.c.crt_sh = shoup(c12, kPrimes[1]);
+
+    const size_t bytes = host.size() * sizeof(uint2);
+    void *d = nullptr;
+    if (hipMalloc(&d, bytes) != hipSuccess) return BI_ENOMEM;
+    if (hipMemcpy(d, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return BI_EHIP;
+    }
+    t.dev = static_cast<uint2 *>(d);
+    for (int i = 0; i < kNttPrimes; ++i) {
+        t.c.fwd[i] = t.dev + size_t(2 * i) * kNttLmax;
+        t.c.inv[i] = t.dev + size_t(2 * i + 1) * kNttLmax;
+    }
+    return BI_OK;
+}
+
+void ntt_release(NttTables &t) {
+    if (t.dev) (void)hipFree(t.dev);
+    t.dev = nullptr;
+}
+
+}  // namespace bi
+
+extern "C" bi_status bi_ntt_field(uint64_t p, bi_ntt_field_info *out) { return bi::field_info(p, out); }
