@@ -12,20 +12,32 @@ struct AddTune {
     uint64_t max_waves = 1u << 16;  // grid cap (waves); kernels grid-stride beyond it
     int rows = 4;                   // rows of 64 chunks each wave loads before consuming (2, 4, 8)
     bool nt = true;                 // non-temporal loads and stores
+    // Instances of 2 / 3-4 / 5-8 rows: barrier-free one-wave-per-instance
+    // schedule instead of the workgroup-cooperative one.
+    bool multi2 = false, multi4 = false, multi8 = false;
 };
 
 // NTT field constants (two primes below 2^31) and device twiddle tables.
 constexpr int kNttPrimes = 2;
 constexpr int kNttLogLmax = 15;                  // transforms of up to 2^15 points
+constexpr int kNttLogLmin = 11;                  // and at least 2^11 (64 threads)
 constexpr uint32_t kNttLmax = 1u << kNttLogLmax;
+// Per prime and direction the twiddle block holds: [0, Lmax) w^e;
+// [kNttT1, +1024) the pass-1 table; from ntt_t0_offset(M) the pass-0 table of
+// length 2^M.
+constexpr uint32_t kNttT1 = kNttLmax;
+__host__ __device__ constexpr uint32_t ntt_t0_offset(uint32_t m) {
+    return kNttT1 + 1024 + ((1u << m) - (1u << kNttLogLmin));
+}
+constexpr uint32_t kNttTableWords = ntt_t0_offset(kNttLogLmax + 1);
 
 struct NttConst {
     uint32_t p[kNttPrimes], pneg[kNttPrimes];     // modulus, -p^-1 mod 2^32
     uint32_t scale[kNttPrimes][kNttLogLmax + 1];  // 2^-l * 2^32 mod p
     uint32_t scale_sh[kNttPrimes][kNttLogLmax + 1];
     uint32_t crt, crt_sh;                         // p1^-1 mod p2 and its Shoup companion
-    const uint2 *fwd[kNttPrimes];                 // (w^e, Shoup) for e < Lmax, w of order Lmax
-    const uint2 *inv[kNttPrimes];                 // (w^-e, Shoup)
+    const uint2 *fwd[kNttPrimes];                 // twiddle blocks (w^e, Shoup), w of order Lmax
+    const uint2 *inv[kNttPrimes];                 // the same for w^-1
 };
 
 struct NttTables {
@@ -81,6 +93,11 @@ uint32_t ntt_log_len(uint32_t n32);  // log2 of the transform length, 0 if too l
 size_t ntt_scratch_bytes(uint32_t n32, uint64_t batch);
 hipError_t launch_bigmul_ntt(const NttConst &k, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32,
                              uint64_t batch, uint32_t *tr, hipStream_t st);
+
+// int8-MFMA schoolbook for up to mfma_max_limbs() 32-bit limbs.
+uint32_t mfma_max_limbs();
+hipError_t launch_bigmul_mfma(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
+                              hipStream_t st);
 
 bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint32_t n32, uint64_t batch, int algo,
                           hipStream_t st);

@@ -16,18 +16,20 @@
 
 namespace bi {
 
-// src(c, x, y) fills the 4 words of chunk c (words 4c .. 4c+3) of both addends.
-// Words at index >= nwords are never stored and must read as 0.
-template <int NW, class Src>
-__device__ __forceinline__ void wg_add_rows(const Src &src, uint32_t *__restrict__ out, uint32_t nwords,
-                                            uint32_t *summary /* LDS, NW words */) {
+// src(c, x, y) fills the 4 words of chunk c (words 4c .. 4c+3) of both
+// addends; sink(c, s) receives the 4 sum words of chunk c (only for chunks
+// with c < nchunks).  Words at index >= nwords must read as 0.  Returns, in
+// every thread, the carry out of the whole sum.  Contains barriers: every
+// thread of the workgroup must call it.
+template <int NW, class Src, class Sink>
+__device__ __forceinline__ uint32_t wg_add_rows_sink(const Src &src, const Sink &sink, uint32_t nwords,
+                                                     uint32_t *summary /* LDS, NW words */) {
     const uint32_t lane = lane_id();
     const uint32_t w = wave_in_block();
     const uint32_t nchunks = (nwords + 3) / 4;
     const uint32_t rows = (nchunks + 63) / 64;
     const uint32_t r0 = (rows * w) / NW, r1 = (rows * (w + 1)) / NW;
 
-    const bool vec_ok = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
     uint32_t cin = 0, allp = 1;
     for (uint32_t r = r0; r < r1; ++r) {
         const uint32_t c = r * 64 + lane;
@@ -43,9 +45,11 @@ __device__ __forceinline__ void wg_add_rows(const Src &src, uint32_t *__restrict
     if (lane == 0) summary[w] = cin | (allp << 1);
     __syncthreads();
     cin = 0;
-    for (uint32_t v = 0; v < w; ++v) {
+    uint32_t total = 0;
+    for (uint32_t v = 0; v < NW; ++v) {
         const uint32_t sv = summary[v];
-        cin = (sv & 1u) | ((sv >> 1) & cin);
+        if (v < w) cin = (sv & 1u) | ((sv >> 1) & cin);
+        total = (sv & 1u) | ((sv >> 1) & total);
     }
     for (uint32_t r = r0; r < r1; ++r) {
         const uint32_t c = r * 64 + lane;
@@ -58,17 +62,34 @@ __device__ __forceinline__ void wg_add_rows(const Src &src, uint32_t *__restrict
         const uint32_t ci = uint32_t(wc.into >> lane) & 1u;
         add_carry_words<4>(s, ci);
         cin = wc.out;
-        if (c < nchunks) {
-            const uint32_t base = 4 * c;
-            if (vec_ok && base + 4 <= nwords) {
-                store_words<4>(out + base, s);
-            } else {
+        if (c < nchunks) sink(c, s);
+    }
+    return total;
+}
+
+// Global-memory sink for wg_add_rows: words >= nwords are dropped.
+struct GlobalSink {
+    uint32_t *out;
+    uint32_t nwords;
+    bool vec_ok;
+    __device__ __forceinline__ void operator()(uint32_t c, const uint32_t (&s)[4]) const {
+        const uint32_t base = 4 * c;
+        if (vec_ok && base + 4 <= nwords) {
+            store_words<4>(out + base, s);
+        } else {
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if (base + t < nwords) out[base + t] = s[t];
-            }
+            for (int t = 0; t < 4; ++t)
+                if (base + t < nwords) out[base + t] = s[t];
         }
     }
+};
+
+// x + y written to global memory (nwords words).
+template <int NW, class Src>
+__device__ __forceinline__ void wg_add_rows(const Src &src, uint32_t *__restrict__ out, uint32_t nwords,
+                                            uint32_t *summary /* LDS, NW words */) {
+    const GlobalSink sink{out, nwords, (reinterpret_cast<uintptr_t>(out) & 15) == 0};
+    (void)wg_add_rows_sink<NW>(src, sink, nwords, summary);
 }
 
 // Addends of a product in "low / high" form with groups of 4 words: L holds

@@ -233,6 +233,59 @@ __global__ __launch_bounds__(64 * NW) void bigadd_coop_kernel(const uint32_t *__
     }
 }
 
+// Barrier-free schedule for instances of RPI rows (2 to 8): one wavefront
+// loads U whole instances (U * RPI rows) before consuming any, then chains
+// the scalar carry through each instance's rows.
+template <int W, int U, int RPI, bool NT>
+__global__ __launch_bounds__(256) void bigadd_multi_kernel(const uint32_t *__restrict__ a,
+                                                           const uint32_t *__restrict__ b,
+                                                           uint32_t *out, uint8_t *carry, uint32_t m,
+                                                           uint64_t batch) {
+    const uint32_t lane = lane_id();
+    const uint64_t wave = wave_global();
+    const uint64_t nwaves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
+    for (uint64_t i0 = wave * U; i0 < batch; i0 += nwaves * U) {
+        uint32_t s[U][RPI][W];
+        uint32_t gl[U][RPI], pl[U][RPI];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int r = 0; r < RPI; ++r) {
+                const uint32_t c = r * 64 + lane;
+                uint32_t va[W], vb[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) { va[w] = 0; vb[w] = 0; }
+                const bool ok = (i0 + u < batch) && c < m;
+                if (ok) {
+                    const uint64_t off = ((i0 + u) * m + c) * W;
+                    load_words<W, NT>(a + off, va);
+                    load_words<W, NT>(b + off, vb);
+                }
+                gl[u][r] = add_words<W>(va, vb, s[u][r]);
+                pl[u][r] = (ok && all_ones<W>(s[u][r])) ? 1u : 0u;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i0 + u >= batch) break;  // uniform
+            uint32_t cin = 0;
+#pragma unroll
+            for (int r = 0; r < RPI; ++r) {
+                const uint32_t c = r * 64 + lane;
+                if (r * 64 >= int(m)) break;  // uniform
+                const uint64_t G = ballot(gl[u][r] != 0), P = ballot(pl[u][r] != 0);
+                const WaveCarry wc = wave_carry(G, P, cin);
+                const uint32_t ci = uint32_t(wc.into >> lane) & 1u;
+                add_carry_words<W>(s[u][r], ci);
+                if (c < m) store_words<W, NT>(out + ((i0 + u) * m + c) * W, s[u][r]);
+                const uint32_t valid = min(m - r * 64, 64u);
+                cin = valid >= 64 ? wc.out : uint32_t(wc.into >> valid) & 1u;
+            }
+            if (carry && lane == 0) carry[i0 + u] = uint8_t(cin);
+        }
+    }
+}
+
 // Largest chunk (in bytes) that divides the instance length and all pointers.
 static int pick_chunk_bytes(uint64_t inst_bytes, const void *a, const void *b, const void *o) {
     const uint64_t al = uint64_t(reinterpret_cast<uintptr_t>(a)) | uint64_t(reinterpret_cast<uintptr_t>(b)) |
@@ -244,7 +297,7 @@ static int pick_chunk_bytes(uint64_t inst_bytes, const void *a, const void *b, c
 
 template <int W, int U, bool NT>
 static hipError_t launch_wu(const uint32_t *a, const uint32_t *b, uint32_t *o, uint8_t *carry, uint64_t m,
-                            uint64_t batch, hipStream_t st, uint64_t max_waves) {
+                            uint64_t batch, hipStream_t st, uint64_t max_waves, bool multi) {
     if (m <= 64) {
         const uint32_t ipr = uint32_t(64 / m);
         const uint64_t nrows = (batch + ipr - 1) / ipr;
@@ -253,6 +306,21 @@ static hipError_t launch_wu(const uint32_t *a, const uint32_t *b, uint32_t *o, u
         const uint64_t blocks = (waves + 3) / 4;
         hipLaunchKernelGGL((bigadd_packed_kernel<W, U, NT>), dim3(uint32_t(blocks)), dim3(256), 0, st, a, b, o, carry,
                            uint32_t(m), ipr, batch);
+    } else if (multi && m <= 8 * 64) {
+        // Up to 8 rows: one wave per instance, `U` instances in flight.
+        const uint64_t rows = (m + 63) / 64;
+        uint64_t waves = (batch + U - 1) / U;
+        if (waves > max_waves) waves = max_waves;
+        const dim3 g{uint32_t((waves + 3) / 4), 1, 1};
+        if (rows <= 2)
+            hipLaunchKernelGGL((bigadd_multi_kernel<W, (U > 2 ? U / 2 : 1), 2, NT>), g, dim3(256), 0, st, a, b, o,
+                               carry, uint32_t(m), batch);
+        else if (rows <= 4)
+            hipLaunchKernelGGL((bigadd_multi_kernel<W, (U > 4 ? U / 4 : 1), 4, NT>), g, dim3(256), 0, st, a, b, o,
+                               carry, uint32_t(m), batch);
+        else
+            hipLaunchKernelGGL((bigadd_multi_kernel<W, 1, 8, NT>), g, dim3(256), 0, st, a, b, o, carry, uint32_t(m),
+                               batch);
     } else {
         // One workgroup per instance: NW waves x UC rows cover the instance
         // in one tile when it has at most 32 rows.
@@ -280,14 +348,15 @@ template <int W>
 static hipError_t launch_w(const uint32_t *a, const uint32_t *b, uint32_t *o, uint8_t *carry, uint64_t m,
                            uint64_t batch, hipStream_t st, const AddTune &t) {
     const uint64_t mw = t.max_waves;
+    const bool mu = (m <= 8 * 64) && ((m <= 2 * 64) ? t.multi2 : (m <= 4 * 64) ? t.multi4 : t.multi8);
     if (t.nt) {
-        if (t.rows == 2) return launch_wu<W, 2, true>(a, b, o, carry, m, batch, st, mw);
-        if (t.rows == 8) return launch_wu<W, 8, true>(a, b, o, carry, m, batch, st, mw);
-        return launch_wu<W, 4, true>(a, b, o, carry, m, batch, st, mw);
+        if (t.rows == 2) return launch_wu<W, 2, true>(a, b, o, carry, m, batch, st, mw, mu);
+        if (t.rows == 8) return launch_wu<W, 8, true>(a, b, o, carry, m, batch, st, mw, mu);
+        return launch_wu<W, 4, true>(a, b, o, carry, m, batch, st, mw, mu);
     }
-    if (t.rows == 2) return launch_wu<W, 2, false>(a, b, o, carry, m, batch, st, mw);
-    if (t.rows == 8) return launch_wu<W, 8, false>(a, b, o, carry, m, batch, st, mw);
-    return launch_wu<W, 4, false>(a, b, o, carry, m, batch, st, mw);
+    if (t.rows == 2) return launch_wu<W, 2, false>(a, b, o, carry, m, batch, st, mw, mu);
+    if (t.rows == 8) return launch_wu<W, 8, false>(a, b, o, carry, m, batch, st, mw, mu);
+    return launch_wu<W, 4, false>(a, b, o, carry, m, batch, st, mw, mu);
 }
 
 hipError_t launch_bigadd_ragged(const void *a, const void *b, void *out, uint8_t *carry, const bi_desc *desc,

@@ -112,16 +112,18 @@ __device__ __forceinline__ void small_dit_inv(uint32_t *x, const uint2 *__restri
 }
 
 // Position k of a group with offset lo in a pass starting at stage s gets the
-// factor w_L^(2^s lo bitrev_R(k)); tables are indexed in units of w_Lmax.
-template <int M, int R>
-__device__ __forceinline__ void twiddle_group(uint32_t *x, const uint2 *__restrict__ tbl, uint32_t lo_s, uint32_t p) {
+// factor w_L^(2^s lo bitrev_R(k)).  The tables hold these products indexed by
+// (bitrev_R(k), lo) with lo fastest, so the lanes of a wave (consecutive lo)
+// read consecutive entries: row stride 1024 for pass 0 (lo = gidx < 1024),
+// 32 for pass 1 (lo < 32, where w_L^(2^s) = w_1024).
+template <int M, int R, uint32_t STRIDE>
+__device__ __forceinline__ void twiddle_group(uint32_t *x, const uint2 *__restrict__ tbl, uint32_t lo, uint32_t p) {
 #pragma unroll
     for (int k = 1; k < (1 << R); ++k) {
-        const uint32_t e = lo_s * bitrev<R>(k);  // < L
-        const uint2 w = tbl[e << (kNttLogLmax - M)];
+        const uint2 w = tbl[STRIDE * bitrev<R>(k) + lo];
         x[k] = mul_shoup(x[k], w.x, w.y, p);
-        // Bound the twiddle loads in flight (each costs 4 registers with its
-        // address): 8 when registers allow, 4 for the 1024-thread transform.
+        // Bound the twiddle loads in flight: 8 when registers allow, 4 for the
+        // 1024-thread transform.
         if ((k & (M >= 15 ? 3 : 7)) == (M >= 15 ? 3 : 7)) __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -163,7 +165,7 @@ __device__ __forceinline__ void ntt_forward(const uint32_t *__restrict__ src, ui
     for (int g = 0; g < G0; ++g) {
         const uint32_t gidx = t + T * g;
         small_dif<R0>(x + g * (1 << R0), fw, p);
-        twiddle_group<M, R0>(x + g * (1 << R0), fw, gidx, p);
+        twiddle_group<M, R0, 1024>(x + g * (1 << R0), fw + ntt_t0_offset(M), gidx, p);
         uint32_t *q = sh + padx(gidx);
 #pragma unroll
         for (int k = 0; k < (1 << R0); ++k) q[1056 * k] = x[g * (1 << R0) + k];
@@ -175,7 +177,7 @@ __device__ __forceinline__ void ntt_forward(const uint32_t *__restrict__ src, ui
 #pragma unroll
         for (int k = 0; k < 32; ++k) x[k] = q[33 * k];
         small_dif<5>(x, fw, p);
-        twiddle_group<M, 5>(x, fw, (t & 31u) << R0, p);
+        twiddle_group<M, 5, 32>(x, fw + kNttT1, t & 31u, p);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 32; ++k) q[33 * k] = x[k];
@@ -212,7 +214,7 @@ __device__ __forceinline__ void ntt_inverse(uint32_t (&x)[E], uint32_t *__restri
         uint32_t *q = sh + base_pass1(t);
 #pragma unroll
         for (int k = 0; k < 32; ++k) x[k] = q[33 * k];
-        twiddle_group<M, 5>(x, iw, (t & 31u) << R0, p);
+        twiddle_group<M, 5, 32>(x, iw + kNttT1, t & 31u, p);
         small_dit_inv<5>(x, iw, p);
         __syncthreads();
 #pragma unroll
@@ -226,7 +228,7 @@ __device__ __forceinline__ void ntt_inverse(uint32_t (&x)[E], uint32_t *__restri
         const uint32_t *q = sh + padx(gidx);
 #pragma unroll
         for (int k = 0; k < (1 << R0); ++k) y[k] = q[1056 * k];
-        twiddle_group<M, R0>(y, iw, gidx, p);
+        twiddle_group<M, R0, 1024>(y, iw + ntt_t0_offset(M), gidx, p);
         small_dit_inv<R0>(y, iw, p);
 #pragma unroll
         for (int k = 0; k < (1 << R0); ++k) y[k] = mul_shoup(y[k], scale, scale_sh, p);

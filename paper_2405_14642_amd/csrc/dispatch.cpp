@@ -12,14 +12,18 @@ bi_status ctx_init(Ctx &c, int device, const hipDeviceProp_t &prop) {
     c.device = device;
     c.num_cus = prop.multiProcessorCount;
     c.add.max_waves = uint64_t(prop.multiProcessorCount) * 256;
-    // Experiment override: BI_ADD_TUNE="rows,nt,max_waves" (e.g. "8,1,32768").
+    // Experiment override: BI_ADD_TUNE="rows,nt,max_waves,multi_mask"
+    // (e.g. "8,1,32768,7"; multi_mask bit 0/1/2 = 2/4/8-row instances).
     if (const char *env = std::getenv("BI_ADD_TUNE")) {
-        int rows = 4, nt = 1;
+        int rows = 4, nt = 1, mm = 0;
         unsigned long long mw = c.add.max_waves;
-        if (std::sscanf(env, "%d,%d,%llu", &rows, &nt, &mw) >= 1) {
+        if (std::sscanf(env, "%d,%d,%llu,%d", &rows, &nt, &mw, &mm) >= 1) {
             c.add.rows = (rows == 2 || rows == 8) ? rows : 4;
             c.add.nt = nt != 0;
             c.add.max_waves = mw ? mw : c.add.max_waves;
+            c.add.multi2 = mm & 1;
+            c.add.multi4 = (mm >> 1) & 1;
+            c.add.multi8 = (mm >> 2) & 1;
         }
     }
     return ntt_setup(c.ntt);
@@ -66,6 +70,12 @@ bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint3
         case BI_MUL_SCHOOL_VALU:
             e = launch_bigmul_valu(static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
                                    static_cast<uint32_t *>(out), n32, batch, st, c.num_cus);
+            break;
+        case BI_MUL_SCHOOL_MFMA:
+            if (n32 > mfma_max_limbs())
+                return set_error(BI_EALGO, "the int8-MFMA schoolbook supports up to %u 32-bit limbs", mfma_max_limbs());
+            e = launch_bigmul_mfma(static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
+                                   static_cast<uint32_t *>(out), n32, batch, st);
             break;
         case BI_MUL_NTT: {
             if (ntt_log_len(n32) == 0) return set_error(BI_EALGO, "NTT supports up to %u limbs", kNttLmax / 4);

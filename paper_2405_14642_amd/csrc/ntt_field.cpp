@@ -96,7 +96,7 @@ bi_status field_info(uint64_t p, bi_ntt_field_info *out) {
 static const uint32_t kPrimes[kNttPrimes] = {2113929217u /* 63 2^25 + 1 */, 2130706433u /* 127 2^24 + 1 */};
 
 bi_status ntt_setup(NttTables &t) {
-    std::vector<uint2> host(size_t(kNttPrimes) * 2 * kNttLmax);
+    std::vector<uint2> host(size_t(kNttPrimes) * 2 * kNttTableWords);
     for (int i = 0; i < kNttPrimes; ++i) {
         bi_ntt_field_info fi;
         if (field_info(kPrimes[i], &fi) != BI_OK || fi.two_adicity < kNttLogLmax) return BI_EINVAL;
@@ -106,13 +106,29 @@ bi_status ntt_setup(NttTables &t) {
         t.c.p[i] = p;
         t.c.pneg[i] = neg_inv32(p);
         uint64_t f = 1, g = 1;
-        uint2 *fw = host.data() + size_t(2 * i) * kNttLmax;
-        uint2 *iw = fw + kNttLmax;
+        uint2 *fw = host.data() + size_t(2 * i) * kNttTableWords;
+        uint2 *iw = fw + kNttTableWords;
         for (uint32_t e = 0; e < kNttLmax; ++e) {
             fw[e] = make_uint2(uint32_t(f), shoup(uint32_t(f), p));
             iw[e] = make_uint2(uint32_t(g), shoup(uint32_t(g), p));
             f = mulmod(f, w, p);
             g = mulmod(g, wi, p);
+        }
+        // Twiddles of the passes, laid out so a wave reads consecutive entries:
+        // pass 1 (any length): T1[j][lo] = w_1024^(lo j), lo, j < 32;
+        // pass 0 (length 2^M): T0[j][gidx] = w_L^(gidx j), gidx < 1024, j < 2^(M-10).
+        for (int dir = 0; dir < 2; ++dir) {
+            uint2 *base = dir ? iw : fw;  // base[e] = w_Lmax^(+-e)
+            for (uint32_t j = 0; j < 32; ++j)
+                for (uint32_t lo = 0; lo < 32; ++lo)
+                    base[kNttT1 + 32 * j + lo] = base[((lo * j) % 1024) * (kNttLmax / 1024)];
+            for (uint32_t m = kNttLogLmin; m <= kNttLogLmax; ++m) {
+                uint2 *t0 = base + ntt_t0_offset(m);
+                const uint32_t L = 1u << m;
+                for (uint32_t j = 0; j < (L >> 10); ++j)
+                    for (uint32_t gi = 0; gi < 1024; ++gi)
+                        t0[1024 * j + gi] = base[(uint64_t(gi) * j % L) * (kNttLmax / L)];
+            }
         }
         // Output scale for transform length 2^l: L^-1 * R mod p (R = 2^32 undoes
         // the R^-1 left by the Montgomery pointwise product).
@@ -138,8 +154,8 @@ bi_status ntt_setup(NttTables &t) {
     }
     t.dev = static_cast<uint2 *>(d);
     for (int i = 0; i < kNttPrimes; ++i) {
-        t.c.fwd[i] = t.dev + size_t(2 * i) * kNttLmax;
-        t.c.inv[i] = t.dev + size_t(2 * i + 1) * kNttLmax;
+        t.c.fwd[i] = t.dev + size_t(2 * i) * kNttTableWords;
+        t.c.inv[i] = t.dev + size_t(2 * i + 1) * kNttTableWords;
     }
     return BI_OK;
 }

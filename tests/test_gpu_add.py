@@ -161,3 +161,24 @@ def test_full_sweep_size(B, ctx, orc, bits):
     a, b = W.add_sweep_inputs(bits)
     got, carry = run_add(B, ctx, a, b)
     check(orc, a, b, got, carry)
+
+
+@pytest.mark.parametrize("tune", ["4,1,65536,7", "2,0,16384,0", "8,1,131072,7", "4,0,8192,3", "2,1,4096,5"])
+def test_tuning_variants(B, orc, tune, monkeypatch):
+    """Every schedule the tuner can select (rows in flight, non-temporal
+    hints, grid cap, one-wave-per-instance vs workgroup-cooperative) gives the
+    same bits.  BI_ADD_TUNE is read when a context is created."""
+    monkeypatch.setenv("BI_ADD_TUNE", tune)
+    c = B.Context(0)
+    try:
+        rng = np.random.default_rng(hash(tune) & 0xFFFF)
+        for n, dt in ((1, np.uint32), (100, np.uint32), (128, np.uint64), (255, np.uint64), (256, np.uint64),
+                      (300, np.uint64), (512, np.uint64), (1000, np.uint32), (2048, np.uint64), (4096, np.uint64)):
+            a, b = rand(rng, 37, n, dt), rand(rng, 37, n, dt)
+            a[::2] = np.iinfo(dt).max
+            b[::4] = 0
+            b[::4, 0] = 1
+            got, carry = run_add(B, c, a, b)
+            check(orc, a, b, got, carry)
+    finally:
+        c.close()
