@@ -17,6 +17,16 @@ struct AddTune {
     bool multi2 = false, multi4 = false, multi8 = false;
 };
 
+constexpr uint32_t kMaxLimbs32 = BI_MAX_BITS / 32;  // 8192
+constexpr uint32_t kNumClasses = 10;               // ragged size classes: <= 16, 32, ..., 8192 limbs
+uint32_t class_nmax(uint32_t c);
+
+// Per-context tuning: multiplication algorithm per size class (BI_MUL_AUTO).
+struct Tune {
+    int mul_algo[kNumClasses];
+};
+bool algo_supports(int algo, uint32_t n32);
+
 // NTT field constants (two primes below 2^31) and device twiddle tables.
 constexpr int kNttPrimes = 2;
 constexpr int kNttLogLmax = 15;                  // transforms of up to 2^15 points
@@ -55,11 +65,46 @@ struct Scratch {
     size_t bytes = 0;
 };
 
+// Where the instances of a launch come from.  Uniform: pair p at a + p n.
+// List: entry p of a size-class list of ragged descriptors (bigmul_v).
+struct InstRef {
+    const uint32_t *a, *b;
+    uint32_t *c;
+    uint32_t n;  // 32-bit limbs
+};
+
+struct UniformInst {
+    const uint32_t *a, *b;
+    uint32_t *c;
+    uint32_t n;
+    uint64_t batch;
+    __device__ __forceinline__ uint64_t count() const { return batch; }
+    __device__ __forceinline__ InstRef get(uint64_t p) const {
+        return InstRef{a + p * n, b + p * n, c + p * 2 * n, n};
+    }
+};
+
+struct ListInst {
+    const uint32_t *a, *b;
+    uint32_t *c;
+    const bi_desc *desc;
+    const uint32_t *list;   // descriptor indices of this size class
+    const uint32_t *count_ptr;
+    uint32_t words_per_limb;  // 1 (32-bit limbs) or 2 (64-bit limbs)
+    __device__ __forceinline__ uint64_t count() const { return *count_ptr; }
+    __device__ __forceinline__ InstRef get(uint64_t p) const {
+        const bi_desc d = desc[list[p]];
+        const uint32_t w = words_per_limb;
+        return InstRef{a + d.a_off * w, b + d.b_off * w, c + d.out_off * w, d.n_limbs * w};
+    }
+};
+
 // Per-device state owned by a context.
 struct Ctx {
     int device = 0;
     int num_cus = 256;
     AddTune add;
+    Tune tune{};
     NttTables ntt;
     Scratch scratch;
 };
@@ -93,6 +138,16 @@ uint32_t ntt_log_len(uint32_t n32);  // log2 of the transform length, 0 if too l
 size_t ntt_scratch_bytes(uint32_t n32, uint64_t batch);
 hipError_t launch_bigmul_ntt(const NttConst &k, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32,
                              uint64_t batch, uint32_t *tr, hipStream_t st);
+
+// Ragged (descriptor-list) launches of one size class; nmax bounds the
+// class's limb counts, count_max bounds the class size (the true size is read
+// on the device).
+hipError_t launch_bigmul_valu_list(const ListInst &src, uint32_t nmax, uint64_t count_max, hipStream_t st,
+                                   int num_cus);
+hipError_t launch_bigmul_mfma_list(const ListInst &src, uint32_t nmax, uint64_t count_max, hipStream_t st);
+hipError_t launch_bigmul_ntt_list(const NttConst &K, const ListInst &src, uint32_t nmax, uint64_t count_max,
+                                  uint32_t *scratch, hipStream_t st, int num_cus);
+size_t ntt_fused_scratch_bytes(int num_cus);
 
 // int8-MFMA schoolbook for up to mfma_max_limbs() 32-bit limbs.
 uint32_t mfma_max_limbs();

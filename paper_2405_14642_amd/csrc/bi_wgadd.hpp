@@ -19,8 +19,9 @@ namespace bi {
 // src(c, x, y) fills the 4 words of chunk c (words 4c .. 4c+3) of both
 // addends; sink(c, s) receives the 4 sum words of chunk c (only for chunks
 // with c < nchunks).  Words at index >= nwords must read as 0.  Returns, in
-// every thread, the carry out of the whole sum.  Contains barriers: every
-// thread of the workgroup must call it.
+// every thread, the carry out of the whole sum when nwords is a multiple of 4
+// (otherwise that carry stays inside the last chunk's sum words).  Contains
+// barriers: every thread of the workgroup must call it.
 template <int NW, class Src, class Sink>
 __device__ __forceinline__ uint32_t wg_add_rows_sink(const Src &src, const Sink &sink, uint32_t nwords,
                                                      uint32_t *summary /* LDS, NW words */) {
@@ -39,8 +40,11 @@ __device__ __forceinline__ uint32_t wg_add_rows_sink(const Src &src, const Sink 
         const bool p = c < nchunks && all_ones<4>(s);
         const uint64_t G = ballot(g), P = ballot(p);
         const WaveCarry wc = wave_carry(G, P, cin);
-        cin = wc.out;
-        allp &= (P == ~0ull) ? 1u : 0u;
+        // a partial last row carries out of its first unused lane
+        const uint32_t valid = min(nchunks - r * 64, 64u);
+        const uint64_t vmask = valid >= 64 ? ~0ull : ((1ull << valid) - 1);
+        cin = valid >= 64 ? wc.out : uint32_t(wc.into >> valid) & 1u;
+        allp &= (P == vmask) ? 1u : 0u;
     }
     if (lane == 0) summary[w] = cin | (allp << 1);
     __syncthreads();
@@ -61,7 +65,8 @@ __device__ __forceinline__ uint32_t wg_add_rows_sink(const Src &src, const Sink 
         const WaveCarry wc = wave_carry(G, P, cin);
         const uint32_t ci = uint32_t(wc.into >> lane) & 1u;
         add_carry_words<4>(s, ci);
-        cin = wc.out;
+        const uint32_t valid = min(nchunks - r * 64, 64u);
+        cin = valid >= 64 ? wc.out : uint32_t(wc.into >> valid) & 1u;
         if (c < nchunks) sink(c, s);
     }
     return total;

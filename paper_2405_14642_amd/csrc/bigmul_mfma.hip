@@ -78,27 +78,27 @@ struct LHSrc4w1 {
 
 }  // namespace
 
-template <int NW>
-__global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(const uint32_t *__restrict__ A,
-                                                              const uint32_t *__restrict__ B,
-                                                              uint32_t *__restrict__ C, uint32_t n32, uint32_t n32p,
-                                                              uint64_t batch) {
+template <int NW, class Src>
+__global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
     extern __shared__ __align__(16) uint8_t lds[];
-    const MfmaLayout lo = mfma_layout(n32p);
-    uint8_t *acopy = lds + lo.acopy;
-    uint8_t *bdig = lds + lo.bdig;
-    int32_t *coef = reinterpret_cast<int32_t *>(lds + lo.coef);
-    uint32_t *adig = reinterpret_cast<uint32_t *>(lds + lo.coef);  // temporary, aliases coef
-    uint32_t *summary = reinterpret_cast<uint32_t *>(lds + lo.small);
-    uint32_t *Lw = reinterpret_cast<uint32_t *>(lds + lo.acopy);  // normalisation, aliases the copies
-    uint32_t *Hw = Lw + 4 * lo.G;
-    const uint32_t D = lo.D, nb = lo.nb, CS = lo.CS, X = D + kPadA;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = wave_in_block();
     constexpr uint32_t T = 64 * NW;
+    const uint64_t count = src.count();
 
-    for (uint64_t pair = blockIdx.x; pair < batch; pair += gridDim.x) {
-        const uint32_t *a = A + pair * n32;
-        const uint32_t *b = B + pair * n32;
+    for (uint64_t pair = blockIdx.x; pair < count; pair += gridDim.x) {
+        const InstRef in = src.get(pair);
+        const uint32_t n32 = in.n, n32p = (n32 + 7) & ~7u;
+        const uint32_t *a = in.a;
+        const uint32_t *b = in.b;
+        const MfmaLayout lo = mfma_layout(n32p);
+        uint8_t *acopy = lds + lo.acopy;
+        uint8_t *bdig = lds + lo.bdig;
+        int32_t *coef = reinterpret_cast<int32_t *>(lds + lo.coef);
+        uint32_t *adig = reinterpret_cast<uint32_t *>(lds + lo.coef);  // temporary, aliases coef
+        uint32_t *summary = reinterpret_cast<uint32_t *>(lds + lo.small);
+        uint32_t *Lw = reinterpret_cast<uint32_t *>(lds + lo.acopy);  // normalisation, aliases the copies
+        uint32_t *Hw = Lw + 4 * lo.G;
+        const uint32_t D = lo.D, nb = lo.nb, CS = lo.CS, X = D + kPadA;
 
         // 1. balanced digits of a (words of (a + R) ^ R) and its top digit
         auto src_a = [&](uint32_t c, uint32_t (&x)[4], uint32_t (&y)[4]) {
@@ -218,36 +218,44 @@ __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(const uint32_t *__
         __syncthreads();
 
         // 7. product = L + H (mod 2^(64 n32))
-        wg_add_rows<NW>(LHSrc4w1{Lw, Hw, 2 * n32}, C + pair * 2 * n32, 2 * n32, summary);
+        wg_add_rows<NW>(LHSrc4w1{Lw, Hw, 2 * n32}, in.c, 2 * n32, summary);
         __syncthreads();
     }
 }
 
 uint32_t mfma_max_limbs() { return 1024; }
 
-template <int NW>
-static hipError_t launch_nw(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
-                            hipStream_t st) {
-    const uint32_t n32p = (n32 + 7) & ~7u;
-    const MfmaLayout lo = mfma_layout(n32p);
+template <int NW, class Src>
+static hipError_t launch_nw(const Src &src, uint32_t nmax, uint64_t count, hipStream_t st) {
+    const MfmaLayout lo = mfma_layout((nmax + 7) & ~7u);
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&bigmul_mfma_kernel<NW>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&bigmul_mfma_kernel<NW, Src>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    const uint32_t grid = uint32_t(batch < 65536 ? batch : 65536);
-    hipLaunchKernelGGL((bigmul_mfma_kernel<NW>), dim3(grid), dim3(64 * NW), lo.total, st, a, b, c, n32, n32p, batch);
+    const uint32_t grid = uint32_t(count < 65536 ? count : 65536);
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL((bigmul_mfma_kernel<NW, Src>), dim3(grid), dim3(64 * NW), lo.total, st, src);
     return hipGetLastError();
+}
+
+template <class Src>
+static hipError_t launch_mfma(const Src &src, uint32_t nmax, uint64_t count, hipStream_t st) {
+    if (nmax > mfma_max_limbs()) return hipErrorInvalidValue;
+    if (nmax <= 256) return launch_nw<4>(src, nmax, count, st);
+    return launch_nw<8>(src, nmax, count, st);
 }
 
 hipError_t launch_bigmul_mfma(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
                               hipStream_t st) {
     if (batch == 0) return hipSuccess;
-    if (n32 > mfma_max_limbs()) return hipErrorInvalidValue;
-    if (n32 <= 256) return launch_nw<4>(a, b, c, n32, batch, st);
-    return launch_nw<8>(a, b, c, n32, batch, st);
+    return launch_mfma(UniformInst{a, b, c, n32, batch}, n32, batch, st);
+}
+
+hipError_t launch_bigmul_mfma_list(const ListInst &src, uint32_t nmax, uint64_t count_max, hipStream_t st) {
+    return launch_mfma(src, nmax, count_max, st);
 }
 
 }  // namespace bi

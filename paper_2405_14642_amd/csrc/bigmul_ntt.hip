@@ -351,6 +351,119 @@ __global__ __launch_bounds__(64 * NW) void ntt_crt_carry_kernel(NttConst K, cons
     }
 }
 
+// Ragged batches: one workgroup per instance does both primes and the
+// recombination.  The first operand's transform is parked in the
+// workgroup's scratch slot (each thread re-reads only what it wrote), the
+// residues of both primes follow it in the slot, and after a barrier the
+// same workgroup runs Garner's CRT and the final carry scan.
+template <int M, class Src>
+__global__ __launch_bounds__((1 << M) / E) void ntt_fused_kernel(NttConst K, Src src, uint32_t *__restrict__ scratch) {
+    extern __shared__ __align__(16) uint32_t sh[];
+    constexpr uint32_t L = 1u << M;
+    constexpr int NW = int(L / E / 64);
+    uint32_t *slot = scratch + uint64_t(blockIdx.x) * 3 * L;
+    const uint32_t t = threadIdx.x;
+    const uint64_t count = src.count();
+    for (uint64_t inst = blockIdx.x; inst < count; inst += gridDim.x) {
+        const InstRef in = src.get(inst);
+        const uint32_t n32 = in.n, nout = 4 * n32;
+#pragma nounroll
+        for (int pr = 0; pr < 2; ++pr) {
+            const uint32_t p = K.p[pr], pneg = K.pneg[pr];
+            uint32_t x[E];
+            ntt_forward<M>(in.a, n32, x, sh, K.fwd[pr], p);
+            uint4 *park = reinterpret_cast<uint4 *>(slot + E * t);
+#pragma unroll
+            for (int q = 0; q < E / 4; ++q) park[q] = make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+            ntt_forward<M>(in.b, n32, x, sh, K.fwd[pr], p);
+#pragma unroll
+            for (int q = 0; q < E / 4; ++q) {
+                const uint4 u = park[q];
+                x[4 * q] = mul_mont(u.x, x[4 * q], p, pneg);
+                x[4 * q + 1] = mul_mont(u.y, x[4 * q + 1], p, pneg);
+                x[4 * q + 2] = mul_mont(u.z, x[4 * q + 2], p, pneg);
+                x[4 * q + 3] = mul_mont(u.w, x[4 * q + 3], p, pneg);
+            }
+            ntt_inverse<M>(x, slot + (1 + pr) * L, nout, sh, K.inv[pr], p, K.scale[pr][M], K.scale_sh[pr][M]);
+        }
+        __syncthreads();  // residues of both primes written (same CU: workgroup-coherent)
+        const uint32_t nwords = 2 * n32, ngroups = (nwords + 3) / 4;
+        uint32_t *Lsh = sh;
+        uint2 *Hsh = reinterpret_cast<uint2 *>(Lsh + 4 * ngroups);
+        uint32_t *summary = reinterpret_cast<uint32_t *>(Hsh + ngroups);
+        const uint32_t *r1 = slot + L, *r2 = slot + 2 * L;
+        const uint32_t p1 = K.p[0], p2 = K.p[1];
+        for (uint32_t g = t; g < ngroups; g += L / E) {
+            uint64_t col[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t k = 8 * g + e;
+                uint64_t c = 0;
+                if (k < nout) {
+                    const uint32_t a1 = r1[k], a2 = r2[k];
+                    const uint32_t tq = mul_shoup(sub_mod(a2, a1, p2), K.crt, K.crt_sh, p2);
+                    c = uint64_t(p1) * tq + a1;
+                }
+                const uint64_t v = c << (16 * (e & 1));
+                col[e >> 1] += uint32_t(v);
+                col[(e >> 1) + 1] += uint32_t(v >> 32);
+            }
+            uint64_t carry = 0;
+            uint32_t R[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                const uint64_t sv = col[j] + carry;
+                R[j] = uint32_t(sv);
+                carry = sv >> 32;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Lsh[4 * g + j] = R[j];
+            Hsh[g] = make_uint2(R[4], R[5]);
+        }
+        __syncthreads();
+        wg_add_rows<NW>(LHSrc4{Lsh, Hsh, nwords}, in.c, nwords, summary);
+        __syncthreads();
+    }
+}
+
+template <int M>
+static hipError_t launch_fused_m(const NttConst &K, const ListInst &src, uint64_t count_max, uint32_t *scratch,
+                                 uint32_t grid, hipStream_t st) {
+    const size_t lds = sizeof(uint32_t) * ((1u << M) + (1u << M) / 32);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_fused_kernel<M, ListInst>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    if (count_max < grid) grid = uint32_t(count_max);
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL((ntt_fused_kernel<M, ListInst>), dim3(grid), dim3((1u << M) / E), lds, st, K, src, scratch);
+    return hipGetLastError();
+}
+
+uint32_t ntt_fused_grid(uint32_t m, int num_cus) { return uint32_t(num_cus) << (kNttLogLmax - m); }
+
+size_t ntt_fused_scratch_bytes(int num_cus) {
+    // every transform length uses num_cus 2^(15-M) workgroups x 3 2^M words
+    return size_t(num_cus) * 3 * kNttLmax * sizeof(uint32_t);
+}
+
+hipError_t launch_bigmul_ntt_list(const NttConst &K, const ListInst &src, uint32_t nmax, uint64_t count_max,
+                                  uint32_t *scratch, hipStream_t st, int num_cus) {
+    const uint32_t m = ntt_log_len(nmax);
+    const uint32_t grid = ntt_fused_grid(m, num_cus);
+    switch (m) {
+        case 11: return launch_fused_m<11>(K, src, count_max, scratch, grid, st);
+        case 12: return launch_fused_m<12>(K, src, count_max, scratch, grid, st);
+        case 13: return launch_fused_m<13>(K, src, count_max, scratch, grid, st);
+        case 14: return launch_fused_m<14>(K, src, count_max, scratch, grid, st);
+        case 15: return launch_fused_m<15>(K, src, count_max, scratch, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 uint32_t ntt_log_len(uint32_t n32) {
     uint32_t m = 11;  // smallest supported transform (64 threads)
     while ((1u << m) < 4 * n32) ++m;

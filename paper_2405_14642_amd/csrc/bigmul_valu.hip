@@ -67,25 +67,25 @@ __device__ __forceinline__ void load_window(const uint32_t *Bsh, int32_t addr, u
 
 }  // namespace
 
-template <int Q, int NW>
-__global__ __launch_bounds__(64 * NW) void bigmul_valu_kernel(const uint32_t *__restrict__ A,
-                                                              const uint32_t *__restrict__ B,
-                                                              uint32_t *__restrict__ C, uint32_t n, uint64_t batch) {
+template <int Q, int NW, class Src>
+__global__ __launch_bounds__(64 * NW) void bigmul_valu_kernel(Src src) {
     extern __shared__ __align__(16) uint32_t lds[];
     constexpr uint32_t span = 64 * Q;
-    const uint32_t NB = (2 * n + span - 1) / span;  // blocks over the 2n output words
     constexpr uint32_t kPad = pad_words<Q>();
-    const uint32_t nbw = (n + 2 * kPad + 3) & ~3u;
-    uint32_t *Bsh = lds;                              // [nbw]
-    uint32_t *Lsh = Bsh + nbw;                        // [NB * span]
-    uint2 *Hsh = reinterpret_cast<uint2 *>(Lsh + NB * span);  // [NB * 64]
-    uint32_t *summary = reinterpret_cast<uint32_t *>(Hsh + NB * 64);  // [NW]
-
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = wave_in_block();
+    const uint64_t count = src.count();
 
-    for (uint64_t inst = blockIdx.x; inst < batch; inst += gridDim.x) {
-        const uint32_t *a = A + inst * n;
-        const uint32_t *b = B + inst * n;
+    for (uint64_t inst = blockIdx.x; inst < count; inst += gridDim.x) {
+        const InstRef in = src.get(inst);
+        const uint32_t n = in.n;
+        const uint32_t *a = in.a;
+        const uint32_t *b = in.b;
+        const uint32_t NB = (2 * n + span - 1) / span;  // blocks over the 2n output words
+        const uint32_t nbw = (n + 2 * kPad + 3) & ~3u;
+        uint32_t *Bsh = lds;                              // [nbw]
+        uint32_t *Lsh = Bsh + nbw;                        // [NB * span]
+        uint2 *Hsh = reinterpret_cast<uint2 *>(Lsh + NB * span);  // [NB * 64]
+        uint32_t *summary = reinterpret_cast<uint32_t *>(Hsh + NB * 64);  // [NW]
         for (uint32_t t = tid; t < nbw; t += 64 * NW) Bsh[t] = (t >= kPad && t < kPad + n) ? b[t - kPad] : 0u;
         __syncthreads();
 
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(64 * NW) void bigmul_valu_kernel(const uint32_t *__
         // out = L + H over 2n words.  H holds, for lane group g (coefficients
         // Q g .. Q g + Q - 1), its high word at position Q (g+1) and its carry
         // word at Q (g+1) + 1.
-        auto src = [&](uint32_t c, uint32_t (&x)[4], uint32_t (&y)[4]) {
+        auto lh = [&](uint32_t c, uint32_t (&x)[4], uint32_t (&y)[4]) {
             const uint4 l = *reinterpret_cast<const uint4 *>(Lsh + 4 * c);
             x[0] = l.x; x[1] = l.y; x[2] = l.z; x[3] = l.w;
             if constexpr (Q == 4) {
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(64 * NW) void bigmul_valu_kernel(const uint32_t *__
             for (int t = 0; t < 4; ++t)
                 if (base + t >= 2 * n) { x[t] = 0; y[t] = 0; }
         };
-        wg_add_rows<NW>(src, C + inst * 2 * n, 2 * n, summary);
+        wg_add_rows<NW>(lh, in.c, 2 * n, summary);
         __syncthreads();
     }
 }
@@ -190,18 +190,16 @@ size_t valu_lds_bytes(uint32_t n, int Q, int NW) {
     return 4ull * (nbw + NB * span + 2ull * NB * 64 + NW);
 }
 
-template <int Q, int NW>
-static hipError_t launch_q(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n, uint64_t batch,
-                           uint32_t grid, hipStream_t st) {
-    const size_t lds = valu_lds_bytes(n, Q, NW);
+template <int Q, int NW, class Src>
+static hipError_t launch_q(const Src &src, size_t lds, uint32_t grid, hipStream_t st) {
     static bool attr_set = false;  // allow up to the whole 160 KiB LDS of a CU
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&bigmul_valu_kernel<Q, NW>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&bigmul_valu_kernel<Q, NW, Src>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((bigmul_valu_kernel<Q, NW>), dim3(grid), dim3(64 * NW), lds, st, a, b, c, n, batch);
+    hipLaunchKernelGGL((bigmul_valu_kernel<Q, NW, Src>), dim3(grid), dim3(64 * NW), lds, st, src);
     return hipGetLastError();
 }
 
@@ -218,18 +216,31 @@ ValuPlan valu_plan(uint32_t n) {
     return p;
 }
 
-hipError_t launch_bigmul_valu(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n, uint64_t batch,
-                              hipStream_t st, int num_cus) {
-    if (batch == 0) return hipSuccess;
-    const ValuPlan p = valu_plan(n);
+// A plan sized for instances of up to nmax limbs (Q, waves and LDS of the
+// largest); smaller instances of a ragged class run with the same plan.
+template <class Src>
+static hipError_t launch_plan(const Src &src, uint32_t nmax, uint64_t count, hipStream_t st, int num_cus) {
+    const ValuPlan p = valu_plan(nmax);
     const uint64_t cap = uint64_t(num_cus) * 32;
-    const uint32_t grid = uint32_t(batch < cap ? batch : cap);
+    const uint32_t grid = uint32_t(count < cap ? count : cap);
+    if (grid == 0) return hipSuccess;
 #define BI_VALU_CASE(QQ, WW) \
-    if (p.Q == QQ && p.NW == WW) return launch_q<QQ, WW>(a, b, c, n, batch, grid, st);
+    if (p.Q == QQ && p.NW == WW) return launch_q<QQ, WW>(src, p.lds, grid, st);
     BI_VALU_CASE(2, 1) BI_VALU_CASE(2, 2) BI_VALU_CASE(2, 4) BI_VALU_CASE(2, 8) BI_VALU_CASE(2, 16)
     BI_VALU_CASE(4, 1) BI_VALU_CASE(4, 2) BI_VALU_CASE(4, 4) BI_VALU_CASE(4, 8) BI_VALU_CASE(4, 16)
 #undef BI_VALU_CASE
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_bigmul_valu(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n, uint64_t batch,
+                              hipStream_t st, int num_cus) {
+    if (batch == 0) return hipSuccess;
+    return launch_plan(UniformInst{a, b, c, n, batch}, n, batch, st, num_cus);
+}
+
+hipError_t launch_bigmul_valu_list(const ListInst &src, uint32_t nmax, uint64_t count_max, hipStream_t st,
+                                   int num_cus) {
+    return launch_plan(src, nmax, count_max, st, num_cus);
 }
 
 }  // namespace bi

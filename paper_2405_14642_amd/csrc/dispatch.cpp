@@ -8,8 +8,26 @@
 
 namespace bi {
 
+bool algo_supports(int algo, uint32_t n32) {
+    switch (algo) {
+        case BI_MUL_SCHOOL_VALU: return n32 >= 1 && n32 <= kMaxLimbs32;
+        case BI_MUL_SCHOOL_MFMA: return n32 >= 1 && n32 <= mfma_max_limbs();
+        case BI_MUL_NTT: return n32 >= 1 && ntt_log_len(n32) != 0;
+        default: return false;
+    }
+}
+
+// Default algorithm per size class (replaced by bi_autotune measurements).
+static void default_tune(Tune &t) {
+    for (uint32_t k = 0; k < kNumClasses; ++k) {
+        const uint32_t n = class_nmax(k);
+        t.mul_algo[k] = n <= 1024 ? BI_MUL_SCHOOL_VALU : BI_MUL_NTT;
+    }
+}
+
 bi_status ctx_init(Ctx &c, int device, const hipDeviceProp_t &prop) {
     c.device = device;
+    default_tune(c.tune);
     c.num_cus = prop.multiProcessorCount;
     c.add.max_waves = uint64_t(prop.multiProcessorCount) * 256;
     // Experiment override: BI_ADD_TUNE="rows,nt,max_waves,multi_mask"
@@ -62,9 +80,18 @@ bi_status dispatch_bigadd_v(Ctx &c, const void *a, const void *b, void *out, uin
     return BI_OK;
 }
 
+uint32_t size_class_host(uint32_t n32) {
+    uint32_t k = 0;
+    while (k + 1 < kNumClasses && class_nmax(k) < n32) ++k;
+    return k;
+}
+
 bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint32_t n32, uint64_t batch, int algo,
                           hipStream_t st) {
-    if (algo == BI_MUL_AUTO) algo = BI_MUL_SCHOOL_VALU;
+    if (algo == BI_MUL_AUTO) {
+        algo = c.tune.mul_algo[size_class_host(n32)];
+        if (!algo_supports(algo, n32)) algo = BI_MUL_SCHOOL_VALU;
+    }
     hipError_t e = hipSuccess;
     switch (algo) {
         case BI_MUL_SCHOOL_VALU:
@@ -92,12 +119,6 @@ bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint3
     }
     if (e != hipSuccess) return set_error(BI_EHIP, "bigmul launch: %s", hipGetErrorString(e));
     return BI_OK;
-}
-
-bi_status dispatch_bigmul_v(Ctx &c, const void *a, const void *b, void *out, const bi_desc *desc, uint64_t count,
-                            uint32_t limb_bits, int algo, hipStream_t st) {
-    (void)c; (void)a; (void)b; (void)out; (void)desc; (void)count; (void)limb_bits; (void)st;
-    return set_error(BI_EALGO, "multiplication algorithm %d is not available", algo);
 }
 
 }  // namespace bi

@@ -167,3 +167,37 @@ def test_full_size_ntt_workload(B, ctx, orc, algo, bits, batch):
     for p in (1000003, 999983):
         P = np.uint64(p)
         assert (residues(got, p) == (residues(a, p) * residues(b, p)) % P).all()
+
+
+@pytest.mark.parametrize("algo", ["auto"] + list(ALGOS))
+@pytest.mark.parametrize("lb", [32, 64])
+def test_ragged_bigmul_v(B, ctx, orc, algo, lb):
+    """bigmul_v over a ragged batch spanning every size class; b stored in
+    reverse instance order, outputs with gaps between them.  A forced
+    algorithm applies to the classes it supports, the others use the tuned
+    choice."""
+    dt = np.uint32 if lb == 32 else np.uint64
+    rng = np.random.default_rng(4242 + lb)
+    ns = [1, 2, 16, 17, 33, 64, 65, 100, 128, 129, 255, 300, 511, 513, 1000, 1025, 2047, 2049, 4000, 4097, 8192]
+    if lb == 64:
+        ns = [max(1, n // 2) for n in ns]
+    ns = np.array(ns, dtype=np.int64)
+    tot = int(ns.sum())
+    A = rng.integers(0, np.iinfo(dt).max, tot, dtype=dt, endpoint=True)
+    Bv = rng.integers(0, np.iinfo(dt).max, tot, dtype=dt, endpoint=True)
+    a_off = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.uint64)
+    b_off = np.concatenate([[0], np.cumsum(ns[::-1])[:-1]])[::-1].astype(np.uint64)
+    A[: int(ns[0] + ns[1] + ns[2])] = np.iinfo(dt).max          # all-ones operands in the small classes
+    Bv[int(b_off[2]): int(b_off[2] + ns[2])] = np.iinfo(dt).max
+    out_off = np.concatenate([[0], np.cumsum(2 * ns + 3)[:-1]]).astype(np.uint64)
+    out_len = int(out_off[-1] + 2 * ns[-1] + 3)
+    dev_out = G.empty_dev((out_len,), dt)
+    desc = G.desc_dev(a_off, b_off, out_off, ns)
+    code = 0 if algo == "auto" else ALGOS[algo]
+    B.bigmul_v(ctx, G.to_dev(A), G.to_dev(Bv), dev_out, desc, len(ns), lb, algo=code)
+    G.sync()
+    got = G.from_dev(dev_out, dt)
+    for i, n in enumerate(ns.tolist()):
+        ao, bo, oo = int(a_off[i]), int(b_off[i]), int(out_off[i])
+        want = orc.mul(A[ao: ao + n][None], Bv[bo: bo + n][None])[0]
+        assert (got[oo: oo + 2 * n] == want).all(), (i, n)
