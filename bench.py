@@ -65,6 +65,10 @@ def add_kernel_name(n_limbs, limb_bits):
     if m <= 64:
         return "bi::bigadd_packed_kernel<4, 4, true>"
     rows = (m + 63) // 64
+    if rows <= 2:
+        return "bi::bigadd_multi_kernel<4, 2, 2, true>"
+    if rows <= 4:
+        return "bi::bigadd_multi_kernel<4, 1, 4, true>"
     u, nw = (1, 2) if rows <= 2 else (1, 4) if rows <= 4 else (2, 4) if rows <= 8 else (2, 8) if rows <= 16 else (4, 8)
     return f"bi::bigadd_coop_kernel<4, {u}, {nw}, true>"
 
@@ -155,7 +159,7 @@ def bench_add(args):
     }
 
 
-# Peak rates used for the multiplication rooflines (the design doc derives them):
+# Peak rates used for the multiplication rooflines, derived from the unit counts and clock:
 # VALU schoolbook: one v_mad_u64_u32 (16 lanes/clk/SIMD) + one v_addc_co_u32
 # (32 lanes/clk/SIMD) per 32x32-bit product term -> 10.67 terms/clk/SIMD,
 # x 1024 SIMDs x 2.4 GHz.

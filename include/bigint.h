@@ -132,6 +132,24 @@ bi_status bigmul_v(bi_ctx *ctx, const void *a, const void *b, void *out,
                    const bi_desc *desc, uint64_t count, uint32_t limb_bits, int algo, void *stream);
 
 /*
+ * Tuning.  Ragged batches and BI_MUL_AUTO pick a multiplication algorithm per
+ * size class: class k holds instances of (16 << (k-1), 16 << k] 32-bit limbs
+ * (class 0: up to 16), k < BI_NUM_CLASSES.  bi_autotune times every algorithm
+ * on synthetic operands of each class's largest size on the context's device
+ * (and the addition schedules for 2-, 4- and 8-row instances), keeps the
+ * fastest, and copies the per-class choice to algo_out[0 .. n_out) if not
+ * NULL.  It allocates and frees 64 MiB of device memory and synchronises
+ * `stream`.  bi_tune_get / bi_tune_set read or replace the per-class choice
+ * (BI_EALGO if an algorithm cannot run a class's sizes; nothing is changed
+ * then).  Until tuned, a context uses a built-in table.
+ */
+#define BI_NUM_CLASSES 10
+
+bi_status bi_autotune(bi_ctx *ctx, void *stream, int *algo_out, uint32_t n_out);
+bi_status bi_tune_get(const bi_ctx *ctx, int *algo_out, uint32_t n_out);
+bi_status bi_tune_set(bi_ctx *ctx, const int *algo_in, uint32_t n_in);
+
+/*
  * bi_ntt_field -- host-only helper for the prime-field construction of
  * Section 4.1: for an odd prime p = k 2^n + 1 (p < 2^63), returns k, the
  * two-adicity n, and the first a = 2, 3, ... for which g = a^k is a primitive

@@ -25,7 +25,9 @@ STATUS = {0: "BI_OK", -1: "BI_EINVAL", -2: "BI_ESIZE", -3: "BI_ELIMB", -4: "BI_E
           -6: "BI_ENOMEM", -7: "BI_EALGO", -8: "BI_ENODEV"}
 
 EXPORTS = ("bi_ctx_create", "bi_ctx_destroy", "bi_status_str", "bi_last_error",
-           "bigadd", "bigmul", "bigadd_v", "bigmul_v", "bi_ntt_field")
+           "bigadd", "bigmul", "bigadd_v", "bigmul_v", "bi_ntt_field", "bi_autotune", "bi_tune_get",
+           "bi_tune_set")
+NUM_CLASSES = 10
 
 
 class NttFieldInfo(ctypes.Structure):
@@ -66,7 +68,11 @@ def _load():
     L.bigadd_v.argtypes = [P, P, P, P, P, P, U64, U32, P]
     L.bigmul_v.argtypes = [P, P, P, P, P, U64, U32, I, P]
     L.bi_ntt_field.argtypes = [U64, P]
-    for f in (L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field):
+    L.bi_autotune.argtypes = [P, P, P, U32]
+    L.bi_tune_get.argtypes = [P, P, U32]
+    L.bi_tune_set.argtypes = [P, P, U32]
+    for f in (L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field, L.bi_autotune,
+              L.bi_tune_get, L.bi_tune_set):
         f.restype = I
     return L
 
@@ -160,6 +166,25 @@ def bigadd_v(ctx, a, b, out, carry, desc, count, limb_bits, stream=None):
     _check(lib.bigadd_v(_h(ctx), _ptr(a), _ptr(b), _ptr(out), _ptr(carry), _ptr(desc), count, limb_bits,
                         _stream(stream, a)))
     return out
+
+
+def autotune(ctx, stream=None):
+    """Time every algorithm per size class on the device; returns the chosen
+    algorithm per class (list of NUM_CLASSES ints)."""
+    out = (ctypes.c_int * NUM_CLASSES)()
+    _check(lib.bi_autotune(_h(ctx), _stream(stream), out, NUM_CLASSES))
+    return list(out)
+
+
+def tune_get(ctx):
+    out = (ctypes.c_int * NUM_CLASSES)()
+    _check(lib.bi_tune_get(_h(ctx), out, NUM_CLASSES))
+    return list(out)
+
+
+def tune_set(ctx, algos):
+    arr = (ctypes.c_int * len(algos))(*algos)
+    _check(lib.bi_tune_set(_h(ctx), arr, len(algos)))
 
 
 def ntt_field(p: int) -> NttFieldInfo:

@@ -212,4 +212,26 @@ bi_status bigmul_v(bi_ctx *ctx, const void *a, const void *b, void *out, const b
     return bi::dispatch_bigmul_v(ctx->impl, a, b, out, desc, count, limb_bits, algo, static_cast<hipStream_t>(stream));
 }
 
+bi_status bi_autotune(bi_ctx *ctx, void *stream, int *algo_out, uint32_t n_out) {
+    if (!ctx) return fail(BI_EINVAL, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    return bi::autotune(ctx->impl, static_cast<hipStream_t>(stream), algo_out, n_out);
+}
+
+bi_status bi_tune_get(const bi_ctx *ctx, int *algo_out, uint32_t n_out) {
+    if (!ctx || !algo_out) return fail(BI_EINVAL, "NULL argument");
+    for (uint32_t k = 0; k < n_out && k < bi::kNumClasses; ++k) algo_out[k] = ctx->impl.tune.mul_algo[k];
+    return BI_OK;
+}
+
+bi_status bi_tune_set(bi_ctx *ctx, const int *algo_in, uint32_t n_in) {
+    if (!ctx || !algo_in) return fail(BI_EINVAL, "NULL argument");
+    for (uint32_t k = 0; k < n_in && k < bi::kNumClasses; ++k)
+        if (!bi::algo_supports(algo_in[k], bi::class_nmax(k)))
+            return fail(BI_EALGO, "algorithm %d cannot run size class %u", algo_in[k], k);
+    for (uint32_t k = 0; k < n_in && k < bi::kNumClasses; ++k) ctx->impl.tune.mul_algo[k] = algo_in[k];
+    return BI_OK;
+}
+
 }  // extern "C"

@@ -1,0 +1,107 @@
+// On-device autotuning: times every multiplication algorithm on synthetic
+// operands of each ragged size class and keeps the fastest per class (used by
+// BI_MUL_AUTO and bigmul_v), and picks the addition schedule for instances of
+// 2, 3-4 and 5-8 rows.  The paper tunes code-version thresholds the same way
+// (Section 5.1, Futhark's autotuned thresholds); here the choices are the
+// kernel families and their schedules.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "bi_internal.hpp"
+
+namespace bi {
+
+__global__ void fill_hash_kernel(uint32_t *p, uint64_t n, uint32_t seed) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+        uint32_t x = uint32_t(i) ^ seed ^ uint32_t(i >> 32) * 0x9E3779B9u;
+        x ^= x >> 16; x *= 0x7FEB352Du; x ^= x >> 15; x *= 0x846CA68Bu; x ^= x >> 16;
+        p[i] = x;
+    }
+}
+
+namespace {
+
+struct Timer {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    Timer() {
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+    }
+    ~Timer() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
+template <class F>
+bi_status time_us(hipStream_t st, Timer &t, int reps, F &&launch, float *us) {
+    bi_status s = launch();  // warm-up (also first-use attribute set-up)
+    if (s != BI_OK) return s;
+    if (hipEventRecord(t.e0, st) != hipSuccess) return BI_EHIP;
+    for (int r = 0; r < reps; ++r)
+        if ((s = launch()) != BI_OK) return s;
+    if (hipEventRecord(t.e1, st) != hipSuccess || hipEventSynchronize(t.e1) != hipSuccess) return BI_EHIP;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, t.e0, t.e1) != hipSuccess) return BI_EHIP;
+    *us = 1000.0f * ms / reps;
+    return BI_OK;
+}
+
+}  // namespace
+
+bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out) {
+    // Operand space: 2^22 32-bit limbs per operand (16 MiB), products 2x.
+    const uint64_t limbs = uint64_t(1) << 22;
+    uint32_t *buf = nullptr;
+    if (hipMalloc(&buf, 4 * limbs * sizeof(uint32_t)) != hipSuccess) return set_error(BI_ENOMEM, "autotune buffers");
+    uint32_t *a = buf, *b = buf + limbs, *o = buf + 2 * limbs;
+    hipLaunchKernelGGL(fill_hash_kernel, dim3(1024), dim3(256), 0, st, a, 2 * limbs, 0x2405u);
+    Timer tm;
+    bi_status s = BI_OK;
+    const int algos[3] = {BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_MFMA, BI_MUL_NTT};
+    for (uint32_t k = 0; k < kNumClasses && s == BI_OK; ++k) {
+        const uint32_t n = class_nmax(k);
+        uint64_t batch = limbs / n;
+        if (batch > 65536) batch = 65536;
+        float best = 0;
+        int best_algo = c.tune.mul_algo[k];
+        for (int al : algos) {
+            if (!algo_supports(al, n)) continue;
+            float us = 0;
+            s = time_us(st, tm, 3, [&]() { return dispatch_bigmul(c, a, b, o, n, batch, al, st); }, &us);
+            if (s != BI_OK) break;
+            if (best == 0 || us < best) {
+                best = us;
+                best_algo = al;
+            }
+        }
+        c.tune.mul_algo[k] = best_algo;
+    }
+    // Addition: workgroup-cooperative vs one wave per instance, per row class.
+    for (int rc = 0; rc < 3 && s == BI_OK; ++rc) {
+        const uint32_t rows = rc == 0 ? 2 : rc == 1 ? 4 : 8;
+        const uint64_t inst_bytes = uint64_t(rows) * 64 * 16;
+        const uint64_t batch = (limbs * 4) / inst_bytes;
+        float t_coop = 0, t_multi = 0;
+        AddTune t = c.add;
+        for (int multi = 0; multi < 2 && s == BI_OK; ++multi) {
+            if (rc == 0) t.multi2 = multi; else if (rc == 1) t.multi4 = multi; else t.multi8 = multi;
+            float us = 0;
+            s = time_us(st, tm, 5, [&]() {
+                return launch_bigadd(a, b, o, nullptr, inst_bytes, batch, st, t) == hipSuccess ? BI_OK : BI_EHIP;
+            }, &us);
+            (multi ? t_multi : t_coop) = us;
+        }
+        const bool m = s == BI_OK && t_multi < t_coop;
+        if (rc == 0) c.add.multi2 = m; else if (rc == 1) c.add.multi4 = m; else c.add.multi8 = m;
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (s != BI_OK) return s;
+    if (algo_out)
+        for (uint32_t k = 0; k < n_out && k < kNumClasses; ++k) algo_out[k] = c.tune.mul_algo[k];
+    return BI_OK;
+}
+
+}  // namespace bi

@@ -161,6 +161,8 @@ bi_status dispatch_bigadd_v(Ctx &c, const void *a, const void *b, void *out, uin
 bi_status dispatch_bigmul_v(Ctx &c, const void *a, const void *b, void *out, const bi_desc *desc, uint64_t count,
                             uint32_t limb_bits, int algo, hipStream_t st);
 
+bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out);
+
 // Sets the calling thread's bi_last_error() message and returns s.
 bi_status set_error(bi_status s, const char *fmt, ...);
 

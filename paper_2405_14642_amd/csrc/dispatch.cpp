@@ -29,11 +29,17 @@ bi_status ctx_init(Ctx &c, int device, const hipDeviceProp_t &prop) {
     c.device = device;
     default_tune(c.tune);
     c.num_cus = prop.multiProcessorCount;
-    c.add.max_waves = uint64_t(prop.multiProcessorCount) * 256;
+    // Defaults from a sweep on MI355X (u64 limbs, 1 GiB of operands): a large
+    // grid, one wave per instance for 2-4 row instances, workgroup-cooperative
+    // above (bi_autotune re-measures the row classes).
+    c.add.max_waves = uint64_t(prop.multiProcessorCount) * 1024;
+    c.add.multi2 = true;
+    c.add.multi4 = true;
+    c.add.multi8 = false;
     // Experiment override: BI_ADD_TUNE="rows,nt,max_waves,multi_mask"
     // (e.g. "8,1,32768,7"; multi_mask bit 0/1/2 = 2/4/8-row instances).
     if (const char *env = std::getenv("BI_ADD_TUNE")) {
-        int rows = 4, nt = 1, mm = 0;
+        int rows = 4, nt = 1, mm = 3;
         unsigned long long mw = c.add.max_waves;
         if (std::sscanf(env, "%d,%d,%llu,%d", &rows, &nt, &mw, &mm) >= 1) {
             c.add.rows = (rows == 2 || rows == 8) ? rows : 4;

@@ -99,3 +99,11 @@ def test_binding_raises(B):
     with pytest.raises(B.BigIntError) as e:
         B.bigadd(None, FAKE, FAKE, FAKE + 4, n_limbs=4, limb_bits=32, batch=8, stream=0)
     assert e.value.status == -4
+
+
+def test_tuning_validation(B):
+    import ctypes
+    arr = (ctypes.c_int * 10)()
+    assert B.lib.bi_autotune(None, None, arr, 10) == -1
+    assert B.lib.bi_tune_get(None, arr, 10) == -1
+    assert B.lib.bi_tune_set(None, arr, 10) == -1

@@ -201,3 +201,24 @@ def test_ragged_bigmul_v(B, ctx, orc, algo, lb):
         ao, bo, oo = int(a_off[i]), int(b_off[i]), int(out_off[i])
         want = orc.mul(A[ao: ao + n][None], Bv[bo: bo + n][None])[0]
         assert (got[oo: oo + 2 * n] == want).all(), (i, n)
+
+
+def test_autotune_and_auto_dispatch(B, orc):
+    """bi_autotune picks a supported algorithm for every size class, and
+    BI_MUL_AUTO with the tuned table stays bit-exact; bi_tune_set rejects an
+    algorithm that cannot run a class and accepts a valid table."""
+    c = B.Context(0)
+    try:
+        algos = B.autotune(c)
+        assert len(algos) == B.NUM_CLASSES and all(a in (1, 2, 3) for a in algos)
+        assert B.tune_get(c) == algos
+        rng = np.random.default_rng(99)
+        for n in (16, 100, 700, 3000, 8192):
+            a, b = patterned(rng, 3, n)
+            check(orc, a, b, run_mul(B, c, a, b, 0))
+        with pytest.raises(B.BigIntError):
+            B.tune_set(c, [2] * B.NUM_CLASSES)  # MFMA cannot run 8192-limb products
+        B.tune_set(c, [1] * B.NUM_CLASSES)
+        assert B.tune_get(c) == [1] * B.NUM_CLASSES
+    finally:
+        c.close()

@@ -72,6 +72,9 @@ def _get():
         lib.wl_key.restype = ctypes.c_uint64
         lib.wl_hash.argtypes = [ctypes.c_uint64]
         lib.wl_hash.restype = ctypes.c_uint64
+        lib.wl_fill_ragged.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint64,
+                                       ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.wl_fill_ragged.restype = None
         _lib = lib
     return _lib
 
@@ -220,6 +223,51 @@ def stream_sizes(count: int = 100000, seed: int = DEFAULT_SEED):
     h2 = words(seed, CFG_STREAM, 6, 1, pairs=idx)[:, 0]
     ones = (h2 % np.uint64(10)) == 0
     return n, ones
+
+
+def stream_bursts(count: int = 100000, seed: int = DEFAULT_SEED):
+    """Burst sizes: log-uniform integers in [64, 4096] until `count` pairs."""
+    sizes = []
+    total, k = 0, 0
+    while total < count:
+        h = hash64(key_py(seed, CFG_STREAM, k, 5))
+        u = (h >> 11) / float(1 << 53)
+        b = int(round(64 * (4096 / 64) ** u))
+        b = min(b, count - total)
+        sizes.append(b)
+        total += b
+        k += 1
+    return np.array(sizes, dtype=np.int64)
+
+
+def stream_inputs(order: np.ndarray, n: np.ndarray, ones: np.ndarray, seed: int = DEFAULT_SEED):
+    """Ragged u32 operand arrays of the stream's pairs in the order given
+    (a permutation of pair indices): returns (a, b, offsets), pair order[i]
+    at limbs [offsets[i], offsets[i] + n[order[i]])."""
+    order = np.ascontiguousarray(order.astype(np.uint64))
+    nn = n[order.astype(np.int64)].astype(np.uint64)
+    nw = (nn + 1) // 2                        # 64-bit generator words per pair
+    woff = np.zeros(len(order), dtype=np.uint64)
+    woff[1:] = np.cumsum(nw)[:-1]
+    total_w = int(nw.sum())
+    lib = _get()
+    out = []
+    for operand in (0, 1):
+        buf = np.empty(total_w, dtype=np.uint64)
+        lib.wl_fill_ragged(seed & _M64, CFG_STREAM, order.ctypes.data, len(order), operand, nw.ctypes.data,
+                           woff.ctypes.data, buf.ctypes.data)
+        out.append(buf.view(np.uint32))
+    # pack to exactly n limbs per pair (drop the odd padding limb)
+    off = np.zeros(len(order), dtype=np.uint64)
+    off[1:] = np.cumsum(nn)[:-1]
+    total_l = int(nn.sum())
+    idx = np.repeat((2 * woff).astype(np.int64) - off.astype(np.int64), nn.astype(np.int64)) + \
+        np.arange(total_l, dtype=np.int64)
+    a, b = out[0][idx], out[1][idx]
+    mask = np.repeat(ones[order.astype(np.int64)], nn.astype(np.int64))
+    a[mask] = 0xFFFFFFFF
+    b[mask] = 0xFFFFFFFF
+    return a, b, off
 
 
 def stream_pair(i: int, n: int, ones: bool, seed: int = DEFAULT_SEED):

@@ -42,3 +42,15 @@ void wl_fill(uint64_t seed, uint64_t cfg, uint64_t pair0, const uint64_t *pairs,
             dst[j] = sm64(key + j * 0xD1B54A32D192ED03ull);
     }
 }
+
+/* Ragged fill: pair p (index pairs[p]) gets nwords[p] words at out + offsets[p]. */
+void wl_fill_ragged(uint64_t seed, uint64_t cfg, const uint64_t *pairs, uint64_t npairs, uint64_t operand,
+                    const uint64_t *nwords, const uint64_t *offsets, uint64_t *out) {
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < (int64_t)npairs; ++p) {
+        uint64_t key = wl_key(seed, cfg, pairs[p], operand);
+        uint64_t *dst = out + offsets[p];
+        for (uint64_t j = 0; j < nwords[p]; ++j)
+            dst[j] = sm64(key + j * 0xD1B54A32D192ED03ull);
+    }
+}
