@@ -8,7 +8,9 @@ copied to HBM once, and stay resident; the timed region contains only the
 kernels.  Every launch is timed with HIP events on the stream it runs on.
 
 Other workloads (--workload): mulq (quadratic multiplication sizes),
-ntt (NTT-multiplication sizes); each prints its own JSON line.
+ntt (NTT-multiplication sizes), stream (10^5 products of mixed sizes in
+bursts: the stream queue against per-class padded launches, saturated
+throughput and burst latency at 0.8x load); each prints its own JSON line.
 
 Prints one JSON line (rank 0, one GPU):
   value   whole-job additions per second over the step (all five sizes);
@@ -37,7 +39,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="add", choices=["add", "mulq", "ntt"])
+    p.add_argument("--workload", default="add", choices=["add", "mulq", "ntt", "stream"])
+    p.add_argument("--stream-pairs", type=int, default=100000, help="pairs in the mixed-size stream")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU baseline budget")
     p.add_argument("--sizes", default="", help="comma-separated subset of sizes in bits (profiling runs)")
@@ -268,6 +271,171 @@ def bench_mul(args, kind):
     }
 
 
+def bench_stream(args):
+    """Mixed-size stream: 10^5 pairs, n = max(1, round(2^u / 32)) u32 limbs,
+    u ~ U[10, 18], 10 % all-ones, in bursts of log-uniform size in [64, 4096].
+
+    stream path: one bi_stream_submit per burst (descriptor copy + one replay
+    of the captured graph: device binning, one persistent list kernel per size
+    class).  plain path (baseline): per burst, one uniform bigmul launch per
+    size class present, on operands zero-padded to the class's largest size
+    (padding prepared before timing).  Both run back to back (saturated), then
+    replay one seeded Poisson arrival trace whose offered load is 0.8x the
+    plain path's saturated throughput; latency = completion - arrival.
+    """
+    import torch
+
+    import paper_2405_14642_amd as B
+    import workloads as W
+    from tests import gpu_util as G
+
+    count = args.stream_pairs
+    n, ones = W.stream_sizes(count)
+    bursts = W.stream_bursts(count)
+    bstart = np.concatenate([[0], np.cumsum(bursts)[:-1]]).astype(np.int64)
+    a, b, off = W.stream_inputs(np.arange(count), n, ones)
+    nn = n.astype(np.int64)
+    sum_n2 = float((nn.astype(np.float64) ** 2).sum())
+    dA, dB = G.to_dev(a), G.to_dev(b)
+    tot = int(nn.sum())
+    out = torch.zeros(2 * tot, dtype=torch.int32, device="cuda")
+    desc = np.zeros(count, dtype=B.DESC_DTYPE)
+    desc["a_off"], desc["b_off"], desc["out_off"], desc["n_limbs"] = off, off, 2 * off, nn
+    ctx = B.Context(0)
+    tuned = B.autotune(ctx)
+    stream = torch.cuda.current_stream()
+
+    # plain path: padded per-(burst, class) operands, built on the device
+    cls = np.array([0 if x <= 16 else int(np.ceil(np.log2(x))) - 4 for x in nn], dtype=np.int64)
+    off_dev = torch.from_numpy(off.astype(np.int64)).cuda()
+    n_dev = torch.from_numpy(nn).cuda()
+    zero = torch.zeros(1, dtype=torch.int32, device="cuda")
+    flatA = torch.cat([dA.view(torch.int32).reshape(-1), zero])
+    flatB = torch.cat([dB.view(torch.int32).reshape(-1), zero])
+    plain = []  # per burst: list of (Apad, Bpad, Opad, idx)
+    for k in range(len(bursts)):
+        sel = np.arange(bstart[k], bstart[k] + bursts[k])
+        jobs = []
+        for c in np.unique(cls[sel]):
+            idx = sel[cls[sel] == c]
+            nmax = 16 << int(c)
+            it = torch.from_numpy(idx).cuda()
+            j = torch.arange(nmax, device="cuda")
+            gi = off_dev[it][:, None] + j[None, :]
+            valid = j[None, :] < n_dev[it][:, None]
+            gi = torch.where(valid, gi, torch.full_like(gi, tot))
+            jobs.append((flatA[gi].contiguous(), flatB[gi].contiguous(),
+                         torch.empty((len(idx), 2 * nmax), dtype=torch.int32, device="cuda"), idx))
+        plain.append(jobs)
+    torch.cuda.synchronize()
+
+    def run_plain(k):
+        for Ap, Bp, Op, _ in plain[k]:
+            B.bigmul(ctx, Ap, Bp, Op, algo=0, stream=stream.cuda_stream)
+
+    q = B.StreamQueue(ctx, dA, dB, out, 32, max_descs=int(bursts.max()), algo=0, use_graph=True)
+
+    def run_stream(k):
+        q.submit(desc[bstart[k]: bstart[k] + bursts[k]])
+
+    def saturated(run):
+        run(0)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(len(bursts)):
+            run(k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3
+
+    def replay(run, arrivals):
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(bursts))]
+        e0 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        t0 = time.perf_counter()
+        for k in range(len(bursts)):
+            while time.perf_counter() - t0 < arrivals[k]:
+                pass
+            run(k)
+            evs[k].record(stream)
+        torch.cuda.synchronize()
+        lat = np.array([e0.elapsed_time(evs[k]) * 1e-3 - arrivals[k] for k in range(len(bursts))])
+        return lat
+
+    sat = {}
+    for name, run in (("plain", run_plain), ("stream", run_stream)):
+        sat[name] = min(saturated(run) for _ in range(max(1, args.steps // 10 or 1)))
+    thr_plain = count / sat["plain"]
+    rng = np.random.default_rng(W.DEFAULT_SEED & 0xFFFFFFFF)
+    mean_gap = float(bursts.mean()) / (0.8 * thr_plain)
+    arrivals = np.concatenate([[0.0], np.cumsum(rng.exponential(mean_gap, len(bursts) - 1))])
+    res = {}
+    for name, run in (("plain", run_plain), ("stream", run_stream)):
+        lat = replay(run, arrivals)
+        res[name] = {"saturated_s": round(sat[name], 6), "pairs_per_s": count / sat[name],
+                     "sum_n2_per_s": sum_n2 / sat[name],
+                     "latency_p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+                     "latency_p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3)}
+    q.close()
+
+    # spot check: stream results against the plain path and the oracle
+    got = out.cpu().numpy().view(np.uint32)
+    import oracle
+    oracle.build()
+    orc = oracle.get()
+    rs = np.random.default_rng(5)
+    checked = 0
+    for i in rs.choice(count, 64, replace=False):
+        o, m = int(off[i]), int(nn[i])
+        want = orc.mul(a[o: o + m][None], b[o: o + m][None])[0]
+        assert (got[2 * o: 2 * o + 2 * m] == want).all(), ("stream result", int(i))
+        checked += 1
+    for Ap, Bp, Op, idx in plain[len(plain) // 2]:
+        Oh = Op.cpu().numpy().view(np.uint32)
+        for r, i in enumerate(idx[:8]):
+            o, m = int(off[i]), int(nn[i])
+            assert (Oh[r, : 2 * m] == got[2 * o: 2 * o + 2 * m]).all(), ("plain result", int(i))
+    cpu = None if args.no_cpu else cpu_baseline_stream(args, orc, a, b, off, nn)
+    ctx.close()
+    return {
+        "metric": "products/s over a stream of 10^5 mixed-size multiplications (2^10..2^18 bits, u32 limbs, "
+                  "bursts of 64..4096), stream queue, saturated",
+        "value": res["stream"]["pairs_per_s"], "unit": "mults/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(1e3 * sat["stream"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded splitmix64; 10 % all-ones pairs)",
+        "config": {"workload": "stream", "pairs": count, "bursts": len(bursts), "limb_bits": 32,
+                   "sum_n2": sum_n2, "tuned_algorithm_per_class": tuned, "parallelism": "single-gpu"},
+        "stream": res["stream"], "plain_per_class_launches": res["plain"],
+        "speedup_vs_plain": round(sat["plain"] / sat["stream"], 3), "checked_pairs": checked,
+        "roofline": None, "cpu_baseline": cpu,
+    }
+
+
+def cpu_baseline_stream(args, orc, a, b, off, nn):
+    """The oracle over the stream's first pairs, one task per pair, until the
+    time budget is spent."""
+    pairs, macs, secs = 0, 0.0, 0.0
+    i = 0
+    chunk = 256
+    while secs < args.cpu_seconds and i < len(nn):
+        items = []
+        for k in range(i, min(i + chunk, len(nn))):
+            o, m = int(off[k]), int(nn[k])
+            items.append((a[o: o + m], b[o: o + m]))
+        t = time.perf_counter()
+        orc.mul_ragged(items)
+        secs += time.perf_counter() - t
+        pairs += len(items)
+        macs += float(sum(len(x) ** 2 for x, _ in items))
+        i += chunk
+    return {"value": pairs / secs, "unit": "mults/s", "cores": orc.last_threads, "kind": "oracle",
+            "sample": f"first {pairs} pairs of the stream", "u32_macs_per_s": macs / secs,
+            "cpu_model": cpu_info(), "seconds": round(secs, 2)}
+
+
 def cpu_baseline_add(args, W):
     import oracle
     oracle.build()
@@ -302,6 +470,8 @@ def main():
         sys.exit(2)
     if args.workload == "add":
         res = bench_add(args)
+    elif args.workload == "stream":
+        res = bench_stream(args)
     else:
         res = bench_mul(args, args.workload)
     print(json.dumps(res), flush=True)

@@ -150,6 +150,43 @@ bi_status bi_tune_get(const bi_ctx *ctx, int *algo_out, uint32_t n_out);
 bi_status bi_tune_set(bi_ctx *ctx, const int *algo_in, uint32_t n_in);
 
 /*
+ * Stream mode: a queue of ragged multiplication bursts over caller-owned
+ * operand buffers a (a_limbs limbs), b (b_limbs) and out (out_limbs), all of
+ * `limb_bits`-bit limbs, executed in submission order on `stream`.
+ *
+ * bi_stream_open allocates the queue's device descriptor buffer (max_descs
+ * entries), its binning and transform scratch and a few pinned host staging
+ * slots, and (use_graph != 0) captures the launch sequence of one burst --
+ * device-side binning into size classes, then one persistent list kernel per
+ * class that reads its instance count on the device -- into a HIP graph that
+ * every submission replays.  The per-class algorithm is `algo`, or for
+ * BI_MUL_AUTO the context's tuning table at open time.  The queue keeps
+ * pointers to ctx and the buffers; they must outlive it.  BI_ENOMEM / BI_EHIP
+ * on allocation or capture failure (nothing is left allocated then).
+ *
+ * bi_stream_submit copies `count` (1 .. max_descs) HOST descriptors through a
+ * pinned slot to the device and enqueues the burst; it validates every
+ * descriptor first (1 <= n_limbs, n_limbs * limb_bits <= BI_MAX_BITS,
+ * reserved == 0, input ranges inside a and b, output range inside out;
+ * BI_EINVAL / BI_ESIZE and nothing enqueued otherwise).  It blocks only when
+ * all staging slots are still in flight.  *ticket receives the burst's
+ * sequence number.  bi_stream_poll sets *done to 1 once that burst's results
+ * are in `out` (0 while it runs); bi_stream_wait blocks until then.
+ * bi_stream_close waits for every burst and frees the queue.  A queue is not
+ * thread-safe.  Descriptor semantics are those of bigmul_v.  This replaces the
+ * paper's fixed-size batches (Section 6.1) by a stream of mixed sizes.
+ */
+typedef struct bi_stream bi_stream;
+
+bi_status bi_stream_open(bi_ctx *ctx, const void *a, uint64_t a_limbs, const void *b, uint64_t b_limbs,
+                         void *out, uint64_t out_limbs, uint32_t limb_bits, uint64_t max_descs, int algo,
+                         int use_graph, void *stream, bi_stream **q);
+bi_status bi_stream_submit(bi_stream *q, const bi_desc *host_descs, uint64_t count, uint64_t *ticket);
+bi_status bi_stream_poll(bi_stream *q, uint64_t ticket, int *done);
+bi_status bi_stream_wait(bi_stream *q, uint64_t ticket);
+bi_status bi_stream_close(bi_stream *q);
+
+/*
  * bi_ntt_field -- host-only helper for the prime-field construction of
  * Section 4.1: for an odd prime p = k 2^n + 1 (p < 2^63), returns k, the
  * two-adicity n, and the first a = 2, 3, ... for which g = a^k is a primitive

@@ -13,7 +13,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["Context", "BigIntError", "bigadd", "bigmul", "bigadd_v", "bigmul_v", "ntt_field", "lib", "library_path",
+__all__ = ["Context", "BigIntError", "bigadd", "bigmul", "bigadd_v", "bigmul_v", "ntt_field", "StreamQueue",
+           "DESC_DTYPE", "lib", "library_path",
            "MUL_AUTO", "MUL_SCHOOL_VALU", "MUL_SCHOOL_MFMA", "MUL_NTT", "MAX_BITS", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -26,7 +27,8 @@ STATUS = {0: "BI_OK", -1: "BI_EINVAL", -2: "BI_ESIZE", -3: "BI_ELIMB", -4: "BI_E
 
 EXPORTS = ("bi_ctx_create", "bi_ctx_destroy", "bi_status_str", "bi_last_error",
            "bigadd", "bigmul", "bigadd_v", "bigmul_v", "bi_ntt_field", "bi_autotune", "bi_tune_get",
-           "bi_tune_set")
+           "bi_tune_set", "bi_stream_open", "bi_stream_submit", "bi_stream_poll", "bi_stream_wait",
+           "bi_stream_close")
 NUM_CLASSES = 10
 
 
@@ -71,8 +73,14 @@ def _load():
     L.bi_autotune.argtypes = [P, P, P, U32]
     L.bi_tune_get.argtypes = [P, P, U32]
     L.bi_tune_set.argtypes = [P, P, U32]
+    L.bi_stream_open.argtypes = [P, P, U64, P, U64, P, U64, U32, U64, I, I, P, ctypes.POINTER(P)]
+    L.bi_stream_submit.argtypes = [P, P, U64, ctypes.POINTER(U64)]
+    L.bi_stream_poll.argtypes = [P, U64, ctypes.POINTER(I)]
+    L.bi_stream_wait.argtypes = [P, U64]
+    L.bi_stream_close.argtypes = [P]
     for f in (L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field, L.bi_autotune,
-              L.bi_tune_get, L.bi_tune_set):
+              L.bi_tune_get, L.bi_tune_set, L.bi_stream_open, L.bi_stream_submit, L.bi_stream_poll,
+              L.bi_stream_wait, L.bi_stream_close):
         f.restype = I
     return L
 
@@ -198,3 +206,60 @@ def bigmul_v(ctx, a, b, out, desc, count, limb_bits, algo=MUL_AUTO, stream=None)
     _check(lib.bigmul_v(_h(ctx), _ptr(a), _ptr(b), _ptr(out), _ptr(desc), count, limb_bits, int(algo),
                         _stream(stream, a)))
     return out
+
+
+def _desc_dtype():
+    import numpy as np
+    return np.dtype([("a_off", "<u8"), ("b_off", "<u8"), ("out_off", "<u8"), ("n_limbs", "<u4"),
+                     ("reserved", "<u4")])
+
+
+DESC_DTYPE = _desc_dtype()
+
+
+class StreamQueue:
+    """bi_stream: bursts of ragged products over fixed operand buffers.
+
+    ``submit`` takes a host numpy array of DESC_DTYPE records and returns a
+    ticket; ``poll`` / ``wait`` report its completion."""
+
+    def __init__(self, ctx, a, b, out, limb_bits, max_descs, algo=MUL_AUTO, use_graph=True, stream=None):
+        q = ctypes.c_void_p()
+        self._keep = (ctx, a, b, out)
+        _check(lib.bi_stream_open(_h(ctx), _ptr(a), a.numel() * a.element_size() * 8 // limb_bits, _ptr(b),
+                                  b.numel() * b.element_size() * 8 // limb_bits, _ptr(out),
+                                  out.numel() * out.element_size() * 8 // limb_bits, limb_bits, max_descs,
+                                  int(algo), 1 if use_graph else 0, _stream(stream, a), ctypes.byref(q)))
+        self.handle = q.value
+
+    def submit(self, descs) -> int:
+        import numpy as np
+        d = np.ascontiguousarray(descs, dtype=DESC_DTYPE)
+        t = ctypes.c_uint64()
+        _check(lib.bi_stream_submit(self.handle, d.ctypes.data, len(d), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        done = ctypes.c_int()
+        _check(lib.bi_stream_poll(self.handle, ticket, ctypes.byref(done)))
+        return bool(done.value)
+
+    def wait(self, ticket: int):
+        _check(lib.bi_stream_wait(self.handle, ticket))
+
+    def close(self):
+        if self.handle:
+            h, self.handle = self.handle, None
+            _check(lib.bi_stream_close(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -9,11 +9,6 @@
 
 #include "bi_internal.hpp"
 
-struct bi_ctx {
-    int device = 0;
-    bi::Ctx impl;
-};
-
 namespace {
 thread_local char g_err[512] = "";
 }
@@ -64,18 +59,7 @@ bi_status check_ptr(const void *p, uint32_t limb_bits, const char *name) {
     return BI_OK;
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    hipError_t err = hipSuccess;
-    explicit DeviceGuard(int dev) {
-        err = hipGetDevice(&prev);
-        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
-        else prev = -1;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
+using bi::DeviceGuard;
 
 }  // namespace
 

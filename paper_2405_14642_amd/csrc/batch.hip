@@ -19,22 +19,57 @@ __global__ void zero_words_kernel(uint32_t *p, uint32_t n) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
-// counts[c] (pre-zeroed) and lists[c * count + slot]: descriptor indices of
-// class c.  Descriptors with 0 limbs or more than 8192 32-bit limbs are skipped.
-__global__ void bin_kernel(const bi_desc *__restrict__ desc, uint64_t count, uint32_t words_per_limb,
-                           uint32_t *counts, uint32_t *lists) {
+// counts[c] (pre-zeroed) and lists[c * stride + slot]: descriptor indices of
+// class c.  The descriptor count is `count`, or *count_ptr when count_ptr is
+// set (read on the device, clamped to `stride`).  Descriptors with 0 limbs or
+// more than 8192 32-bit limbs are skipped.
+__global__ void bin_kernel(const bi_desc *__restrict__ desc, uint64_t count, const uint64_t *count_ptr,
+                           uint32_t words_per_limb, uint32_t *counts, uint32_t *lists, uint64_t stride) {
+    if (count_ptr) count = min(*count_ptr, stride);
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
          i += uint64_t(gridDim.x) * blockDim.x) {
         const uint32_t n32 = desc[i].n_limbs * words_per_limb;
         if (n32 == 0 || n32 > kMaxLimbs32) continue;
         const uint32_t c = size_class(n32);
         const uint32_t slot = atomicAdd(&counts[c], 1u);
-        lists[uint64_t(c) * count + slot] = uint32_t(i);
+        lists[uint64_t(c) * stride + slot] = uint32_t(i);
     }
 }
 
 size_t batch_scratch_bytes(uint64_t count, int num_cus) {
     return 256 + size_t(kNumClasses) * count * sizeof(uint32_t) + ntt_fused_scratch_bytes(num_cus);
+}
+
+hipError_t launch_bigmul_v_core(const Ctx &c, const Tune &tune, const void *a, const void *b, void *out,
+                                const bi_desc *desc, uint64_t count_max, const uint64_t *count_ptr,
+                                uint32_t limb_bits, int algo, void *scratch, hipStream_t st) {
+    uint32_t *counts = static_cast<uint32_t *>(scratch);
+    uint32_t *lists = reinterpret_cast<uint32_t *>(static_cast<char *>(scratch) + 256);
+    uint32_t *ntt_scr = reinterpret_cast<uint32_t *>(static_cast<char *>(scratch) + 256 +
+                                                     size_t(kNumClasses) * count_max * sizeof(uint32_t));
+    const uint32_t wpl = limb_bits / 32;
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, counts, uint32_t(kNumClasses));
+    const uint64_t bins = (count_max + 255) / 256;
+    hipLaunchKernelGGL(bin_kernel, dim3(uint32_t(bins < 4096 ? bins : 4096)), dim3(256), 0, st, desc, count_max,
+                       count_ptr, wpl, counts, lists, count_max);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    auto A = static_cast<const uint32_t *>(a);
+    auto B = static_cast<const uint32_t *>(b);
+    auto C = static_cast<uint32_t *>(out);
+    for (uint32_t k = 0; k < kNumClasses; ++k) {
+        const uint32_t nmax = class_nmax(k);
+        const ListInst src{A, B, C, desc, lists + uint64_t(k) * count_max, counts + k, wpl};
+        int alg = tune.mul_algo[k];
+        if (algo != BI_MUL_AUTO && algo_supports(algo, nmax)) alg = algo;
+        switch (alg) {
+            case BI_MUL_SCHOOL_MFMA: e = launch_bigmul_mfma_list(src, nmax, count_max, st, c.num_cus); break;
+            case BI_MUL_NTT: e = launch_bigmul_ntt_list(c.ntt.c, src, nmax, count_max, ntt_scr, st, c.num_cus); break;
+            default: e = launch_bigmul_valu_list(src, nmax, count_max, st, c.num_cus); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 bi_status dispatch_bigmul_v(Ctx &c, const void *a, const void *b, void *out, const bi_desc *desc, uint64_t count,
@@ -43,32 +78,8 @@ bi_status dispatch_bigmul_v(Ctx &c, const void *a, const void *b, void *out, con
     void *scr = nullptr;
     bi_status s = ctx_scratch(c, batch_scratch_bytes(count, c.num_cus), st, &scr);
     if (s != BI_OK) return s;
-    uint32_t *counts = static_cast<uint32_t *>(scr);
-    uint32_t *lists = reinterpret_cast<uint32_t *>(static_cast<char *>(scr) + 256);
-    uint32_t *ntt_scr = reinterpret_cast<uint32_t *>(static_cast<char *>(scr) + 256 +
-                                                     size_t(kNumClasses) * count * sizeof(uint32_t));
-    const uint32_t wpl = limb_bits / 32;
-    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, counts, uint32_t(kNumClasses));
-    const uint64_t bins = (count + 255) / 256;
-    hipLaunchKernelGGL(bin_kernel, dim3(uint32_t(bins < 4096 ? bins : 4096)), dim3(256), 0, st, desc, count, wpl,
-                       counts, lists);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return set_error(BI_EHIP, "bigmul_v binning: %s", hipGetErrorString(e));
-    auto A = static_cast<const uint32_t *>(a);
-    auto B = static_cast<const uint32_t *>(b);
-    auto C = static_cast<uint32_t *>(out);
-    for (uint32_t k = 0; k < kNumClasses; ++k) {
-        const uint32_t nmax = class_nmax(k);
-        const ListInst src{A, B, C, desc, lists + uint64_t(k) * count, counts + k, wpl};
-        int alg = c.tune.mul_algo[k];
-        if (algo != BI_MUL_AUTO && algo_supports(algo, nmax)) alg = algo;
-        switch (alg) {
-            case BI_MUL_SCHOOL_MFMA: e = launch_bigmul_mfma_list(src, nmax, count, st); break;
-            case BI_MUL_NTT: e = launch_bigmul_ntt_list(c.ntt.c, src, nmax, count, ntt_scr, st, c.num_cus); break;
-            default: e = launch_bigmul_valu_list(src, nmax, count, st, c.num_cus); break;
-        }
-        if (e != hipSuccess) return set_error(BI_EHIP, "bigmul_v class %u launch: %s", k, hipGetErrorString(e));
-    }
+    hipError_t e = launch_bigmul_v_core(c, c.tune, a, b, out, desc, count, nullptr, limb_bits, algo, scr, st);
+    if (e != hipSuccess) return set_error(BI_EHIP, "bigmul_v launch: %s", hipGetErrorString(e));
     return BI_OK;
 }
 

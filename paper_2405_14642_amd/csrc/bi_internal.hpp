@@ -144,7 +144,8 @@ hipError_t launch_bigmul_ntt(const NttConst &k, const uint32_t *a, const uint32_
 // on the device).
 hipError_t launch_bigmul_valu_list(const ListInst &src, uint32_t nmax, uint64_t count_max, hipStream_t st,
                                    int num_cus);
-hipError_t launch_bigmul_mfma_list(const ListInst &src, uint32_t nmax, uint64_t count_max, hipStream_t st);
+hipError_t launch_bigmul_mfma_list(const ListInst &src, uint32_t nmax, uint64_t count_max, hipStream_t st,
+                                   int num_cus);
 hipError_t launch_bigmul_ntt_list(const NttConst &K, const ListInst &src, uint32_t nmax, uint64_t count_max,
                                   uint32_t *scratch, hipStream_t st, int num_cus);
 size_t ntt_fused_scratch_bytes(int num_cus);
@@ -152,12 +153,20 @@ size_t ntt_fused_scratch_bytes(int num_cus);
 // int8-MFMA schoolbook for up to mfma_max_limbs() 32-bit limbs.
 uint32_t mfma_max_limbs();
 hipError_t launch_bigmul_mfma(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
-                              hipStream_t st);
+                              hipStream_t st, int num_cus);
 
 bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint32_t n32, uint64_t batch, int algo,
                           hipStream_t st);
 bi_status dispatch_bigadd_v(Ctx &c, const void *a, const void *b, void *out, uint8_t *carry, const bi_desc *desc,
                             uint64_t count, uint32_t limb_bits, hipStream_t st);
+// Ragged multiplication core: binning plus one list launch per size class.
+// `scratch` holds batch_scratch_bytes(count_max) bytes; the descriptor count
+// is count_max, or read on the device from *count_ptr when it is set (so the
+// launch sequence can be captured once and replayed with other counts).
+size_t batch_scratch_bytes(uint64_t count, int num_cus);
+hipError_t launch_bigmul_v_core(const Ctx &c, const Tune &tune, const void *a, const void *b, void *out,
+                                const bi_desc *desc, uint64_t count_max, const uint64_t *count_ptr,
+                                uint32_t limb_bits, int algo, void *scratch, hipStream_t st);
 bi_status dispatch_bigmul_v(Ctx &c, const void *a, const void *b, void *out, const bi_desc *desc, uint64_t count,
                             uint32_t limb_bits, int algo, hipStream_t st);
 
@@ -167,3 +176,26 @@ bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out);
 bi_status set_error(bi_status s, const char *fmt, ...);
 
 }  // namespace bi
+
+namespace bi {
+// Makes `dev` the current device for the scope of a call, restoring the
+// caller's device afterwards.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev) {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+}  // namespace bi
+
+// The opaque context handle of the C ABI.
+struct bi_ctx {
+    int device = 0;
+    bi::Ctx impl;
+};

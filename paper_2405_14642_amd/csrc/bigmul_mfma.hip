@@ -34,6 +34,8 @@
 // lies above the product.  L + H is added with the workgroup ballot-adder, as
 // for the other products (Section 3.1 combines its low and high parts the
 // same way).
+#include <atomic>
+
 #include "bi_common.hpp"
 #include "bi_internal.hpp"
 #include "bi_wgadd.hpp"
@@ -45,7 +47,7 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr uint32_t kPA = 40;     // zero bytes before the digits of a in copy 0
+constexpr uint32_t kPA = 48;     // zero bytes before the digits of a in copy 0
 constexpr uint32_t kBPad = 32;   // zero B entries before block 0
 constexpr uint32_t kBTail = 31;  // zero B entries after the last block
 constexpr uint32_t kR8 = 0x80808080u;
@@ -59,10 +61,10 @@ __host__ __device__ inline MfmaLayout mfma_layout(uint32_t n32p) {
     MfmaLayout l;
     l.D = 4 * n32p;
     l.nb = l.D / 32;
-    // Copy stride: the MFMA loop reads copy bytes below kPA + D + 64 and the
-    // last 16-byte chunk of a copy is never built, so the stride is at least
-    // kPA + D + 80; = 32 mod 128 spreads the 8 copies over the LDS banks.
-    l.CSA = ((kPA + l.D + 48 + 127) / 128) * 128 + 32;
+    // Copy stride: the MFMA loop reads copy bytes below kPA + D + 64, so the
+    // stride is at least kPA + D + 64; = 32 mod 128 spreads the 8 copies over
+    // the LDS banks.
+    l.CSA = ((kPA + l.D + 32 + 127) / 128) * 128 + 32;
     l.NBE = kBPad + l.nb + kBTail;
     l.bpl = 8 * l.CSA;
     l.sum = l.bpl + 2 * 16 * l.NBE;
@@ -101,6 +103,78 @@ __device__ __forceinline__ void load4(const uint32_t *p, uint32_t n, uint32_t c,
 // Byte i of w as a signed digit.
 __device__ __forceinline__ int32_t sbyte(uint32_t w, uint32_t i) { return int32_t(w << (24 - 8 * i)) >> 24; }
 
+// Operand words of one 16-byte chunk per lane: chunk c = 64 w + lane of wave
+// w, plus for a the first two words of chunk c + 1 (zero beyond n words).
+struct Chunks {
+    uint32_t a[6];
+    uint32_t b[4];
+};
+
+__device__ __forceinline__ void fetch_chunks(const InstRef &in, uint32_t c, Chunks &x) {
+    const uint32_t n = in.n, base = 4 * c;
+    load4(in.a, n, c, *reinterpret_cast<uint32_t(*)[4]>(x.a));
+    x.a[4] = base + 4 < n ? in.a[base + 4] : 0u;
+    x.a[5] = base + 5 < n ? in.a[base + 5] : 0u;
+    load4(in.b, n, c, x.b);
+}
+
+// Balanced digits of both operands in one carry scan per operand (nchunks <=
+// 64 NW, one chunk per lane).  On return x.a[0..3] / x.b[0..3] hold the digit
+// words of (A + R) ^ R, x.a[4..5] the first digit words of chunk c + 1 (zero
+// past the last chunk), and t[0], t[1] the carries t_A, t_B.
+template <int NW>
+__device__ __forceinline__ void recode_chunks(Chunks &x, uint32_t nchunks, uint32_t *summary, uint32_t (&t)[2]) {
+    const uint32_t lane = lane_id(), w = wave_in_block();
+    const uint32_t c = 64 * w + lane;
+    const uint32_t valid = nchunks > 64 * w ? min(nchunks - 64 * w, 64u) : 0u;
+    const uint64_t vmask = valid >= 64 ? ~0ull : ((1ull << valid) - 1);
+    const uint32_t R[4] = {kR8, kR8, kR8, kR8};
+    uint32_t sa[4], sb[4];
+    const uint32_t ga = add_words<4>(*reinterpret_cast<const uint32_t(*)[4]>(x.a), R, sa);
+    const uint32_t gb = add_words<4>(x.b, R, sb);
+    const uint64_t Ga = ballot(ga != 0), Pa = ballot(c < nchunks && all_ones<4>(sa));
+    const uint64_t Gb = ballot(gb != 0), Pb = ballot(c < nchunks && all_ones<4>(sb));
+    {
+        const WaveCarry ca = wave_carry(Ga, Pa, 0), cb = wave_carry(Gb, Pb, 0);
+        const uint32_t oa = valid >= 64 ? ca.out : uint32_t(ca.into >> valid) & 1u;
+        const uint32_t ob = valid >= 64 ? cb.out : uint32_t(cb.into >> valid) & 1u;
+        if (lane == 0) {
+            summary[w] = oa | ((Pa == vmask ? 1u : 0u) << 1);
+            summary[4 + w] = ob | ((Pb == vmask ? 1u : 0u) << 1);
+        }
+    }
+    __syncthreads();
+    uint32_t cina = 0, cinb = 0, ta = 0, tb = 0;
+#pragma unroll
+    for (uint32_t v = 0; v < uint32_t(NW); ++v) {
+        const uint32_t sva = summary[v], svb = summary[4 + v];
+        if (v < w) {
+            cina = (sva & 1u) | ((sva >> 1) & cina);
+            cinb = (svb & 1u) | ((svb >> 1) & cinb);
+        }
+        ta = (sva & 1u) | ((sva >> 1) & ta);
+        tb = (svb & 1u) | ((svb >> 1) & tb);
+    }
+    t[0] = ta;
+    t[1] = tb;
+    const WaveCarry ca = wave_carry(Ga, Pa, cina), cb = wave_carry(Gb, Pb, cinb);
+    // carry into chunk c + 1 (lane 63: out of the row)
+    const uint32_t cnext = lane < 63 ? uint32_t(ca.into >> (lane + 1)) & 1u : ca.out;
+    add_carry_words<4>(sa, uint32_t(ca.into >> lane) & 1u);
+    add_carry_words<4>(sb, uint32_t(cb.into >> lane) & 1u);
+    uint32_t co;
+    const uint32_t n0 = __builtin_addc(x.a[4], kR8, cnext, &co);
+    const uint32_t n1 = __builtin_addc(x.a[5], kR8, co, &co);
+    const bool last = c + 1 >= nchunks;
+    x.a[4] = last ? 0u : n0 ^ kR8;
+    x.a[5] = last ? 0u : n1 ^ kR8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        x.a[i] = sa[i] ^ kR8;
+        x.b[i] = sb[i] ^ kR8;
+    }
+}
+
 }  // namespace
 
 template <int NW, class Src>
@@ -110,6 +184,9 @@ __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
     constexpr uint32_t T = 64 * NW;
     const uint64_t count = src.count();
 
+    Chunks x;
+    if (uint64_t(blockIdx.x) < count) fetch_chunks(src.get(blockIdx.x), 64 * wave + lane, x);
+
     for (uint64_t pair = blockIdx.x; pair < count; pair += gridDim.x) {
         const InstRef in = src.get(pair);
         const uint32_t n32 = in.n, n32p = (n32 + 7) & ~7u;
@@ -117,37 +194,60 @@ __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
         const uint32_t D = lo.D, nb = lo.nb, CSA = lo.CSA, NBE = lo.NBE;
         uint8_t *bpl = lds + lo.bpl;
         uint32_t *summary = reinterpret_cast<uint32_t *>(lds + lo.sum);
+        const uint32_t nchunks = n32p / 4;
 
-        // 1. balanced digits: a in natural order into copy 0, b group-reversed
-        //    into the two B planes; zero the pads around both.
-        const uint32_t *a = in.a, *b = in.b;
-        auto src_a = [&](uint32_t c, uint32_t (&x)[4], uint32_t (&y)[4]) {
-            load4(a, n32, c, x);
-            y[0] = y[1] = y[2] = y[3] = kR8;
-        };
-        auto sink_a = [&](uint32_t c, const uint32_t (&s)[4]) {
-            uint64_t *p = reinterpret_cast<uint64_t *>(lds + kPA + 16 * c);
-            p[0] = uint64_t(s[0] ^ kR8) | (uint64_t(s[1] ^ kR8) << 32);
-            p[1] = uint64_t(s[2] ^ kR8) | (uint64_t(s[3] ^ kR8) << 32);
-        };
-        const uint32_t tA = wg_add_rows_sink<NW>(src_a, sink_a, n32p, summary);
-        auto src_b = [&](uint32_t c, uint32_t (&x)[4], uint32_t (&y)[4]) {
-            load4(b, n32, c, x);
-            y[0] = y[1] = y[2] = y[3] = kR8;
-        };
-        auto sink_b = [&](uint32_t c, const uint32_t (&s)[4]) {
-            uint4 v;
-            v.x = __builtin_bswap32(s[3] ^ kR8);
-            v.y = __builtin_bswap32(s[2] ^ kR8);
-            v.z = __builtin_bswap32(s[1] ^ kR8);
-            v.w = __builtin_bswap32(s[0] ^ kR8);
-            *reinterpret_cast<uint4 *>(bpl + (c & 1u) * 16 * NBE + 16 * (kBPad + (c >> 1))) = v;
-        };
-        const uint32_t tB = wg_add_rows_sink<NW>(src_b, sink_b, n32p, summary + 4);
+        // 1. balanced digits, written as the 8 byte-shifted copies of a
+        //    (copy k byte y = digit y + k - kPA) and the group-reversed
+        //    B planes; zero the pads around both.
+        uint32_t tAB[2];
+        recode_chunks<NW>(x, nchunks, summary, tAB);
+        const uint32_t tA = tAB[0], tB = tAB[1];
         {
-            uint64_t *a0 = reinterpret_cast<uint64_t *>(lds);
-            const uint32_t z0 = kPA / 8, z1 = (kPA + D) / 8, z2 = CSA / 8;
-            for (uint32_t i = tid; i < z0 + (z2 - z1); i += T) a0[i < z0 ? i : z1 + (i - z0)] = 0;
+            const uint32_t c = 64 * wave + lane;
+            if (c < nchunks) {
+                const uint32_t q = kPA / 16 + c;
+                const uint32_t *d = x.a;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const uint32_t o = uint32_t(k) >> 2, sh = uint32_t(k) & 3u;
+                    uint4 v;
+                    v.x = __builtin_amdgcn_alignbyte(d[o + 1], d[o + 0], sh);
+                    v.y = __builtin_amdgcn_alignbyte(d[o + 2], d[o + 1], sh);
+                    v.z = __builtin_amdgcn_alignbyte(d[o + 3], d[o + 2], sh);
+                    v.w = __builtin_amdgcn_alignbyte(o + 4 < 6 ? d[o + 4] : 0u, d[o + 3], sh);
+                    *reinterpret_cast<uint4 *>(lds + k * CSA + 16 * q) = v;
+                }
+                if (c == 0) {  // the chunk before the digits: zeros, then the first digits
+#pragma unroll
+                    for (int k = 1; k < 8; ++k) {
+                        const uint32_t z[6] = {0u, 0u, 0u, 0u, d[0], d[1]};
+                        const uint32_t o = uint32_t(k) >> 2, sh = uint32_t(k) & 3u;
+                        uint4 v;
+                        v.x = __builtin_amdgcn_alignbyte(z[o + 1], z[o + 0], sh);
+                        v.y = __builtin_amdgcn_alignbyte(z[o + 2], z[o + 1], sh);
+                        v.z = __builtin_amdgcn_alignbyte(z[o + 3], z[o + 2], sh);
+                        v.w = __builtin_amdgcn_alignbyte(z[o + 4], z[o + 3], sh);
+                        *reinterpret_cast<uint4 *>(lds + k * CSA + 16 * (q - 1)) = v;
+                    }
+                }
+                uint4 v;
+                v.x = __builtin_bswap32(x.b[3]);
+                v.y = __builtin_bswap32(x.b[2]);
+                v.z = __builtin_bswap32(x.b[1]);
+                v.w = __builtin_bswap32(x.b[0]);
+                *reinterpret_cast<uint4 *>(bpl + (c & 1u) * 16 * NBE + 16 * (kBPad + (c >> 1))) = v;
+            }
+            // zero chunks: copy 0 below the digits, every copy from kPA + D to
+            // its read limit, and the B pads
+            const uint32_t zlo = kPA / 16, zhi = (CSA - kPA - D) / 16;
+            const uint32_t nz0 = zlo + 7 * (zlo - 1), nza = nz0 + 8 * zhi;
+            for (uint32_t i = tid; i < nza; i += T) {
+                uint32_t k, qq;
+                if (i < zlo) { k = 0; qq = i; }
+                else if (i < nz0) { k = 1 + (i - zlo) / (zlo - 1); qq = (i - zlo) % (zlo - 1); }
+                else { k = (i - nz0) / zhi; qq = (kPA + D) / 16 + (i - nz0) % zhi; }
+                *reinterpret_cast<uint4 *>(lds + k * CSA + 16 * qq) = make_uint4(0, 0, 0, 0);
+            }
             const uint32_t nz = kBPad + kBTail;
             for (uint32_t i = tid; i < 2 * nz; i += T) {
                 const uint32_t pl = i / nz, e = i - pl * nz;
@@ -157,25 +257,8 @@ __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
         }
         __syncthreads();
 
-        // 2. copies 1..7: copy c byte y = copy 0 byte y + c
-        {
-            const uint32_t nq = CSA / 16 - 1;
-            for (uint32_t c = 1; c < 8; ++c) {
-                for (uint32_t q = tid; q < nq; q += T) {
-                    const uint4 x0 = *reinterpret_cast<const uint4 *>(lds + 16 * q);
-                    const uint4 x1 = *reinterpret_cast<const uint4 *>(lds + 16 * q + 16);
-                    const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-                    const uint32_t o = c >> 2, sh = c & 3u;
-                    uint4 v;
-                    v.x = __builtin_amdgcn_alignbyte(w[o + 1], w[o + 0], sh);
-                    v.y = __builtin_amdgcn_alignbyte(w[o + 2], w[o + 1], sh);
-                    v.z = __builtin_amdgcn_alignbyte(w[o + 3], w[o + 2], sh);
-                    v.w = __builtin_amdgcn_alignbyte(w[o + 4], w[o + 3], sh);
-                    *reinterpret_cast<uint4 *>(lds + c * CSA + 16 * q) = v;
-                }
-            }
-        }
-        __syncthreads();
+        // next pair's operands, in flight during the products
+        if (pair + gridDim.x < count) fetch_chunks(src.get(pair + gridDim.x), 64 * wave + lane, x);
 
         // 3. MFMA: this wave's supertiles wave and wave + h
         const uint32_t nst = (n32p + 127) / 128, h = (nst + 1) / 2;
@@ -266,39 +349,48 @@ static uint32_t mfma_waves(uint32_t nmax) {
 }
 
 template <int NW, class Src>
-static hipError_t launch_nw(const Src &src, uint32_t nmax, uint64_t count, hipStream_t st) {
+static hipError_t launch_nw(const Src &src, uint32_t nmax, uint64_t count, hipStream_t st, int num_cus) {
     const MfmaLayout lo = mfma_layout((nmax + 7) & ~7u);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&bigmul_mfma_kernel<NW, Src>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    const void *fn = reinterpret_cast<const void *>(&bigmul_mfma_kernel<NW, Src>);
+    // (LDS bytes << 32 | resident workgroups per CU) of the last launch shape
+    static std::atomic<uint64_t> occ{0};
+    uint64_t o = occ.load(std::memory_order_relaxed);
+    if ((o >> 32) != lo.total) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
-        attr = true;
+        int nblk = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, fn, 64 * NW, lo.total);
+        if (e != hipSuccess) return e;
+        o = (uint64_t(lo.total) << 32) | uint32_t(nblk < 1 ? 1 : nblk);
+        occ.store(o, std::memory_order_relaxed);
     }
-    const uint32_t grid = uint32_t(count < 65536 ? count : 65536);
+    // persistent workgroups: each loops over pairs, prefetching the next
+    const uint64_t cap = uint64_t(uint32_t(o)) * uint64_t(num_cus > 0 ? num_cus : 1);
+    const uint32_t grid = uint32_t(count < cap ? count : cap);
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL((bigmul_mfma_kernel<NW, Src>), dim3(grid), dim3(64 * NW), lo.total, st, src);
     return hipGetLastError();
 }
 
 template <class Src>
-static hipError_t launch_mfma(const Src &src, uint32_t nmax, uint64_t count, hipStream_t st) {
+static hipError_t launch_mfma(const Src &src, uint32_t nmax, uint64_t count, hipStream_t st, int num_cus) {
     if (nmax > mfma_max_limbs()) return hipErrorInvalidValue;
     switch (mfma_waves(nmax)) {
-        case 1: return launch_nw<1>(src, nmax, count, st);
-        case 2: return launch_nw<2>(src, nmax, count, st);
-        default: return launch_nw<4>(src, nmax, count, st);
+        case 1: return launch_nw<1>(src, nmax, count, st, num_cus);
+        case 2: return launch_nw<2>(src, nmax, count, st, num_cus);
+        default: return launch_nw<4>(src, nmax, count, st, num_cus);
     }
 }
 
 hipError_t launch_bigmul_mfma(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
-                              hipStream_t st) {
+                              hipStream_t st, int num_cus) {
     if (batch == 0) return hipSuccess;
-    return launch_mfma(UniformInst{a, b, c, n32, batch}, n32, batch, st);
+    return launch_mfma(UniformInst{a, b, c, n32, batch}, n32, batch, st, num_cus);
 }
 
-hipError_t launch_bigmul_mfma_list(const ListInst &src, uint32_t nmax, uint64_t count_max, hipStream_t st) {
-    return launch_mfma(src, nmax, count_max, st);
+hipError_t launch_bigmul_mfma_list(const ListInst &src, uint32_t nmax, uint64_t count_max, hipStream_t st,
+                                   int num_cus) {
+    return launch_mfma(src, nmax, count_max, st, num_cus);
 }
 
 }  // namespace bi

@@ -108,7 +108,7 @@ bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint3
             if (n32 > mfma_max_limbs())
                 return set_error(BI_EALGO, "the int8-MFMA schoolbook supports up to %u 32-bit limbs", mfma_max_limbs());
             e = launch_bigmul_mfma(static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
-                                   static_cast<uint32_t *>(out), n32, batch, st);
+                                   static_cast<uint32_t *>(out), n32, batch, st, c.num_cus);
             break;
         case BI_MUL_NTT: {
             if (ntt_log_len(n32) == 0) return set_error(BI_EALGO, "NTT supports up to %u limbs", kNttLmax / 4);

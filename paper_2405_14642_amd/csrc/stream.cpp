@@ -1,0 +1,226 @@
+// Stream mode (bi_stream_*): a queue of ragged multiplication bursts.
+//
+// Every burst runs the ragged path (device-side binning into size classes,
+// then one persistent list kernel per class, each reading its instance count
+// on the device), so the launch sequence does not depend on the burst: it is
+// captured once into a HIP graph and each submission is one descriptor copy
+// plus one graph launch.  Descriptors pass through pinned staging slots; a
+// slot is reused only after the event of its previous burst has completed.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+
+#include "bi_internal.hpp"
+
+namespace {
+
+constexpr int kSlots = 4;
+constexpr size_t kHeader = 256;  // device buffer: count (u64) at 0, descriptors from 256
+
+struct Slot {
+    void *host = nullptr;  // pinned: header + descriptors
+    hipEvent_t done = nullptr;
+    uint64_t ticket = ~0ull;
+};
+
+}  // namespace
+
+struct bi_stream {
+    bi_ctx *ctx = nullptr;
+    const void *a = nullptr, *b = nullptr;
+    void *out = nullptr;
+    uint64_t a_limbs = 0, b_limbs = 0, out_limbs = 0;
+    uint32_t limb_bits = 32;
+    uint64_t max_descs = 0;
+    int algo = BI_MUL_AUTO;
+    bi::Tune tune{};
+    hipStream_t st = nullptr;
+    void *dev = nullptr;      // header + descriptors
+    void *scratch = nullptr;  // binning lists and transform scratch
+    Slot slots[kSlots];
+    uint64_t next = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void release(bi_stream *q) {
+    for (Slot &s : q->slots) {
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.host) (void)hipHostFree(s.host);
+    }
+    if (q->exec) (void)hipGraphExecDestroy(q->exec);
+    if (q->graph) (void)hipGraphDestroy(q->graph);
+    if (q->scratch) (void)hipFree(q->scratch);
+    if (q->dev) (void)hipFree(q->dev);
+    delete q;
+}
+
+hipError_t launch_burst(bi_stream *q, hipStream_t st) {
+    const bi_desc *d = reinterpret_cast<const bi_desc *>(static_cast<char *>(q->dev) + kHeader);
+    const uint64_t *cnt = static_cast<const uint64_t *>(q->dev);
+    return bi::launch_bigmul_v_core(q->ctx->impl, q->tune, q->a, q->b, q->out, d, q->max_descs, cnt, q->limb_bits,
+                                    q->algo, q->scratch, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+bi_status bi_stream_open(bi_ctx *ctx, const void *a, uint64_t a_limbs, const void *b, uint64_t b_limbs, void *out,
+                         uint64_t out_limbs, uint32_t limb_bits, uint64_t max_descs, int algo, int use_graph,
+                         void *stream, bi_stream **qout) {
+    using bi::set_error;
+    if (!qout) return set_error(BI_EINVAL, "q is NULL");
+    *qout = nullptr;
+    if (!ctx) return set_error(BI_EINVAL, "ctx is NULL");
+    if (limb_bits != 32 && limb_bits != 64) return set_error(BI_ELIMB, "limb_bits must be 32 or 64 (got %u)", limb_bits);
+    if (!a || !b || !out) return set_error(BI_EINVAL, "operand or output buffer is NULL");
+    const uintptr_t al = limb_bits / 8;
+    if (reinterpret_cast<uintptr_t>(a) % al || reinterpret_cast<uintptr_t>(b) % al ||
+        reinterpret_cast<uintptr_t>(out) % al)
+        return set_error(BI_ELIMB, "buffers must be aligned to %u-bit limbs", limb_bits);
+    if (max_descs == 0 || max_descs > (uint64_t(1) << 24))
+        return set_error(BI_ESIZE, "max_descs must be in [1, 2^24] (got %llu)", (unsigned long long)max_descs);
+    if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT) return set_error(BI_EINVAL, "unknown algorithm %d", algo);
+    bi::DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return set_error(BI_EHIP, "hipSetDevice: %s", hipGetErrorString(g.err));
+
+    bi_stream *q = new (std::nothrow) bi_stream;
+    if (!q) return set_error(BI_ENOMEM, "queue allocation failed");
+    q->ctx = ctx;
+    q->a = a; q->b = b; q->out = out;
+    q->a_limbs = a_limbs; q->b_limbs = b_limbs; q->out_limbs = out_limbs;
+    q->limb_bits = limb_bits;
+    q->max_descs = max_descs;
+    q->algo = algo;
+    q->tune = ctx->impl.tune;
+    q->st = static_cast<hipStream_t>(stream);
+    const size_t dbytes = kHeader + max_descs * sizeof(bi_desc);
+    if (hipMalloc(&q->dev, dbytes) != hipSuccess ||
+        hipMalloc(&q->scratch, bi::batch_scratch_bytes(max_descs, ctx->impl.num_cus)) != hipSuccess) {
+        release(q);
+        return set_error(BI_ENOMEM, "queue device buffers");
+    }
+    for (Slot &s : q->slots) {
+        if (hipHostMalloc(&s.host, dbytes, hipHostMallocDefault) != hipSuccess) {
+            release(q);
+            return set_error(BI_ENOMEM, "pinned staging");
+        }
+        if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+            release(q);
+            return set_error(BI_EHIP, "event creation");
+        }
+    }
+    // One empty burst outside capture: sets up the launchers' per-kernel
+    // attributes, and leaves a valid count (0) on the device.
+    hipError_t e = hipMemsetAsync(q->dev, 0, kHeader, q->st);
+    if (e == hipSuccess) e = launch_burst(q, q->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(q->st);
+    if (e != hipSuccess) {
+        release(q);
+        return set_error(BI_EHIP, "queue set-up: %s", hipGetErrorString(e));
+    }
+    if (use_graph) {
+        hipStream_t cap = nullptr;
+        e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+            const hipError_t le = launch_burst(q, cap);
+            e = hipStreamEndCapture(cap, &q->graph);
+            if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&q->exec, q->graph, nullptr, nullptr, 0);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (e != hipSuccess) {
+            release(q);
+            return set_error(BI_EHIP, "graph capture: %s", hipGetErrorString(e));
+        }
+    }
+    *qout = q;
+    return BI_OK;
+}
+
+bi_status bi_stream_submit(bi_stream *q, const bi_desc *descs, uint64_t count, uint64_t *ticket) {
+    using bi::set_error;
+    if (!q || !descs || !ticket) return set_error(BI_EINVAL, "NULL argument");
+    if (count == 0 || count > q->max_descs)
+        return set_error(BI_ESIZE, "count must be in [1, %llu] (got %llu)", (unsigned long long)q->max_descs,
+                         (unsigned long long)count);
+    const uint64_t maxn = BI_MAX_BITS / q->limb_bits;
+    for (uint64_t i = 0; i < count; ++i) {
+        const bi_desc &d = descs[i];
+        if (d.reserved != 0) return set_error(BI_EINVAL, "descriptor %llu: reserved is not 0", (unsigned long long)i);
+        if (d.n_limbs == 0 || d.n_limbs > maxn)
+            return set_error(BI_ESIZE, "descriptor %llu: n_limbs %u outside [1, %llu]", (unsigned long long)i,
+                             d.n_limbs, (unsigned long long)maxn);
+        const uint64_t n = d.n_limbs;
+        if (d.a_off > q->a_limbs || q->a_limbs - d.a_off < n || d.b_off > q->b_limbs || q->b_limbs - d.b_off < n ||
+            d.out_off > q->out_limbs || q->out_limbs - d.out_off < 2 * n)
+            return set_error(BI_EINVAL, "descriptor %llu: range outside its buffer", (unsigned long long)i);
+    }
+    bi::DeviceGuard g(q->ctx->device);
+    if (g.err != hipSuccess) return set_error(BI_EHIP, "hipSetDevice: %s", hipGetErrorString(g.err));
+    const uint64_t t = q->next;
+    Slot &s = q->slots[t % kSlots];
+    if (s.ticket != ~0ull) {
+        const hipError_t e = hipEventSynchronize(s.done);
+        if (e != hipSuccess) return set_error(BI_EHIP, "staging slot wait: %s", hipGetErrorString(e));
+    }
+    std::memset(s.host, 0, kHeader);
+    std::memcpy(s.host, &count, sizeof count);
+    std::memcpy(static_cast<char *>(s.host) + kHeader, descs, count * sizeof(bi_desc));
+    hipError_t e = hipMemcpyAsync(q->dev, s.host, kHeader + count * sizeof(bi_desc), hipMemcpyHostToDevice, q->st);
+    if (e == hipSuccess) e = q->exec ? hipGraphLaunch(q->exec, q->st) : launch_burst(q, q->st);
+    if (e == hipSuccess) e = hipEventRecord(s.done, q->st);
+    if (e != hipSuccess) return set_error(BI_EHIP, "burst launch: %s", hipGetErrorString(e));
+    s.ticket = t;
+    q->next = t + 1;
+    *ticket = t;
+    return BI_OK;
+}
+
+bi_status bi_stream_poll(bi_stream *q, uint64_t ticket, int *done) {
+    using bi::set_error;
+    if (!q || !done) return set_error(BI_EINVAL, "NULL argument");
+    if (ticket >= q->next) return set_error(BI_EINVAL, "ticket %llu was not issued", (unsigned long long)ticket);
+    const Slot &s = q->slots[ticket % kSlots];
+    if (s.ticket != ticket) {  // the slot was reused, which waited for this burst
+        *done = 1;
+        return BI_OK;
+    }
+    const hipError_t e = hipEventQuery(s.done);
+    if (e == hipSuccess) { *done = 1; return BI_OK; }
+    if (e == hipErrorNotReady) { *done = 0; return BI_OK; }
+    return set_error(BI_EHIP, "poll: %s", hipGetErrorString(e));
+}
+
+bi_status bi_stream_wait(bi_stream *q, uint64_t ticket) {
+    using bi::set_error;
+    if (!q) return set_error(BI_EINVAL, "q is NULL");
+    if (ticket >= q->next) return set_error(BI_EINVAL, "ticket %llu was not issued", (unsigned long long)ticket);
+    const Slot &s = q->slots[ticket % kSlots];
+    if (s.ticket != ticket) return BI_OK;
+    const hipError_t e = hipEventSynchronize(s.done);
+    if (e != hipSuccess) return set_error(BI_EHIP, "wait: %s", hipGetErrorString(e));
+    return BI_OK;
+}
+
+bi_status bi_stream_close(bi_stream *q) {
+    if (!q) return BI_OK;
+    bi::DeviceGuard g(q->ctx->device);
+    hipError_t first = g.err;
+    for (Slot &s : q->slots) {
+        if (s.ticket != ~0ull) {
+            const hipError_t e = hipEventSynchronize(s.done);
+            if (first == hipSuccess) first = e;
+        }
+    }
+    release(q);
+    if (first != hipSuccess) return bi::set_error(BI_EHIP, "close: %s", hipGetErrorString(first));
+    return BI_OK;
+}
+
+}  // extern "C"

@@ -107,3 +107,18 @@ def test_tuning_validation(B):
     assert B.lib.bi_autotune(None, None, arr, 10) == -1
     assert B.lib.bi_tune_get(None, arr, 10) == -1
     assert B.lib.bi_tune_set(None, arr, 10) == -1
+
+
+def test_stream_validation_host(B):
+    """Stream-mode argument checks that return before any HIP call."""
+    import ctypes
+    q = ctypes.c_void_p()
+    X = 4096
+    assert B.lib.bi_stream_open(None, X, 1, X, 1, X, 2, 32, 8, 0, 1, None, ctypes.byref(q)) == -1   # no ctx
+    assert B.lib.bi_stream_open(None, X, 1, X, 1, X, 2, 32, 8, 0, 1, None, None) == -1             # no q
+    t = ctypes.c_uint64()
+    done = ctypes.c_int()
+    assert B.lib.bi_stream_submit(None, X, 1, ctypes.byref(t)) == -1
+    assert B.lib.bi_stream_poll(None, 0, ctypes.byref(done)) == -1
+    assert B.lib.bi_stream_wait(None, 0) == -1
+    assert B.lib.bi_stream_close(None) == 0
