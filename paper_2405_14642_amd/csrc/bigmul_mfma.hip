@@ -17,10 +17,12 @@
 // "digit blocks K - u of b, K = 32 st .. 32 st + 31" adds the u-th term to
 // the 32 output blocks of supertile st.  The k index of both operands runs
 // through s in reverse inside each 16-byte half, so lane (r, g) reads
-// a[32 u + r - 16 g - 15 ..] as 16 ascending bytes: from one of 8 byte-shifted
-// copies of a, at an 8-byte aligned address (one ds_read2_b64).  b is stored
-// with every 16-digit group byte-reversed, the two halves of each 32-digit
-// block in separate planes, so the B reads of a wave are contiguous.
+// a[32 u + r - 16 g - 15 ..] as 16 ascending bytes.  LDS holds every 8-byte
+// window of a's digits: entry x (8 bytes at 8 x) = digits x - kPA .. x - kPA + 7,
+// so the lanes of a wave read consecutive entries x and x + 8 (two
+// conflict-free 8-byte reads) whatever the byte offset.  b is stored with
+// every 16-digit group byte-reversed, the two halves of each 32-digit block in
+// separate planes, so the B reads of a wave are contiguous too.
 //
 // Work split.  Supertile st needs the u in [32 st - nb + 1, 32 st + 31]
 // clipped to [0, nb]; supertiles st and st + h (h = half their number) need
@@ -47,26 +49,27 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr uint32_t kPA = 48;     // zero bytes before the digits of a in copy 0
+constexpr uint32_t kPA = 32;     // zero bytes before the digits of a
 constexpr uint32_t kBPad = 32;   // zero B entries before block 0
 constexpr uint32_t kBTail = 31;  // zero B entries after the last block
 constexpr uint32_t kR8 = 0x80808080u;
 
 struct MfmaLayout {  // byte offsets into the dynamic LDS block
-    uint32_t D, nb, CSA, NBE;
-    uint32_t bpl, sum, total;
+    uint32_t D, nb, NE, NBE;
+    uint32_t a0, A0S, bpl, sum, total;
 };
 
 __host__ __device__ inline MfmaLayout mfma_layout(uint32_t n32p) {
     MfmaLayout l;
     l.D = 4 * n32p;
     l.nb = l.D / 32;
-    // Copy stride: the MFMA loop reads copy bytes below kPA + D + 64, so the
-    // stride is at least kPA + D + 64; = 32 mod 128 spreads the 8 copies over
-    // the LDS banks.
-    l.CSA = ((kPA + l.D + 32 + 127) / 128) * 128 + 32;
+    // 8-byte windows: the MFMA loop reads entries below D + 89
+    l.NE = (l.D + 89 + 31) & ~31u;
+    // digits of a with kPA zero bytes before and zeros up to NE + 16
+    l.a0 = 8 * l.NE;
+    l.A0S = (l.NE + 16 + 15) & ~15u;
     l.NBE = kBPad + l.nb + kBTail;
-    l.bpl = 8 * l.CSA;
+    l.bpl = l.a0 + l.A0S;
     l.sum = l.bpl + 2 * 16 * l.NBE;
     l.total = l.sum + 3 * 16;
     return l;
@@ -104,24 +107,20 @@ __device__ __forceinline__ void load4(const uint32_t *p, uint32_t n, uint32_t c,
 __device__ __forceinline__ int32_t sbyte(uint32_t w, uint32_t i) { return int32_t(w << (24 - 8 * i)) >> 24; }
 
 // Operand words of one 16-byte chunk per lane: chunk c = 64 w + lane of wave
-// w, plus for a the first two words of chunk c + 1 (zero beyond n words).
+// w (zero beyond n words).
 struct Chunks {
-    uint32_t a[6];
+    uint32_t a[4];
     uint32_t b[4];
 };
 
 __device__ __forceinline__ void fetch_chunks(const InstRef &in, uint32_t c, Chunks &x) {
-    const uint32_t n = in.n, base = 4 * c;
-    load4(in.a, n, c, *reinterpret_cast<uint32_t(*)[4]>(x.a));
-    x.a[4] = base + 4 < n ? in.a[base + 4] : 0u;
-    x.a[5] = base + 5 < n ? in.a[base + 5] : 0u;
-    load4(in.b, n, c, x.b);
+    load4(in.a, in.n, c, x.a);
+    load4(in.b, in.n, c, x.b);
 }
 
 // Balanced digits of both operands in one carry scan per operand (nchunks <=
-// 64 NW, one chunk per lane).  On return x.a[0..3] / x.b[0..3] hold the digit
-// words of (A + R) ^ R, x.a[4..5] the first digit words of chunk c + 1 (zero
-// past the last chunk), and t[0], t[1] the carries t_A, t_B.
+// 64 NW, one chunk per lane).  On return x.a / x.b hold the digit words of
+// (A + R) ^ R and t[0], t[1] the carries t_A, t_B.
 template <int NW>
 __device__ __forceinline__ void recode_chunks(Chunks &x, uint32_t nchunks, uint32_t *summary, uint32_t (&t)[2]) {
     const uint32_t lane = lane_id(), w = wave_in_block();
@@ -130,7 +129,7 @@ __device__ __forceinline__ void recode_chunks(Chunks &x, uint32_t nchunks, uint3
     const uint64_t vmask = valid >= 64 ? ~0ull : ((1ull << valid) - 1);
     const uint32_t R[4] = {kR8, kR8, kR8, kR8};
     uint32_t sa[4], sb[4];
-    const uint32_t ga = add_words<4>(*reinterpret_cast<const uint32_t(*)[4]>(x.a), R, sa);
+    const uint32_t ga = add_words<4>(x.a, R, sa);
     const uint32_t gb = add_words<4>(x.b, R, sb);
     const uint64_t Ga = ballot(ga != 0), Pa = ballot(c < nchunks && all_ones<4>(sa));
     const uint64_t Gb = ballot(gb != 0), Pb = ballot(c < nchunks && all_ones<4>(sb));
@@ -158,16 +157,8 @@ __device__ __forceinline__ void recode_chunks(Chunks &x, uint32_t nchunks, uint3
     t[0] = ta;
     t[1] = tb;
     const WaveCarry ca = wave_carry(Ga, Pa, cina), cb = wave_carry(Gb, Pb, cinb);
-    // carry into chunk c + 1 (lane 63: out of the row)
-    const uint32_t cnext = lane < 63 ? uint32_t(ca.into >> (lane + 1)) & 1u : ca.out;
     add_carry_words<4>(sa, uint32_t(ca.into >> lane) & 1u);
     add_carry_words<4>(sb, uint32_t(cb.into >> lane) & 1u);
-    uint32_t co;
-    const uint32_t n0 = __builtin_addc(x.a[4], kR8, cnext, &co);
-    const uint32_t n1 = __builtin_addc(x.a[5], kR8, co, &co);
-    const bool last = c + 1 >= nchunks;
-    x.a[4] = last ? 0u : n0 ^ kR8;
-    x.a[5] = last ? 0u : n1 ^ kR8;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         x.a[i] = sa[i] ^ kR8;
@@ -191,45 +182,21 @@ __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
         const InstRef in = src.get(pair);
         const uint32_t n32 = in.n, n32p = (n32 + 7) & ~7u;
         const MfmaLayout lo = mfma_layout(n32p);
-        const uint32_t D = lo.D, nb = lo.nb, CSA = lo.CSA, NBE = lo.NBE;
+        const uint32_t D = lo.D, nb = lo.nb, NE = lo.NE, NBE = lo.NBE;
         uint8_t *bpl = lds + lo.bpl;
         uint32_t *summary = reinterpret_cast<uint32_t *>(lds + lo.sum);
         const uint32_t nchunks = n32p / 4;
 
-        // 1. balanced digits, written as the 8 byte-shifted copies of a
-        //    (copy k byte y = digit y + k - kPA) and the group-reversed
-        //    B planes; zero the pads around both.
+        // 1. balanced digits: a after kPA zero bytes, b group-reversed into
+        //    the two B planes; zero the pads around both.
+        uint8_t *adg = lds + lo.a0;
         uint32_t tAB[2];
         recode_chunks<NW>(x, nchunks, summary, tAB);
         const uint32_t tA = tAB[0], tB = tAB[1];
         {
             const uint32_t c = 64 * wave + lane;
             if (c < nchunks) {
-                const uint32_t q = kPA / 16 + c;
-                const uint32_t *d = x.a;
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const uint32_t o = uint32_t(k) >> 2, sh = uint32_t(k) & 3u;
-                    uint4 v;
-                    v.x = __builtin_amdgcn_alignbyte(d[o + 1], d[o + 0], sh);
-                    v.y = __builtin_amdgcn_alignbyte(d[o + 2], d[o + 1], sh);
-                    v.z = __builtin_amdgcn_alignbyte(d[o + 3], d[o + 2], sh);
-                    v.w = __builtin_amdgcn_alignbyte(o + 4 < 6 ? d[o + 4] : 0u, d[o + 3], sh);
-                    *reinterpret_cast<uint4 *>(lds + k * CSA + 16 * q) = v;
-                }
-                if (c == 0) {  // the chunk before the digits: zeros, then the first digits
-#pragma unroll
-                    for (int k = 1; k < 8; ++k) {
-                        const uint32_t z[6] = {0u, 0u, 0u, 0u, d[0], d[1]};
-                        const uint32_t o = uint32_t(k) >> 2, sh = uint32_t(k) & 3u;
-                        uint4 v;
-                        v.x = __builtin_amdgcn_alignbyte(z[o + 1], z[o + 0], sh);
-                        v.y = __builtin_amdgcn_alignbyte(z[o + 2], z[o + 1], sh);
-                        v.z = __builtin_amdgcn_alignbyte(z[o + 3], z[o + 2], sh);
-                        v.w = __builtin_amdgcn_alignbyte(z[o + 4], z[o + 3], sh);
-                        *reinterpret_cast<uint4 *>(lds + k * CSA + 16 * (q - 1)) = v;
-                    }
-                }
+                *reinterpret_cast<uint4 *>(adg + kPA + 16 * c) = make_uint4(x.a[0], x.a[1], x.a[2], x.a[3]);
                 uint4 v;
                 v.x = __builtin_bswap32(x.b[3]);
                 v.y = __builtin_bswap32(x.b[2]);
@@ -237,22 +204,28 @@ __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
                 v.w = __builtin_bswap32(x.b[0]);
                 *reinterpret_cast<uint4 *>(bpl + (c & 1u) * 16 * NBE + 16 * (kBPad + (c >> 1))) = v;
             }
-            // zero chunks: copy 0 below the digits, every copy from kPA + D to
-            // its read limit, and the B pads
-            const uint32_t zlo = kPA / 16, zhi = (CSA - kPA - D) / 16;
-            const uint32_t nz0 = zlo + 7 * (zlo - 1), nza = nz0 + 8 * zhi;
-            for (uint32_t i = tid; i < nza; i += T) {
-                uint32_t k, qq;
-                if (i < zlo) { k = 0; qq = i; }
-                else if (i < nz0) { k = 1 + (i - zlo) / (zlo - 1); qq = (i - zlo) % (zlo - 1); }
-                else { k = (i - nz0) / zhi; qq = (kPA + D) / 16 + (i - nz0) % zhi; }
-                *reinterpret_cast<uint4 *>(lds + k * CSA + 16 * qq) = make_uint4(0, 0, 0, 0);
+            const uint32_t zlo = kPA / 16, zhi = (lo.A0S - kPA - D) / 16;
+            for (uint32_t i = tid; i < zlo + zhi; i += T) {
+                const uint32_t q = i < zlo ? i : (kPA + D) / 16 + (i - zlo);
+                *reinterpret_cast<uint4 *>(adg + 16 * q) = make_uint4(0, 0, 0, 0);
             }
             const uint32_t nz = kBPad + kBTail;
             for (uint32_t i = tid; i < 2 * nz; i += T) {
                 const uint32_t pl = i / nz, e = i - pl * nz;
                 const uint32_t ent = e < kBPad ? e : nb + e;
                 *reinterpret_cast<uint4 *>(bpl + pl * 16 * NBE + 16 * ent) = make_uint4(0, 0, 0, 0);
+            }
+        }
+        __syncthreads();
+
+        // 2. the 8-byte windows of a: entry x = digit bytes x - kPA .. x - kPA + 7
+        {
+            const uint32_t *a0w = reinterpret_cast<const uint32_t *>(adg);
+            for (uint32_t xe = tid; xe < NE; xe += T) {
+                const uint32_t q = xe >> 2, sh = xe & 3u;
+                const uint32_t w0 = a0w[q], w1 = a0w[q + 1], w2 = a0w[q + 2];
+                *reinterpret_cast<uint2 *>(lds + 8 * xe) =
+                    make_uint2(__builtin_amdgcn_alignbyte(w1, w0, sh), __builtin_amdgcn_alignbyte(w2, w1, sh));
             }
         }
         __syncthreads();
@@ -264,8 +237,7 @@ __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
         const uint32_t nst = (n32p + 127) / 128, h = (nst + 1) / 2;
         const uint32_t r = lane & 31u, g = lane >> 5;
         uint32_t Lo[2][4], Hi[2][4];
-        const uint32_t xb = r + kPA - 16 * g - 15, cpy = xb & 7u;
-        const uint8_t *abase = lds + cpy * CSA + (xb - cpy);
+        const uint8_t *abase = lds + 8 * (r + kPA - 16 * g - 15);
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const uint32_t st = wave + uint32_t(t) * h;
@@ -274,8 +246,8 @@ __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
             const int32_t uhi = min(int32_t(nb), int32_t(32 * st + 31));
             const uint8_t *bbase = bpl + g * 16 * NBE + 16 * (32 * st + r + kBPad);
             auto ldA = [&](int32_t u) -> v4i {
-                const uint64_t *p = reinterpret_cast<const uint64_t *>(abase + 32 * u);
-                const uint64_t x0 = p[0], x1 = p[1];
+                const uint64_t *p = reinterpret_cast<const uint64_t *>(abase + 256 * u);
+                const uint64_t x0 = p[0], x1 = p[8];
                 return v4i{int(uint32_t(x0)), int(uint32_t(x0 >> 32)), int(uint32_t(x1)), int(uint32_t(x1 >> 32))};
             };
             auto ldB = [&](int32_t u) -> v4i { return *reinterpret_cast<const v4i *>(bbase - 16 * u); };
@@ -301,7 +273,7 @@ __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
                 for (int e = 0; e < 4; ++e) c[e] = acc0[4 * j + e] + acc1[4 * j + e];
                 if (w >= n32p && w < 2 * n32p && (tA | tB)) {
                     const uint32_t m = w - n32p, cc = m >> 2;
-                    const uint32_t aw = *reinterpret_cast<const uint32_t *>(lds + kPA + 4 * m);
+                    const uint32_t aw = *reinterpret_cast<const uint32_t *>(adg + kPA + 4 * m);
                     const uint32_t bw = *reinterpret_cast<const uint32_t *>(
                         bpl + (cc & 1u) * 16 * NBE + 16 * (kBPad + (cc >> 1)) + 4 * (3 - (m & 3u)));
 #pragma unroll
@@ -315,9 +287,9 @@ __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
                 Hi[t][j] = uint32_t(V >> 32);
             }
         }
-        __syncthreads();  // every wave is done with the copies of a
+        __syncthreads();  // every wave is done with the windows of a
 
-        // 4. L and H (aliasing the copies), then product = L + H
+        // 4. L and H (aliasing the windows), then product = L + H
         const uint32_t W = 2 * n32p;
         uint32_t *L = reinterpret_cast<uint32_t *>(lds);
         uint32_t *H = L + W;
