@@ -36,8 +36,14 @@ __global__ void bin_kernel(const bi_desc *__restrict__ desc, uint64_t count, con
     }
 }
 
+// counts (256 B), class lists, then the NTT transforms (256-byte aligned).
+static size_t lists_bytes(uint64_t count) {
+    return (size_t(kNumClasses) * count * sizeof(uint32_t) + 255) & ~size_t(255);
+}
+
 size_t batch_scratch_bytes(uint64_t count, int num_cus) {
-    return 256 + size_t(kNumClasses) * count * sizeof(uint32_t) + ntt_fused_scratch_bytes(num_cus);
+    (void)num_cus;
+    return 256 + lists_bytes(count) + ntt_list_scratch_bytes(count);
 }
 
 hipError_t launch_bigmul_v_core(const Ctx &c, const Tune &tune, const void *a, const void *b, void *out,
@@ -45,8 +51,7 @@ hipError_t launch_bigmul_v_core(const Ctx &c, const Tune &tune, const void *a, c
                                 uint32_t limb_bits, int algo, void *scratch, hipStream_t st) {
     uint32_t *counts = static_cast<uint32_t *>(scratch);
     uint32_t *lists = reinterpret_cast<uint32_t *>(static_cast<char *>(scratch) + 256);
-    uint32_t *ntt_scr = reinterpret_cast<uint32_t *>(static_cast<char *>(scratch) + 256 +
-                                                     size_t(kNumClasses) * count_max * sizeof(uint32_t));
+    uint32_t *ntt_scr = reinterpret_cast<uint32_t *>(static_cast<char *>(scratch) + 256 + lists_bytes(count_max));
     const uint32_t wpl = limb_bits / 32;
     hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, counts, uint32_t(kNumClasses));
     const uint64_t bins = (count_max + 255) / 256;

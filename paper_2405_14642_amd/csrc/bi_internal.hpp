@@ -148,7 +148,10 @@ hipError_t launch_bigmul_mfma_list(const ListInst &src, uint32_t nmax, uint64_t 
                                    int num_cus);
 hipError_t launch_bigmul_ntt_list(const NttConst &K, const ListInst &src, uint32_t nmax, uint64_t count_max,
                                   uint32_t *scratch, hipStream_t st, int num_cus);
-size_t ntt_fused_scratch_bytes(int num_cus);
+// Ragged NTT classes run in rounds of at most kNttListChunk instances of the
+// longest transform (more at shorter lengths); scratch for `count` instances.
+constexpr uint64_t kNttListChunk = 4096;
+size_t ntt_list_scratch_bytes(uint64_t count);
 
 // int8-MFMA schoolbook for up to mfma_max_limbs() 32-bit limbs.
 uint32_t mfma_max_limbs();

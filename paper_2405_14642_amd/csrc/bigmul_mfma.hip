@@ -25,9 +25,9 @@
 // separate planes, so the B reads of a wave are contiguous too.
 //
 // Work split.  Supertile st needs the u in [32 st - nb + 1, 32 st + 31]
-// clipped to [0, nb]; supertiles st and st + h (h = half their number) need
-// about nb + 32 steps together, so each wave owns such a pair, keeps its
-// accumulators in registers and needs no atomics.
+// clipped to [0, nb].  Each wave owns two adjacent supertiles, whose ranges
+// coincide but for 32 steps at each end, keeps their accumulators in
+// registers (no atomics), and reads each A operand once for both.
 //
 // Normalisation.  A lane holds, for each of its output words w, the four
 // coefficients of bytes 4w .. 4w+3.  V_w = sum_e c_e 2^(8e) + 2^63 - 2^31 [w > 0]
@@ -168,6 +168,46 @@ __device__ __forceinline__ void recode_chunks(Chunks &x, uint32_t nchunks, uint3
 
 }  // namespace
 
+// A operand of step u for this lane: the windows x and x + 8 of a, x =
+// 32 u + r - 16 g - 15 + kPA (byte offset oA + 256 u).  Both addresses are
+// laundered so the compiler keeps separate consecutive-lane ds_read_b64
+// instead of merging pairs into ds_read2_b64, which the LDS serves at half
+// the rate.
+__device__ __forceinline__ v4i load_a(const uint8_t *lds, uint32_t oA, int32_t u) {
+    uint32_t p0 = oA + 256 * uint32_t(u), p1 = p0 + 64;
+    asm volatile("" : "+v"(p0));
+    asm volatile("" : "+v"(p1));
+    const uint64_t x0 = *reinterpret_cast<const uint64_t *>(lds + p0);
+    const uint64_t x1 = *reinterpret_cast<const uint64_t *>(lds + p1);
+    return v4i{int(uint32_t(x0)), int(uint32_t(x0 >> 32)), int(uint32_t(x1)), int(uint32_t(x1 >> 32))};
+}
+
+// MFMA steps u in [ua, ub) for supertile s0 (M bit 0) and/or s1 = s0 + 1
+// (M bit 1), which share the A operand T_u.  bb0 / bb1: this lane's B entry
+// of step 0 for s0 / s1 (the entry of step u is 16 u bytes lower).
+// acc[0] accumulates s0, acc[1] s1.
+template <int M>
+__device__ __forceinline__ void mfma_steps(int32_t ua, int32_t ub, const uint8_t *lds, uint32_t oA,
+                                           const uint8_t *bb0, const uint8_t *bb1, v16i (&acc)[2]) {
+    auto ldB = [](const uint8_t *bb, int32_t u) -> v4i { return *reinterpret_cast<const v4i *>(bb - 16 * u); };
+    int32_t u = ua;
+    for (; u + 1 < ub; u += 2) {
+        const v4i a0 = load_a(lds, oA, u), a1 = load_a(lds, oA, u + 1);
+        v4i p0 = {}, p1 = {}, q0 = {}, q1 = {};
+        if (M & 1) { p0 = ldB(bb0, u); p1 = ldB(bb0, u + 1); }
+        if (M & 2) { q0 = ldB(bb1, u); q1 = ldB(bb1, u + 1); }
+        if (M & 1) acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, p0, acc[0], 0, 0, 0);
+        if (M & 2) acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, q0, acc[1], 0, 0, 0);
+        if (M & 1) acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, p1, acc[0], 0, 0, 0);
+        if (M & 2) acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, q1, acc[1], 0, 0, 0);
+    }
+    if (u < ub) {
+        const v4i a0 = load_a(lds, oA, u);
+        if (M & 1) acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, ldB(bb0, u), acc[0], 0, 0, 0);
+        if (M & 2) acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, ldB(bb1, u), acc[1], 0, 0, 0);
+    }
+}
+
 template <int NW, class Src>
 __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -218,14 +258,19 @@ __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
         }
         __syncthreads();
 
-        // 2. the 8-byte windows of a: entry x = digit bytes x - kPA .. x - kPA + 7
+        // 2. the 8-byte windows of a: entry x = digit bytes x - kPA .. x - kPA + 7,
+        //    two entries (16 bytes) per thread and step
         {
             const uint32_t *a0w = reinterpret_cast<const uint32_t *>(adg);
-            for (uint32_t xe = tid; xe < NE; xe += T) {
-                const uint32_t q = xe >> 2, sh = xe & 3u;
+            for (uint32_t x2 = tid; 2 * x2 < NE; x2 += T) {
+                const uint32_t q = x2 >> 1, sh = 2 * (x2 & 1u);
                 const uint32_t w0 = a0w[q], w1 = a0w[q + 1], w2 = a0w[q + 2];
-                *reinterpret_cast<uint2 *>(lds + 8 * xe) =
-                    make_uint2(__builtin_amdgcn_alignbyte(w1, w0, sh), __builtin_amdgcn_alignbyte(w2, w1, sh));
+                uint4 v;
+                v.x = __builtin_amdgcn_alignbyte(w1, w0, sh);
+                v.y = __builtin_amdgcn_alignbyte(w2, w1, sh);
+                v.z = __builtin_amdgcn_alignbyte(w1, w0, sh + 1);
+                v.w = __builtin_amdgcn_alignbyte(w2, w1, sh + 1);
+                *reinterpret_cast<uint4 *>(lds + 16 * x2) = v;
             }
         }
         __syncthreads();
@@ -233,58 +278,57 @@ __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
         // next pair's operands, in flight during the products
         if (pair + gridDim.x < count) fetch_chunks(src.get(pair + gridDim.x), 64 * wave + lane, x);
 
-        // 3. MFMA: this wave's supertiles wave and wave + h
-        const uint32_t nst = (n32p + 127) / 128, h = (nst + 1) / 2;
+        // 3. MFMA: this wave's adjacent supertiles s0 = 2 p and s1 = 2 p + 1.
+        //    Their u-ranges overlap except for 32 steps at each end; inside
+        //    the overlap both share every A operand (3 LDS reads per 2
+        //    MFMAs).  p rotates with the pair index so that every SIMD sees
+        //    the light (band-edge) and heavy (middle) supertiles equally.
+        const uint32_t nst = (n32p + 127) / 128, npt = (nst + 1) / 2;
         const uint32_t r = lane & 31u, g = lane >> 5;
+        const uint32_t pw = (wave + uint32_t(pair % NW)) % NW;
+        const uint32_t s0 = 2 * pw, s1 = s0 + 1;
+        const bool has0 = pw < npt, has1 = has0 && s1 < nst;
         uint32_t Lo[2][4], Hi[2][4];
-        const uint8_t *abase = lds + 8 * (r + kPA - 16 * g - 15);
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const uint32_t st = wave + uint32_t(t) * h;
-            if (wave >= h || st >= nst) continue;
-            const int32_t ulo = max(0, int32_t(32 * st) - int32_t(nb) + 1);
-            const int32_t uhi = min(int32_t(nb), int32_t(32 * st + 31));
-            const uint8_t *bbase = bpl + g * 16 * NBE + 16 * (32 * st + r + kBPad);
-            auto ldA = [&](int32_t u) -> v4i {
-                const uint64_t *p = reinterpret_cast<const uint64_t *>(abase + 256 * u);
-                const uint64_t x0 = p[0], x1 = p[8];
-                return v4i{int(uint32_t(x0)), int(uint32_t(x0 >> 32)), int(uint32_t(x1)), int(uint32_t(x1 >> 32))};
-            };
-            auto ldB = [&](int32_t u) -> v4i { return *reinterpret_cast<const v4i *>(bbase - 16 * u); };
-            v16i acc0 = {}, acc1 = {};
-            const int32_t npair = (uhi - ulo + 2) >> 1;
-            int32_t u = ulo;
-            v4i a0 = ldA(u), b0 = ldB(u), a1 = ldA(u + 1), b1 = ldB(u + 1);
-            for (int32_t i = 0; i < npair; ++i) {
-                const int32_t un = (i + 1 < npair) ? u + 2 : u;
-                const v4i na0 = ldA(un), nb0 = ldB(un), na1 = ldA(un + 1), nb1 = ldB(un + 1);
-                acc0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, acc1, 0, 0, 0);
-                a0 = na0; b0 = nb0; a1 = na1; b1 = nb1;
-                u = un;
+        if (has0) {
+            const uint32_t oA = 8 * (r + kPA - 16 * g - 15);
+            const uint8_t *bb0 = bpl + g * 16 * NBE + 16 * (32 * s0 + r + kBPad);
+            const uint8_t *bb1 = bb0 + 16 * 32;
+            const int32_t lo0 = max(0, int32_t(32 * s0) - int32_t(nb) + 1);
+            const int32_t hi0 = min(int32_t(nb), int32_t(32 * s0 + 31)) + 1;
+            const int32_t lo1 = has1 ? max(0, int32_t(32 * s1) - int32_t(nb) + 1) : hi0;
+            const int32_t hi1 = has1 ? min(int32_t(nb), int32_t(32 * s1 + 31)) + 1 : hi0;
+            v16i acc[2] = {};
+            mfma_steps<1>(lo0, min(lo1, hi0), lds, oA, bb0, bb1, acc);
+            if (has1) {
+                mfma_steps<3>(lo1, hi0, lds, oA, bb0, bb1, acc);
+                mfma_steps<2>(max(hi0, lo1), hi1, lds, oA, bb0, bb1, acc);
             }
             // acc[4j + i] at lane (r, g) is coefficient 32 K + 8 j + 4 g + i,
             // K = 32 st + r: the four bytes of word w = 8 K + 2 j + g.
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t w = 256 * st + 8 * r + 2 * uint32_t(j) + g;
-                int32_t c[4];
+            for (int t = 0; t < 2; ++t) {
+                const uint32_t st = s0 + uint32_t(t);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) c[e] = acc0[4 * j + e] + acc1[4 * j + e];
-                if (w >= n32p && w < 2 * n32p && (tA | tB)) {
-                    const uint32_t m = w - n32p, cc = m >> 2;
-                    const uint32_t aw = *reinterpret_cast<const uint32_t *>(adg + kPA + 4 * m);
-                    const uint32_t bw = *reinterpret_cast<const uint32_t *>(
-                        bpl + (cc & 1u) * 16 * NBE + 16 * (kBPad + (cc >> 1)) + 4 * (3 - (m & 3u)));
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t w = 256 * st + 8 * r + 2 * uint32_t(j) + g;
+                    int32_t c[4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        c[e] += int32_t(tA) * sbyte(bw, 3 - e) + int32_t(tB) * sbyte(aw, e);
+                    for (int e = 0; e < 4; ++e) c[e] = acc[t][4 * j + e];
+                    if (w >= n32p && w < 2 * n32p && (tA | tB)) {
+                        const uint32_t m = w - n32p, cc = m >> 2;
+                        const uint32_t aw = *reinterpret_cast<const uint32_t *>(adg + kPA + 4 * m);
+                        const uint32_t bw = *reinterpret_cast<const uint32_t *>(
+                            bpl + (cc & 1u) * 16 * NBE + 16 * (kBPad + (cc >> 1)) + 4 * (3 - (m & 3u)));
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            c[e] += int32_t(tA) * sbyte(bw, 3 - e) + int32_t(tB) * sbyte(aw, e);
+                    }
+                    uint64_t V = uint64_t(int64_t(c[0])) + (uint64_t(int64_t(c[1])) << 8) +
+                                 (uint64_t(int64_t(c[2])) << 16) + (uint64_t(int64_t(c[3])) << 24);
+                    V += (1ull << 63) - (w > 0 ? (1ull << 31) : 0ull);
+                    Lo[t][j] = uint32_t(V);
+                    Hi[t][j] = uint32_t(V >> 32);
                 }
-                uint64_t V = uint64_t(int64_t(c[0])) + (uint64_t(int64_t(c[1])) << 8) +
-                             (uint64_t(int64_t(c[2])) << 16) + (uint64_t(int64_t(c[3])) << 24);
-                V += (1ull << 63) - (w > 0 ? (1ull << 31) : 0ull);
-                Lo[t][j] = uint32_t(V);
-                Hi[t][j] = uint32_t(V >> 32);
             }
         }
         __syncthreads();  // every wave is done with the windows of a
@@ -295,8 +339,8 @@ __global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
         uint32_t *H = L + W;
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            const uint32_t st = wave + uint32_t(t) * h;
-            if (wave >= h || st >= nst) continue;
+            const uint32_t st = s0 + uint32_t(t);
+            if (!(t == 0 ? has0 : has1)) continue;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const uint32_t w = 256 * st + 8 * r + 2 * uint32_t(j) + g;

@@ -24,6 +24,8 @@
 // (Garner), folds each thread's 8 coefficients (16-bit positions) into 4 low
 // words plus 2 high words, and adds the low and high arrays with the
 // workgroup ballot-adder, as for the schoolbook product.
+#include <algorithm>
+
 #include "bi_common.hpp"
 #include "bi_internal.hpp"
 #include "bi_wgadd.hpp"
@@ -247,20 +249,28 @@ __device__ __forceinline__ void ntt_inverse(uint32_t (&x)[E], uint32_t *__restri
 
 }  // namespace
 
-// One workgroup per (pair, operand, prime): the forward transform, stored in
-// bit-reversed order to tr[work * L ...] (thread t owns positions 32 t .. 32 t + 31).
-template <int M>
-__global__ __launch_bounds__((1 << M) / E) void ntt_fwd_kernel(NttConst K, const uint32_t *__restrict__ A,
-                                                               const uint32_t *__restrict__ B, uint32_t n32,
-                                                               uint64_t batch, uint32_t *__restrict__ tr) {
+// Instances [base, base + chunk) of src, fewer when its count is smaller
+// (the count of a ragged class list is read on the device).
+template <class Src>
+__device__ __forceinline__ uint64_t chunk_count(const Src &src, uint64_t base, uint64_t chunk) {
+    const uint64_t c = src.count();
+    return c > base ? min(c - base, chunk) : 0;
+}
+
+// One workgroup per (instance, operand, prime): the forward transform, stored
+// in bit-reversed order to tr[work * L ...] (thread t owns positions
+// 32 t .. 32 t + 31), work = 4 (instance - base) + 2 operand + prime.
+template <int M, class Src>
+__global__ __launch_bounds__((1 << M) / E) void ntt_fwd_kernel(NttConst K, Src src, uint64_t base, uint64_t chunk,
+                                                               uint32_t *__restrict__ tr) {
     extern __shared__ __align__(16) uint32_t sh[];
     constexpr uint32_t L = 1u << M;
-    for (uint64_t work = blockIdx.x; work < 4 * batch; work += gridDim.x) {
-        const uint64_t pair = work >> 2;
+    const uint64_t cnt = chunk_count(src, base, chunk);
+    for (uint64_t work = blockIdx.x; work < 4 * cnt; work += gridDim.x) {
+        const InstRef in = src.get(base + (work >> 2));
         const int pr = int(work & 1), op = int((work >> 1) & 1);
-        const uint32_t *src = (op ? B : A) + pair * n32;
         uint32_t x[E];
-        ntt_forward<M>(src, n32, x, sh, K.fwd[pr], K.p[pr]);
+        ntt_forward<M>(op ? in.b : in.a, in.n, x, sh, K.fwd[pr], K.p[pr]);
         uint4 *dst = reinterpret_cast<uint4 *>(tr + work * L + E * threadIdx.x);
 #pragma unroll
         for (int q = 0; q < E / 4; ++q) dst[q] = make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
@@ -268,20 +278,21 @@ __global__ __launch_bounds__((1 << M) / E) void ntt_fwd_kernel(NttConst K, const
     }
 }
 
-// One workgroup per (pair, prime): pointwise product of the two transforms,
-// inverse transform, scaling; the coefficient residues overwrite the first
-// operand's transform.
-template <int M>
-__global__ __launch_bounds__((1 << M) / E) void ntt_inv_kernel(NttConst K, uint32_t n32, uint64_t batch,
+// One workgroup per (instance, prime): pointwise product of the two
+// transforms, inverse transform, scaling; the coefficient residues overwrite
+// the first operand's transform.
+template <int M, class Src>
+__global__ __launch_bounds__((1 << M) / E) void ntt_inv_kernel(NttConst K, Src src, uint64_t base, uint64_t chunk,
                                                                uint32_t *__restrict__ tr) {
     extern __shared__ __align__(16) uint32_t sh[];
     constexpr uint32_t L = 1u << M;
-    const uint32_t nout = 4 * n32;  // coefficients of the product (the last is 0)
-    for (uint64_t work = blockIdx.x; work < 2 * batch; work += gridDim.x) {
-        const uint64_t pair = work >> 1;
+    const uint64_t cnt = chunk_count(src, base, chunk);
+    for (uint64_t work = blockIdx.x; work < 2 * cnt; work += gridDim.x) {
+        const uint64_t q2 = work >> 1;
+        const uint32_t nout = 4 * src.get(base + q2).n;  // coefficients of the product (the last is 0)
         const int pr = int(work & 1);
         const uint32_t p = K.p[pr], pneg = K.pneg[pr];
-        uint32_t *ta = tr + (4 * pair + pr) * L;      // operand a, prime pr
+        uint32_t *ta = tr + (4 * q2 + pr) * L;        // operand a, prime pr
         const uint32_t *tb = ta + 2 * L;              // operand b, prime pr
         uint32_t x[E];
         const uint4 *va = reinterpret_cast<const uint4 *>(ta + E * threadIdx.x);
@@ -300,22 +311,24 @@ __global__ __launch_bounds__((1 << M) / E) void ntt_inv_kernel(NttConst K, uint3
     }
 }
 
-// One workgroup per pair: CRT, per-thread combine of 8 coefficients, L + H.
-// Residues of prime i for pair q are at tr + (4 q + i) L.
-template <int NW>
-__global__ __launch_bounds__(64 * NW) void ntt_crt_carry_kernel(NttConst K, const uint32_t *__restrict__ tr,
-                                                                uint32_t L, uint32_t *__restrict__ C, uint32_t n32,
-                                                                uint64_t batch) {
+// One workgroup per instance: CRT, per-thread combine of 8 coefficients,
+// L + H.  Residues of prime i for chunk slot q are at tr + (4 q + i) L.
+template <int NW, class Src>
+__global__ __launch_bounds__(64 * NW) void ntt_crt_carry_kernel(NttConst K, Src src, uint64_t base, uint64_t chunk,
+                                                                const uint32_t *__restrict__ tr, uint32_t L) {
     extern __shared__ __align__(16) uint32_t lds[];
-    const uint32_t nout = 4 * n32;
-    const uint32_t nwords = 2 * n32;
-    const uint32_t ngroups = (nwords + 3) / 4;
-    uint32_t *Lsh = lds;                                          // [4 ngroups]
-    uint2 *Hsh = reinterpret_cast<uint2 *>(Lsh + 4 * ngroups);    // [ngroups]
-    uint32_t *summary = reinterpret_cast<uint32_t *>(Hsh + ngroups);
-    const uint32_t p1 = K.p[0], p2 = K.p[1];
-    for (uint64_t pair = blockIdx.x; pair < batch; pair += gridDim.x) {
-        const uint32_t *r1 = tr + (4 * pair) * L;
+    const uint32_t p1 = K.p[0];
+    const uint32_t p2 = K.p[1];
+    const uint64_t cnt = chunk_count(src, base, chunk);
+    for (uint64_t q = blockIdx.x; q < cnt; q += gridDim.x) {
+        const InstRef in = src.get(base + q);
+        const uint32_t nout = 4 * in.n;
+        const uint32_t nwords = 2 * in.n;
+        const uint32_t ngroups = (nwords + 3) / 4;
+        uint32_t *Lsh = lds;                                          // [4 ngroups]
+        uint2 *Hsh = reinterpret_cast<uint2 *>(Lsh + 4 * ngroups);    // [ngroups]
+        uint32_t *summary = reinterpret_cast<uint32_t *>(Hsh + ngroups);
+        const uint32_t *r1 = tr + (4 * q) * L;
         const uint32_t *r2 = r1 + L;
         for (uint32_t g = threadIdx.x; g < ngroups; g += 64 * NW) {
             // column sums of sum_e c_{8g+e} 2^(16 e), one 64-bit column per word
@@ -337,81 +350,6 @@ __global__ __launch_bounds__(64 * NW) void ntt_crt_carry_kernel(NttConst K, cons
             uint32_t R[6];
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
-                const uint64_t s = col[j] + carry;
-                R[j] = uint32_t(s);
-                carry = s >> 32;
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) Lsh[4 * g + j] = R[j];
-            Hsh[g] = make_uint2(R[4], R[5]);
-        }
-        __syncthreads();
-        wg_add_rows<NW>(LHSrc4{Lsh, Hsh, nwords}, C + pair * nwords, nwords, summary);
-        __syncthreads();
-    }
-}
-
-// Ragged batches: one workgroup per instance does both primes and the
-// recombination.  The first operand's transform is parked in the
-// workgroup's scratch slot (each thread re-reads only what it wrote), the
-// residues of both primes follow it in the slot, and after a barrier the
-// same workgroup runs Garner's CRT and the final carry scan.
-template <int M, class Src>
-__global__ __launch_bounds__((1 << M) / E) void ntt_fused_kernel(NttConst K, Src src, uint32_t *__restrict__ scratch) {
-    extern __shared__ __align__(16) uint32_t sh[];
-    constexpr uint32_t L = 1u << M;
-    constexpr int NW = int(L / E / 64);
-    uint32_t *slot = scratch + uint64_t(blockIdx.x) * 3 * L;
-    const uint32_t t = threadIdx.x;
-    const uint64_t count = src.count();
-    for (uint64_t inst = blockIdx.x; inst < count; inst += gridDim.x) {
-        const InstRef in = src.get(inst);
-        const uint32_t n32 = in.n, nout = 4 * n32;
-#pragma nounroll
-        for (int pr = 0; pr < 2; ++pr) {
-            const uint32_t p = K.p[pr], pneg = K.pneg[pr];
-            uint32_t x[E];
-            ntt_forward<M>(in.a, n32, x, sh, K.fwd[pr], p);
-            uint4 *park = reinterpret_cast<uint4 *>(slot + E * t);
-#pragma unroll
-            for (int q = 0; q < E / 4; ++q) park[q] = make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
-            ntt_forward<M>(in.b, n32, x, sh, K.fwd[pr], p);
-#pragma unroll
-            for (int q = 0; q < E / 4; ++q) {
-                const uint4 u = park[q];
-                x[4 * q] = mul_mont(u.x, x[4 * q], p, pneg);
-                x[4 * q + 1] = mul_mont(u.y, x[4 * q + 1], p, pneg);
-                x[4 * q + 2] = mul_mont(u.z, x[4 * q + 2], p, pneg);
-                x[4 * q + 3] = mul_mont(u.w, x[4 * q + 3], p, pneg);
-            }
-            ntt_inverse<M>(x, slot + (1 + pr) * L, nout, sh, K.inv[pr], p, K.scale[pr][M], K.scale_sh[pr][M]);
-        }
-        __syncthreads();  // residues of both primes written (same CU: workgroup-coherent)
-        const uint32_t nwords = 2 * n32, ngroups = (nwords + 3) / 4;
-        uint32_t *Lsh = sh;
-        uint2 *Hsh = reinterpret_cast<uint2 *>(Lsh + 4 * ngroups);
-        uint32_t *summary = reinterpret_cast<uint32_t *>(Hsh + ngroups);
-        const uint32_t *r1 = slot + L, *r2 = slot + 2 * L;
-        const uint32_t p1 = K.p[0], p2 = K.p[1];
-        for (uint32_t g = t; g < ngroups; g += L / E) {
-            uint64_t col[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const uint32_t k = 8 * g + e;
-                uint64_t c = 0;
-                if (k < nout) {
-                    const uint32_t a1 = r1[k], a2 = r2[k];
-                    const uint32_t tq = mul_shoup(sub_mod(a2, a1, p2), K.crt, K.crt_sh, p2);
-                    c = uint64_t(p1) * tq + a1;
-                }
-                const uint64_t v = c << (16 * (e & 1));
-                col[e >> 1] += uint32_t(v);
-                col[(e >> 1) + 1] += uint32_t(v >> 32);
-            }
-            uint64_t carry = 0;
-            uint32_t R[6];
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
                 const uint64_t sv = col[j] + carry;
                 R[j] = uint32_t(sv);
                 carry = sv >> 32;
@@ -426,91 +364,98 @@ __global__ __launch_bounds__((1 << M) / E) void ntt_fused_kernel(NttConst K, Src
     }
 }
 
-template <int M>
-static hipError_t launch_fused_m(const NttConst &K, const ListInst &src, uint64_t count_max, uint32_t *scratch,
-                                 uint32_t grid, hipStream_t st) {
-    const size_t lds = sizeof(uint32_t) * ((1u << M) + (1u << M) / 32);
+template <int NW, class Src>
+static hipError_t launch_crt(const NttConst &K, const Src &src, uint64_t base, uint64_t chunk, uint64_t grid,
+                             const uint32_t *tr, uint32_t L, uint32_t nmax, hipStream_t st) {
+    const uint32_t ngroups = (2 * nmax + 3) / 4;
+    const size_t lds = sizeof(uint32_t) * (4 * ngroups + 2 * ngroups + NW);
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_fused_kernel<M, ListInst>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_crt_carry_kernel<NW, Src>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    if (count_max < grid) grid = uint32_t(count_max);
-    if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((ntt_fused_kernel<M, ListInst>), dim3(grid), dim3((1u << M) / E), lds, st, K, src, scratch);
+    hipLaunchKernelGGL((ntt_crt_carry_kernel<NW, Src>), dim3(uint32_t(grid)), dim3(64 * NW), lds, st, K, src, base,
+                       chunk, tr, L);
     return hipGetLastError();
 }
 
-uint32_t ntt_fused_grid(uint32_t m, int num_cus) { return uint32_t(num_cus) << (kNttLogLmax - m); }
+// The three kernels of a product over instances [0, count_max) of src in
+// rounds of `chunk` instances (each round's transforms fill tr).  Grids are
+// capped at `cap` workgroups per kernel (the kernels loop over their work).
+template <int M, class Src>
+static hipError_t launch_ntt_m(const NttConst &K, const Src &src, uint32_t nmax, uint64_t count_max, uint64_t chunk,
+                               uint64_t cap, uint32_t *tr, hipStream_t st) {
+    const size_t lds = sizeof(uint32_t) * ((1u << M) + (1u << M) / 32);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_fwd_kernel<M, Src>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_inv_kernel<M, Src>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const uint32_t T = (1u << M) / E;
+    const uint32_t L = 1u << M;
+    const uint32_t ngroups = (2 * nmax + 3) / 4;
+    for (uint64_t base = 0; base < count_max; base += chunk) {
+        const uint64_t c = std::min(chunk, count_max - base);
+        hipLaunchKernelGGL((ntt_fwd_kernel<M, Src>), dim3(uint32_t(std::min(4 * c, cap))), dim3(T), lds, st, K, src, base,
+                           chunk, tr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((ntt_inv_kernel<M, Src>), dim3(uint32_t(std::min(2 * c, cap))), dim3(T), lds, st, K, src, base,
+                           chunk, tr);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const uint64_t g = std::min(c, cap);
+        if (ngroups <= 256) e = launch_crt<4>(K, src, base, chunk, g, tr, L, nmax, st);
+        else if (ngroups <= 1024) e = launch_crt<8>(K, src, base, chunk, g, tr, L, nmax, st);
+        else e = launch_crt<16>(K, src, base, chunk, g, tr, L, nmax, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
-size_t ntt_fused_scratch_bytes(int num_cus) {
-    // every transform length uses num_cus 2^(15-M) workgroups x 3 2^M words
-    return size_t(num_cus) * 3 * kNttLmax * sizeof(uint32_t);
+template <class Src>
+static hipError_t launch_ntt(const NttConst &K, const Src &src, uint32_t nmax, uint64_t count_max, uint64_t chunk,
+                             uint64_t cap, uint32_t *tr, hipStream_t st) {
+    switch (ntt_log_len(nmax)) {
+        case 11: return launch_ntt_m<11>(K, src, nmax, count_max, chunk, cap, tr, st);
+        case 12: return launch_ntt_m<12>(K, src, nmax, count_max, chunk, cap, tr, st);
+        case 13: return launch_ntt_m<13>(K, src, nmax, count_max, chunk, cap, tr, st);
+        case 14: return launch_ntt_m<14>(K, src, nmax, count_max, chunk, cap, tr, st);
+        case 15: return launch_ntt_m<15>(K, src, nmax, count_max, chunk, cap, tr, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t ntt_list_scratch_bytes(uint64_t count) {
+    // at most kNttListChunk instances of the longest transform per round
+    const uint64_t c = count < kNttListChunk ? count : kNttListChunk;
+    return size_t(c) * 4 * kNttLmax * sizeof(uint32_t);
 }
 
 hipError_t launch_bigmul_ntt_list(const NttConst &K, const ListInst &src, uint32_t nmax, uint64_t count_max,
                                   uint32_t *scratch, hipStream_t st, int num_cus) {
     const uint32_t m = ntt_log_len(nmax);
-    const uint32_t grid = ntt_fused_grid(m, num_cus);
-    switch (m) {
-        case 11: return launch_fused_m<11>(K, src, count_max, scratch, grid, st);
-        case 12: return launch_fused_m<12>(K, src, count_max, scratch, grid, st);
-        case 13: return launch_fused_m<13>(K, src, count_max, scratch, grid, st);
-        case 14: return launch_fused_m<14>(K, src, count_max, scratch, grid, st);
-        case 15: return launch_fused_m<15>(K, src, count_max, scratch, grid, st);
-        default: return hipErrorInvalidValue;
-    }
+    if (m == 0) return hipErrorInvalidValue;
+    if (count_max == 0) return hipSuccess;
+    // rounds of as many instances as the scratch holds at this length
+    const uint64_t cmax = count_max < kNttListChunk ? count_max : kNttListChunk;
+    const uint64_t chunk = cmax << (kNttLogLmax - m);
+    // about two resident workgroups per CU (2^(15-M) fit at length 2^M)
+    const uint64_t cap = uint64_t(num_cus) << (16 - m);
+    return launch_ntt(K, src, nmax, count_max, chunk, cap, scratch, st);
 }
 
 uint32_t ntt_log_len(uint32_t n32) {
     uint32_t m = 11;  // smallest supported transform (64 threads)
     while ((1u << m) < 4 * n32) ++m;
     return m <= uint32_t(kNttLogLmax) ? m : 0;
-}
-
-template <int M>
-static hipError_t launch_transforms(const NttConst &K, const uint32_t *a, const uint32_t *b, uint32_t n32,
-                                    uint64_t batch, uint32_t *tr, hipStream_t st) {
-    const size_t lds = sizeof(uint32_t) * ((1u << M) + (1u << M) / 32);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_fwd_kernel<M>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_inv_kernel<M>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    const uint32_t T = (1u << M) / E;
-    uint64_t w = 4 * batch;
-    hipLaunchKernelGGL((ntt_fwd_kernel<M>), dim3(uint32_t(w < 65536 ? w : 65536)), dim3(T), lds, st, K, a, b, n32,
-                       batch, tr);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    w = 2 * batch;
-    hipLaunchKernelGGL((ntt_inv_kernel<M>), dim3(uint32_t(w < 65536 ? w : 65536)), dim3(T), lds, st, K, n32, batch,
-                       tr);
-    return hipGetLastError();
-}
-
-template <int NW>
-static hipError_t launch_crt(const NttConst &K, const uint32_t *tr, uint32_t L, uint32_t *c, uint32_t n32,
-                             uint64_t batch, hipStream_t st) {
-    const uint32_t ngroups = (2 * n32 + 3) / 4;
-    const size_t lds = sizeof(uint32_t) * (4 * ngroups + 2 * ngroups + NW);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_crt_carry_kernel<NW>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    const uint32_t grid = uint32_t(batch < 65536 ? batch : 65536);
-    hipLaunchKernelGGL((ntt_crt_carry_kernel<NW>), dim3(grid), dim3(64 * NW), lds, st, K, tr, L, c, n32, batch);
-    return hipGetLastError();
 }
 
 size_t ntt_scratch_bytes(uint32_t n32, uint64_t batch) {
@@ -521,22 +466,7 @@ size_t ntt_scratch_bytes(uint32_t n32, uint64_t batch) {
 hipError_t launch_bigmul_ntt(const NttConst &K, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32,
                              uint64_t batch, uint32_t *tr, hipStream_t st) {
     if (batch == 0) return hipSuccess;
-    const uint32_t m = ntt_log_len(n32);
-    hipError_t e;
-    switch (m) {
-        case 11: e = launch_transforms<11>(K, a, b, n32, batch, tr, st); break;
-        case 12: e = launch_transforms<12>(K, a, b, n32, batch, tr, st); break;
-        case 13: e = launch_transforms<13>(K, a, b, n32, batch, tr, st); break;
-        case 14: e = launch_transforms<14>(K, a, b, n32, batch, tr, st); break;
-        case 15: e = launch_transforms<15>(K, a, b, n32, batch, tr, st); break;
-        default: return hipErrorInvalidValue;
-    }
-    if (e != hipSuccess) return e;
-    const uint32_t L = 1u << m;
-    const uint32_t ngroups = (2 * n32 + 3) / 4;
-    if (ngroups <= 256) return launch_crt<4>(K, tr, L, c, n32, batch, st);
-    if (ngroups <= 1024) return launch_crt<8>(K, tr, L, c, n32, batch, st);
-    return launch_crt<16>(K, tr, L, c, n32, batch, st);
+    return launch_ntt(K, UniformInst{a, b, c, n32, batch}, n32, batch, batch, 65536, tr, st);
 }
 
 }  // namespace bi
