@@ -10,7 +10,9 @@ kernels.  Every launch is timed with HIP events on the stream it runs on.
 Other workloads (--workload): mulq (quadratic multiplication sizes),
 ntt (NTT-multiplication sizes), stream (10^5 products of mixed sizes in
 bursts: the stream queue against per-class padded launches, saturated
-throughput and burst latency at 0.8x load); each prints its own JSON line.
+throughput and burst latency at 0.8x load), copy (a plain 1 GiB device copy,
+the known-size kernel that scales the HBM byte counters); each prints its own
+JSON line.
 
 Prints one JSON line (rank 0, one GPU):
   value   whole-job additions per second over the step (all five sizes);
@@ -39,7 +41,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="add", choices=["add", "mulq", "ntt", "stream"])
+    p.add_argument("--workload", default="add", choices=["add", "mulq", "ntt", "stream", "copy"])
     p.add_argument("--stream-pairs", type=int, default=100000, help="pairs in the mixed-size stream")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU baseline budget")
@@ -436,6 +438,40 @@ def cpu_baseline_stream(args, orc, a, b, off, nn):
             "cpu_model": cpu_info(), "seconds": round(secs, 2)}
 
 
+def bench_copy(args):
+    """A plain device-to-device copy of 1 GiB (torch's copy kernel): the
+    reference of known size for the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    evs = []
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dst.copy_(src)
+        e1.record(stream)
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    us = 1e3 * float(np.mean([x.elapsed_time(y) for x, y in evs]))
+    nbytes = 4 * n
+    return {"metric": "device copy bandwidth (read + write)", "value": 2 * nbytes / (us * 1e-6) / 1e9,
+            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": us / 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "int32", "data": "synthetic (constant)",
+            "config": {"workload": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                       "parallelism": "single-gpu"},
+            "roofline": {"bound": "hbm", "achieved": round(2 * nbytes / (us * 1e-6) / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(2 * nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None},
+            "cpu_baseline": None}
+
+
 def cpu_baseline_add(args, W):
     import oracle
     oracle.build()
@@ -472,6 +508,8 @@ def main():
         res = bench_add(args)
     elif args.workload == "stream":
         res = bench_stream(args)
+    elif args.workload == "copy":
+        res = bench_copy(args)
     else:
         res = bench_mul(args, args.workload)
     print(json.dumps(res), flush=True)
