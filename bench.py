@@ -63,6 +63,27 @@ def cpu_info():
     return model
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed PMC summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or None when
+    the summary is for another kernel or the add kernels' source changed since
+    the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "bigadd_sweep_traffic.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(re.search(r"```json\s*(\{.*?\})\s*```", text, re.S).group(1))
+        src = b"".join(open(os.path.join(ROOT, "paper_2405_14642_amd", "csrc", f), "rb").read()
+                       for f in ("bigadd.hip", "bi_common.hpp"))
+    except (OSError, AttributeError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+        return None
+    return {"bytes_per_launch": rec["traffic_bytes"], "read": rec["fetch_bytes"], "written": rec["write_bytes"],
+            "source": "profiles/bigadd_sweep_traffic.md"}
+
+
 def add_kernel_name(n_limbs, limb_bits):
     """Name of the addition kernel the library launches for this shape (16-byte
     chunks; mirrors the size classes of the launcher in csrc/bigadd.hip)."""
@@ -141,9 +162,12 @@ def bench_add(args):
     dom_bits = max(sizes, key=lambda b: per_size[str(b)]["us_per_launch"])
     dom_us = per_size[str(dom_bits)]["us_per_launch"]
     achieved = bytes_per_launch / (dom_us * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "kernel": add_kernel_name(dom_bits // 64, 64) + f" at 2^{dom_bits.bit_length() - 1} bits",
+    dom_kernel = add_kernel_name(dom_bits // 64, 64) + f" at 2^{dom_bits.bit_length() - 1} bits"
+    tr = measured_traffic(dom_kernel)
+    roofline = {"bound": "hbm", "kernel": dom_kernel,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr["bytes_per_launch"] if tr else None,
+                "traffic_detail": tr,
                 "avg_launch_us": round(dom_us, 2), "algorithmic_bytes_per_launch": bytes_per_launch}
     value = pairs_per_step / (ms_per_step * 1e-3)
 
