@@ -68,7 +68,12 @@ hipError_t launch_bigmul_v_core(const Ctx &c, const Tune &tune, const void *a, c
         int alg = tune.mul_algo[k];
         if (algo != BI_MUL_AUTO && algo_supports(algo, nmax)) alg = algo;
         switch (alg) {
-            case BI_MUL_SCHOOL_MFMA: e = launch_bigmul_mfma_list(src, nmax, count_max, st, c.num_cus); break;
+            case BI_MUL_SCHOOL_MFMA:
+                e = nmax <= mfma_max_limbs()
+                        ? launch_bigmul_mfma_list(src, nmax, count_max, st, c.num_cus)
+                        : launch_bigmul_mfma_big_list(src, nmax, count_max, reinterpret_cast<uint8_t *>(ntt_scr),
+                                                      ntt_list_scratch_bytes(count_max), st, c.num_cus);
+                break;
             case BI_MUL_NTT: e = launch_bigmul_ntt_list(c.ntt.c, src, nmax, count_max, ntt_scr, st, c.num_cus); break;
             default: e = launch_bigmul_valu_list(src, nmax, count_max, st, c.num_cus); break;
         }

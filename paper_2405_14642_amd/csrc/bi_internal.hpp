@@ -153,8 +153,15 @@ hipError_t launch_bigmul_ntt_list(const NttConst &K, const ListInst &src, uint32
 constexpr uint64_t kNttListChunk = 4096;
 size_t ntt_list_scratch_bytes(uint64_t count);
 
-// int8-MFMA schoolbook for up to mfma_max_limbs() 32-bit limbs.
+// int8-MFMA schoolbook: one workgroup per product up to mfma_max_limbs()
+// 32-bit limbs; above that (up to kMaxLimbs32) the three-kernel large-product
+// path, with a scratch slot of mfma_big_slot_bytes(n) per product.
 uint32_t mfma_max_limbs();
+size_t mfma_big_slot_bytes(uint32_t nmax);
+hipError_t launch_bigmul_mfma_big(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
+                                  uint8_t *scr, hipStream_t st, int num_cus);
+hipError_t launch_bigmul_mfma_big_list(const ListInst &src, uint32_t nmax, uint64_t count_max, uint8_t *scr,
+                                       size_t scr_bytes, hipStream_t st, int num_cus);
 hipError_t launch_bigmul_mfma(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
                               hipStream_t st, int num_cus);
 

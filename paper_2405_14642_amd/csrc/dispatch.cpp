@@ -11,7 +11,7 @@ namespace bi {
 bool algo_supports(int algo, uint32_t n32) {
     switch (algo) {
         case BI_MUL_SCHOOL_VALU: return n32 >= 1 && n32 <= kMaxLimbs32;
-        case BI_MUL_SCHOOL_MFMA: return n32 >= 1 && n32 <= mfma_max_limbs();
+        case BI_MUL_SCHOOL_MFMA: return n32 >= 1 && n32 <= kMaxLimbs32;
         case BI_MUL_NTT: return n32 >= 1 && ntt_log_len(n32) != 0;
         default: return false;
     }
@@ -105,10 +105,17 @@ bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint3
                                    static_cast<uint32_t *>(out), n32, batch, st, c.num_cus);
             break;
         case BI_MUL_SCHOOL_MFMA:
-            if (n32 > mfma_max_limbs())
-                return set_error(BI_EALGO, "the int8-MFMA schoolbook supports up to %u 32-bit limbs", mfma_max_limbs());
-            e = launch_bigmul_mfma(static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
-                                   static_cast<uint32_t *>(out), n32, batch, st, c.num_cus);
+            if (n32 <= mfma_max_limbs()) {
+                e = launch_bigmul_mfma(static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
+                                       static_cast<uint32_t *>(out), n32, batch, st, c.num_cus);
+            } else {
+                void *scr = nullptr;
+                bi_status s = ctx_scratch(c, size_t(batch) * mfma_big_slot_bytes(n32), st, &scr);
+                if (s != BI_OK) return s;
+                e = launch_bigmul_mfma_big(static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
+                                           static_cast<uint32_t *>(out), n32, batch, static_cast<uint8_t *>(scr), st,
+                                           c.num_cus);
+            }
             break;
         case BI_MUL_NTT: {
             if (ntt_log_len(n32) == 0) return set_error(BI_EALGO, "NTT supports up to %u limbs", kNttLmax / 4);

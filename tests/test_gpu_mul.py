@@ -206,7 +206,8 @@ def test_ragged_bigmul_v(B, ctx, orc, algo, lb):
 def test_autotune_and_auto_dispatch(B, orc):
     """bi_autotune picks a supported algorithm for every size class, and
     BI_MUL_AUTO with the tuned table stays bit-exact; bi_tune_set rejects an
-    algorithm that cannot run a class and accepts a valid table."""
+    entry that names no algorithm (AUTO or an unknown value) and accepts a
+    valid table."""
     c = B.Context(0)
     try:
         algos = B.autotune(c)
@@ -216,8 +217,12 @@ def test_autotune_and_auto_dispatch(B, orc):
         for n in (16, 100, 700, 3000, 8192):
             a, b = patterned(rng, 3, n)
             check(orc, a, b, run_mul(B, c, a, b, 0))
-        with pytest.raises(B.BigIntError):
-            B.tune_set(c, [2] * B.NUM_CLASSES)  # MFMA cannot run 8192-limb products
+        for bad in (0, 9):
+            with pytest.raises(B.BigIntError):
+                B.tune_set(c, [bad] + [1] * (B.NUM_CLASSES - 1))
+        assert B.tune_get(c) == algos
+        B.tune_set(c, [2] * B.NUM_CLASSES)
+        assert B.tune_get(c) == [2] * B.NUM_CLASSES
         B.tune_set(c, [1] * B.NUM_CLASSES)
         assert B.tune_get(c) == [1] * B.NUM_CLASSES
     finally:
