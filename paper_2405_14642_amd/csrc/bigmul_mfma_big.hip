@@ -30,7 +30,7 @@ namespace {
 
 using namespace mfma;
 
-constexpr uint32_t kSU = 128;                // u-steps per segment
+constexpr uint32_t kSU = 96;                 // u-steps per segment (LDS < 40 KB: 4 workgroups per CU)
 constexpr uint32_t kPadA = 64;               // zero bytes around a's digits in scratch
 constexpr uint32_t kNEs = 32 * kSU + 32;     // windows per segment
 constexpr uint32_t kStage = 32 * kSU + 48;   // staged digit bytes per segment
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(64 * kNWRecode) void mfma_big_recode_kernel(Src src
 }
 
 template <class Src>
-__global__ __launch_bounds__(256) void mfma_big_kernel(Src src, uint64_t base, uint64_t chunk, uint32_t groups,
+__global__ __launch_bounds__(256, 4) void mfma_big_kernel(Src src, uint64_t base, uint64_t chunk, uint32_t groups,
                                                        uint8_t *__restrict__ scr, uint64_t stride) {
     extern __shared__ __align__(16) uint8_t lds[];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = wave_in_block();
