@@ -78,10 +78,13 @@ def measured_traffic(kernel):
                        for f in ("bigadd.hip", "bi_common.hpp"))
     except (OSError, AttributeError, ValueError):
         return None
-    if rec.get("kernel") != kernel or rec.get("source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+    if rec.get("source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
         return None
-    return {"bytes_per_launch": rec["traffic_bytes"], "read": rec["fetch_bytes"], "written": rec["write_bytes"],
-            "source": "profiles/bigadd_sweep_traffic.md"}
+    for r in rec.get("launches", []):
+        if r.get("kernel") == kernel:
+            return {"bytes_per_launch": r["traffic_bytes"], "read": r["fetch_bytes"], "written": r["write_bytes"],
+                    "source": "profiles/bigadd_sweep_traffic.md"}
+    return None
 
 
 def add_kernel_name(n_limbs, limb_bits):
