@@ -200,8 +200,13 @@ VALU_MAC_PEAK = 1024 * (16 * 32 / 48) * 2.4e9   # 2.62e13 u32 MAC/s
 # (16 lanes/clk/SIMD) + 7 add-class (32 lanes/clk/SIMD) instructions.
 NTT_BFLY_PEAK = 1024 * 2.4e9 / (3 / 16 + 7 / 32)  # 6.05e12 butterflies/s
 MFMA_I8_PEAK_OPS = 5.0e15                        # dense int8, ops (2 per MAC)
+# PrimeField64 NTT: a butterfly with a 64-bit Montgomery twiddle product is
+# 7 multiply-class instructions (4 for the 64x64 -> 128-bit product, 3 for the
+# reduction by p = 29 2^57 + 1) and 16 add-class ones (64-bit add, subtract,
+# compare-select and shifts).
+NTT64_BFLY_PEAK = 1024 * 2.4e9 / (7 / 16 + 16 / 32)  # 2.62e12 butterflies/s
 
-ALGO_IDS = {"valu": 1, "mfma": 2, "ntt": 3}
+ALGO_IDS = {"valu": 1, "mfma": 2, "ntt": 3, "ntt64": 4}
 
 
 def bench_mul(args, kind):
@@ -271,6 +276,15 @@ def bench_mul(args, kind):
                 r["roofline"] = {"bound": "alu", "achieved": round(bfly / (us * 1e-6) / 1e12, 3),
                                  "peak": round(NTT_BFLY_PEAK / 1e12, 3), "unit": "T butterflies/s",
                                  "frac": round(bfly / (us * 1e-6) / NTT_BFLY_PEAK, 4)}
+            elif name == "ntt64":
+                m = 11
+                while (1 << m) < 2 * n:
+                    m += 1
+                bfly = 2.0 * 3 * batch * (1 << m) / 2 * m
+                r["butterflies_per_launch"] = bfly
+                r["roofline"] = {"bound": "alu", "achieved": round(bfly / (us * 1e-6) / 1e12, 3),
+                                 "peak": round(NTT64_BFLY_PEAK / 1e12, 3), "unit": "T butterflies/s (PF64)",
+                                 "frac": round(bfly / (us * 1e-6) / NTT64_BFLY_PEAK, 4)}
             elif name == "mfma":
                 ops = 2.0 * batch * (4 * n) ** 2
                 r["roofline"] = {"bound": "mfma", "achieved": round(ops / (us * 1e-6) / 1e12, 1),

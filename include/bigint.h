@@ -54,7 +54,8 @@ typedef enum bi_mul_algo {
     BI_MUL_AUTO = 0,         /* the context's tuned choice for (n, batch)            */
     BI_MUL_SCHOOL_VALU = 1,  /* load-balanced schoolbook on the VALU (Section 3)     */
     BI_MUL_SCHOOL_MFMA = 2,  /* schoolbook on int8 MFMA, signed 8-bit digits         */
-    BI_MUL_NTT = 3           /* NTT over two word-size primes + CRT (Section 4)       */
+    BI_MUL_NTT = 3,          /* NTT over two word-size primes + CRT (Section 4)       */
+    BI_MUL_NTT_PF64 = 4      /* NTT over the one 64-bit prime PrimeField64 (Section 4.1) */
 } bi_mul_algo;
 
 typedef struct bi_ctx bi_ctx;
@@ -102,6 +103,11 @@ bi_status bigadd(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t *
  *   BI_MUL_NTT           Section 4: number-theoretic transforms modulo primes
  *                        k 2^m + 1 over 16-bit coefficients, recombined by the
  *                        Chinese remainder theorem, then a carry scan.
+ *   BI_MUL_NTT_PF64      Section 4.1's PrimeField64, p = 29 2^57 + 1: one
+ *                        prime above every coefficient bound (2^46), 64-bit
+ *                        Montgomery arithmetic; the product is taken as its
+ *                        cyclic and negacyclic halves (transforms of half the
+ *                        padded length), recombined, then a carry scan.
  *   BI_MUL_AUTO          the fastest of the above for (n_limbs, batch).
  * Results are exact (bit-identical across algorithms).
  */

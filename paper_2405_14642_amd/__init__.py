@@ -15,12 +15,12 @@ import os
 
 __all__ = ["Context", "BigIntError", "bigadd", "bigmul", "bigadd_v", "bigmul_v", "ntt_field", "StreamQueue",
            "DESC_DTYPE", "lib", "library_path",
-           "MUL_AUTO", "MUL_SCHOOL_VALU", "MUL_SCHOOL_MFMA", "MUL_NTT", "MAX_BITS", "STATUS"]
+           "MUL_AUTO", "MUL_SCHOOL_VALU", "MUL_SCHOOL_MFMA", "MUL_NTT", "MUL_NTT_PF64", "MAX_BITS", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libbigint.so")
 
-MUL_AUTO, MUL_SCHOOL_VALU, MUL_SCHOOL_MFMA, MUL_NTT = 0, 1, 2, 3
+MUL_AUTO, MUL_SCHOOL_VALU, MUL_SCHOOL_MFMA, MUL_NTT, MUL_NTT_PF64 = 0, 1, 2, 3, 4
 MAX_BITS = 1 << 18
 STATUS = {0: "BI_OK", -1: "BI_EINVAL", -2: "BI_ESIZE", -3: "BI_ELIMB", -4: "BI_EALIAS", -5: "BI_EHIP",
           -6: "BI_ENOMEM", -7: "BI_EALGO", -8: "BI_ENODEV"}

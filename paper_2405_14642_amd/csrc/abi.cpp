@@ -147,7 +147,7 @@ bi_status bigmul(bi_ctx *ctx, const void *a, const void *b, void *out, uint32_t 
     uint64_t ib = 0;
     bi_status s = check_shape(n_limbs, limb_bits, batch, &ib);
     if (s != BI_OK) return s;
-    if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT) return fail(BI_EINVAL, "unknown algorithm %d", algo);
+    if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT_PF64) return fail(BI_EINVAL, "unknown algorithm %d", algo);
     if (batch == 0) return ctx ? BI_OK : fail(BI_EINVAL, "ctx is NULL");
     if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
     if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;
@@ -182,7 +182,7 @@ bi_status bigadd_v(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t
 bi_status bigmul_v(bi_ctx *ctx, const void *a, const void *b, void *out, const bi_desc *desc, uint64_t count,
                    uint32_t limb_bits, int algo, void *stream) {
     if (limb_bits != 32 && limb_bits != 64) return fail(BI_ELIMB, "limb_bits must be 32 or 64 (got %u)", limb_bits);
-    if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT) return fail(BI_EINVAL, "unknown algorithm %d", algo);
+    if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT_PF64) return fail(BI_EINVAL, "unknown algorithm %d", algo);
     if (count == 0) return ctx ? BI_OK : fail(BI_EINVAL, "ctx is NULL");
     if (!desc) return fail(BI_EINVAL, "desc is NULL");
     bi_status s;

@@ -3,6 +3,8 @@
 // class's algorithm names, each reading its instances from the class list.
 // Everything is stream-ordered (no host synchronisation), so a whole ragged
 // batch can be captured into a HIP graph and replayed.
+#include <algorithm>
+
 #include "bi_common.hpp"
 #include "bi_internal.hpp"
 
@@ -43,7 +45,7 @@ static size_t lists_bytes(uint64_t count) {
 
 size_t batch_scratch_bytes(uint64_t count, int num_cus) {
     (void)num_cus;
-    return 256 + lists_bytes(count) + ntt_list_scratch_bytes(count);
+    return 256 + lists_bytes(count) + std::max(ntt_list_scratch_bytes(count), ntt64_list_scratch_bytes(count));
 }
 
 hipError_t launch_bigmul_v_core(const Ctx &c, const Tune &tune, const void *a, const void *b, void *out,
@@ -75,6 +77,10 @@ hipError_t launch_bigmul_v_core(const Ctx &c, const Tune &tune, const void *a, c
                                                       ntt_list_scratch_bytes(count_max), st, c.num_cus);
                 break;
             case BI_MUL_NTT: e = launch_bigmul_ntt_list(c.ntt.c, src, nmax, count_max, ntt_scr, st, c.num_cus); break;
+            case BI_MUL_NTT_PF64:
+                e = launch_bigmul_ntt64_list(c.ntt.c64, src, nmax, count_max, reinterpret_cast<uint64_t *>(ntt_scr), st,
+                                             c.num_cus);
+                break;
             default: e = launch_bigmul_valu_list(src, nmax, count_max, st, c.num_cus); break;
         }
         if (e != hipSuccess) return e;

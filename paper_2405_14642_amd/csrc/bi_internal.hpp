@@ -50,12 +50,39 @@ struct NttConst {
     const uint2 *inv[kNttPrimes];                 // the same for w^-1
 };
 
+// PrimeField64 of Section 4.1: p = 29 2^57 + 1 (k = 29, n = 57), one prime
+// whose 2^61.86 exceeds every product coefficient (< 2^46), so no CRT.  A
+// product of operands with up to H coefficients is split into its cyclic and
+// negacyclic convolutions of length H (half the zero-padded length), which
+// give the low and high halves of the coefficient vector.  Residues are
+// 64-bit; twiddles are stored in Montgomery form (w 2^64 mod p).
+constexpr uint64_t kP64 = 4179340454199820289ull;  // 29 * 2^57 + 1
+constexpr int kP64LogHmax = 14;                    // half-length transforms of up to 2^14 points
+constexpr int kP64LogHmin = 11;
+constexpr uint32_t kP64Hmax = 1u << kP64LogHmax;
+// Twiddle block per direction, as for the two-prime tables: [0, Hmax) w^e;
+// [kP64T1, +1024) the pass-1 table; from p64_t0_offset(M) the pass-0 table.
+constexpr uint32_t kP64T1 = kP64Hmax;
+__host__ __device__ constexpr uint32_t p64_t0_offset(uint32_t m) {
+    return kP64T1 + 1024 + ((1u << m) - (1u << kP64LogHmin));
+}
+constexpr uint32_t kP64TableWords = p64_t0_offset(kP64LogHmax + 1);
+
+struct NttConst64 {
+    uint64_t scale[kP64LogHmax + 1];  // Montgomery form of 2^-l 2^64 (undoes the pointwise R^-1)
+    const uint64_t *fwd, *inv;        // twiddle blocks, w of order Hmax
+    const uint64_t *twist, *untwist;  // psi^e and psi^-e for e < Hmax, psi of order 2 Hmax
+};
+
 struct NttTables {
     NttConst c{};
     uint2 *dev = nullptr;
+    NttConst64 c64{};
+    uint64_t *dev64 = nullptr;
 };
 
 bi_status ntt_setup(NttTables &t);
+bi_status ntt64_setup(NttTables &t);
 void ntt_release(NttTables &t);
 bi_status field_info(uint64_t p, bi_ntt_field_info *out);
 
@@ -152,6 +179,17 @@ hipError_t launch_bigmul_ntt_list(const NttConst &K, const ListInst &src, uint32
 // longest transform (more at shorter lengths); scratch for `count` instances.
 constexpr uint64_t kNttListChunk = 4096;
 size_t ntt_list_scratch_bytes(uint64_t count);
+
+// PrimeField64 NTT multiplication: four half-length transforms per pair (2
+// operands x cyclic / negacyclic, H 64-bit words each) in the scratch `tr`
+// (ntt64_scratch_bytes), then the halves are recombined and carried.
+uint32_t ntt64_log_len(uint32_t n32);  // log2 H, 0 if too large
+size_t ntt64_scratch_bytes(uint32_t n32, uint64_t batch);
+hipError_t launch_bigmul_ntt64(const NttConst64 &k, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32,
+                               uint64_t batch, uint64_t *tr, hipStream_t st);
+hipError_t launch_bigmul_ntt64_list(const NttConst64 &K, const ListInst &src, uint32_t nmax, uint64_t count_max,
+                                    uint64_t *scratch, hipStream_t st, int num_cus);
+size_t ntt64_list_scratch_bytes(uint64_t count);
 
 // int8-MFMA schoolbook: one workgroup per product up to mfma_max_limbs()
 // 32-bit limbs; above that (up to kMaxLimbs32) the three-kernel large-product

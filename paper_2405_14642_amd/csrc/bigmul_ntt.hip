@@ -24,6 +24,15 @@
 // (Garner), folds each thread's 8 coefficients (16-bit positions) into 4 low
 // words plus 2 high words, and adds the low and high arrays with the
 // workgroup ballot-adder, as for the schoolbook product.
+//
+// The same transform code, templated over the field, runs the single-prime
+// PrimeField64 variant of Section 4.1 (p = 29 2^57 + 1, 64-bit Montgomery
+// multiplies).  One prime suffices for exactness, and instead of one transform
+// of the zero-padded length L it runs two of length H = L/2: the cyclic
+// convolution (c_lo + c_hi) and, on inputs twisted by powers of psi (psi^H =
+// -1), the negacyclic one (c_lo - c_hi), where c = c_lo + x^H c_hi.  Every
+// coefficient is below 2^46 < p, so (cyc + neg)/2 and (cyc - neg)/2 mod p are
+// the coefficients themselves.
 #include <algorithm>
 
 #include "bi_common.hpp"
@@ -59,31 +68,72 @@ __device__ __forceinline__ uint32_t mul_mont(uint32_t a, uint32_t b, uint32_t p,
     return min(u, u - p);
 }
 
+// a * b * 2^-64 mod p for p = 29 2^57 + 1 (a, b < p).  -p^-1 mod 2^64 is
+// 29 2^57 - 1 because p = 1 mod 2^57, so both the Montgomery factor m and the
+// product m p reduce to shifts and a multiply by 29.
+__device__ __forceinline__ uint64_t mul_mont64(uint64_t a, uint64_t b) {
+    const uint64_t tl = a * b, th = __umul64hi(a, b);
+    const uint64_t m = ((tl * 29u) << 57) - tl;            // tl (-p^-1) mod 2^64
+    const uint64_t m29l = m * 29u, m29h = __umul64hi(m, 29u);
+    const uint64_t mpl = m + (m29l << 57);                  // low word of m p = m + 29 m 2^57
+    const uint64_t mph = ((m29h << 57) | (m29l >> 7)) + (mpl < m ? 1u : 0u);
+    const uint64_t u = th + mph + (tl != 0 ? 1u : 0u);      // (a b + m p) / 2^64 < 2p
+    return u >= kP64 ? u - kP64 : u;
+}
+
+// Field policies of the transform code: element type T, twiddle entry W, the
+// tables' root order 2^kLogTab with their pass-table offsets, and how many
+// butterflies (kBfly, 0 = a whole stage) and twiddle products (kTw, 0 = the
+// default) the scheduler may interleave, which bounds live registers.
+struct Fp32 {  // one prime below 2^31; twiddles (w, Shoup companion)
+    using T = uint32_t;
+    using W = uint2;
+    static constexpr int kBfly = 0, kTw = 0;
+    static constexpr int kLogTab = kNttLogLmax;
+    static constexpr uint32_t kT1 = kNttT1;
+    __device__ static constexpr uint32_t t0(uint32_t m) { return ntt_t0_offset(m); }
+    uint32_t p;
+    __device__ __forceinline__ T add(T a, T b) const { return add_mod(a, b, p); }
+    __device__ __forceinline__ T sub(T a, T b) const { return sub_mod(a, b, p); }
+    __device__ __forceinline__ T mulw(T a, W w) const { return mul_shoup(a, w.x, w.y, p); }
+};
+struct Fp64 {  // PrimeField64; twiddles in Montgomery form
+    using T = uint64_t;
+    using W = uint64_t;
+    static constexpr int kBfly = 4, kTw = 4;
+    static constexpr int kLogTab = kP64LogHmax;
+    static constexpr uint32_t kT1 = kP64T1;
+    __device__ static constexpr uint32_t t0(uint32_t m) { return p64_t0_offset(m); }
+    __device__ __forceinline__ T add(T a, T b) const {
+        const T s = a + b;  // < 2p < 2^63
+        return s >= kP64 ? s - kP64 : s;
+    }
+    __device__ __forceinline__ T sub(T a, T b) const { return a >= b ? a - b : a - b + kP64; }
+    __device__ __forceinline__ T mulw(T a, W w) const { return mul_mont64(a, w); }
+};
+
 __device__ __forceinline__ uint32_t padx(uint32_t i) { return i + (i >> 5); }
 
 template <int R>
 __device__ __forceinline__ uint32_t bitrev(uint32_t k) { return __brev(k) >> (32 - R); }
 
 // 2^R-point DIF network on x[base .. base + 2^R): stage t pairs (k, k + h),
-// h = 2^(R-t-1), twiddle w_{2^R}^((k mod h) 2^t); w_{2^R} = table[Lmax / 2^R].
-template <int R>
-__device__ __forceinline__ void small_dif(uint32_t *x, const uint2 *__restrict__ tw, uint32_t p) {
+// h = 2^(R-t-1), twiddle w_{2^R}^((k mod h) 2^t); w_{2^R} = table[2^kLogTab / 2^R].
+template <int R, class F>
+__device__ __forceinline__ void small_dif(typename F::T *x, const typename F::W *__restrict__ tw, const F &f) {
 #pragma unroll
     for (int t = 0; t < R; ++t) {
         const int h = 1 << (R - t - 1);
 #pragma unroll
         for (int k = 0; k < (1 << R); ++k) {
             if (k & h) continue;
+            const int nb = (k >> (R - t)) * h + (k & (h - 1));  // butterfly number within the stage
+            if (F::kBfly && nb > 0 && nb % F::kBfly == 0) __builtin_amdgcn_sched_barrier(0);
             const int j = (k & (h - 1)) << t;  // exponent of the 2^R-th root
-            const uint32_t u = x[k], v = x[k + h];
-            x[k] = add_mod(u, v, p);
-            const uint32_t d = sub_mod(u, v, p);
-            if (j == 0) {
-                x[k + h] = d;
-            } else {
-                const uint2 w = tw[j * (kNttLmax >> R)];
-                x[k + h] = mul_shoup(d, w.x, w.y, p);
-            }
+            const typename F::T u = x[k], v = x[k + h];
+            x[k] = f.add(u, v);
+            const typename F::T d = f.sub(u, v);
+            x[k + h] = j == 0 ? d : f.mulw(d, tw[j * ((1u << F::kLogTab) >> R)]);
         }
         __builtin_amdgcn_sched_barrier(0);  // one stage at a time: bounds live registers
     }
@@ -91,23 +141,22 @@ __device__ __forceinline__ void small_dif(uint32_t *x, const uint2 *__restrict__
 
 // Inverse of small_dif up to the factor 2^R: stages in reverse order,
 // (a, b) -> (a + b w^-j, a - b w^-j).
-template <int R>
-__device__ __forceinline__ void small_dit_inv(uint32_t *x, const uint2 *__restrict__ itw, uint32_t p) {
+template <int R, class F>
+__device__ __forceinline__ void small_dit_inv(typename F::T *x, const typename F::W *__restrict__ itw, const F &f) {
 #pragma unroll
     for (int t = R - 1; t >= 0; --t) {
         const int h = 1 << (R - t - 1);
 #pragma unroll
         for (int k = 0; k < (1 << R); ++k) {
             if (k & h) continue;
+            const int nb = (k >> (R - t)) * h + (k & (h - 1));  // butterfly number within the stage
+            if (F::kBfly && nb > 0 && nb % F::kBfly == 0) __builtin_amdgcn_sched_barrier(0);
             const int j = (k & (h - 1)) << t;
-            const uint32_t a = x[k];
-            uint32_t b = x[k + h];
-            if (j != 0) {
-                const uint2 w = itw[j * (kNttLmax >> R)];
-                b = mul_shoup(b, w.x, w.y, p);
-            }
-            x[k] = add_mod(a, b, p);
-            x[k + h] = sub_mod(a, b, p);
+            const typename F::T a = x[k];
+            typename F::T b = x[k + h];
+            if (j != 0) b = f.mulw(b, itw[j * ((1u << F::kLogTab) >> R)]);
+            x[k] = f.add(a, b);
+            x[k + h] = f.sub(a, b);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -118,15 +167,16 @@ __device__ __forceinline__ void small_dit_inv(uint32_t *x, const uint2 *__restri
 // (bitrev_R(k), lo) with lo fastest, so the lanes of a wave (consecutive lo)
 // read consecutive entries: row stride 1024 for pass 0 (lo = gidx < 1024),
 // 32 for pass 1 (lo < 32, where w_L^(2^s) = w_1024).
-template <int M, int R, uint32_t STRIDE>
-__device__ __forceinline__ void twiddle_group(uint32_t *x, const uint2 *__restrict__ tbl, uint32_t lo, uint32_t p) {
+template <int M, int R, uint32_t STRIDE, class F>
+__device__ __forceinline__ void twiddle_group(typename F::T *x, const typename F::W *__restrict__ tbl, uint32_t lo,
+                                              const F &f) {
 #pragma unroll
     for (int k = 1; k < (1 << R); ++k) {
-        const uint2 w = tbl[STRIDE * bitrev<R>(k) + lo];
-        x[k] = mul_shoup(x[k], w.x, w.y, p);
+        x[k] = f.mulw(x[k], tbl[STRIDE * bitrev<R>(k) + lo]);
         // Bound the twiddle loads in flight: 8 when registers allow, 4 for the
-        // 1024-thread transform.
-        if ((k & (M >= 15 ? 3 : 7)) == (M >= 15 ? 3 : 7)) __builtin_amdgcn_sched_barrier(0);
+        // 1024-thread transform (or the field's own bound).
+        constexpr int G = F::kTw ? F::kTw : (M >= 15 ? 4 : 8);
+        if ((k & (G - 1)) == G - 1) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -141,18 +191,22 @@ __device__ __forceinline__ uint32_t base_pass1(uint32_t t) {
     return (hi << 10) + (hi << 5) + lo;
 }
 
-// Forward transform of the 16-bit coefficients of `src` (n32 limbs); on return
-// x[k] holds position 32 t + k of the bit-reversed-order transform.
-template <int M>
-__device__ __forceinline__ void ntt_forward(const uint32_t *__restrict__ src, uint32_t n32, uint32_t (&x)[E],
-                                            uint32_t *sh, const uint2 *__restrict__ fw, uint32_t p) {
+// Forward transform of the 16-bit coefficients of `src` (n32 limbs, zero
+// beyond them up to 2^M coefficients), each first multiplied by twist[i
+// 2^(kLogTab - M)] when `twist` is set; on return x[k] holds position 32 t + k
+// of the bit-reversed-order transform.
+template <int M, class F>
+__device__ __forceinline__ void ntt_forward(const uint32_t *__restrict__ src, uint32_t n32, typename F::T (&x)[E],
+                                            typename F::T *sh, const typename F::W *__restrict__ fw, const F &f,
+                                            const typename F::W *__restrict__ twist) {
     constexpr int R0 = M - 10;
     constexpr int G0 = E >> R0;
     constexpr uint32_t T = (1u << M) / E;
     const uint32_t t = threadIdx.x;
     // Stage the limbs (zero-padded to L/2 words = L coefficients) in LDS.
     __syncthreads();  // the previous user of sh is done
-    for (uint32_t w = t; w < (1u << M) / 2; w += T) sh[w] = w < n32 ? src[w] : 0u;
+    uint32_t *sw = reinterpret_cast<uint32_t *>(sh);
+    for (uint32_t w = t; w < (1u << M) / 2; w += T) sw[w] = w < n32 ? src[w] : 0u;
     __syncthreads();
     const uint16_t *coef = reinterpret_cast<const uint16_t *>(sh);
     // pass 0: stages [0, R0); group g: elements k 2^10 + gidx, gidx = t + T g
@@ -160,26 +214,31 @@ __device__ __forceinline__ void ntt_forward(const uint32_t *__restrict__ src, ui
     for (int g = 0; g < G0; ++g) {
         const uint32_t gidx = t + T * g;
 #pragma unroll
-        for (int k = 0; k < (1 << R0); ++k) x[g * (1 << R0) + k] = coef[gidx + (uint32_t(k) << 10)];
+        for (int k = 0; k < (1 << R0); ++k) {
+            const uint32_t i = gidx + (uint32_t(k) << 10);
+            x[g * (1 << R0) + k] = coef[i];
+            if (twist) x[g * (1 << R0) + k] = f.mulw(x[g * (1 << R0) + k], twist[i << (F::kLogTab - M)]);
+            if (F::kTw && (k & (F::kTw - 1)) == F::kTw - 1) __builtin_amdgcn_sched_barrier(0);
+        }
     }
     __syncthreads();  // staging is overwritten below
 #pragma unroll
     for (int g = 0; g < G0; ++g) {
         const uint32_t gidx = t + T * g;
-        small_dif<R0>(x + g * (1 << R0), fw, p);
-        twiddle_group<M, R0, 1024>(x + g * (1 << R0), fw + ntt_t0_offset(M), gidx, p);
-        uint32_t *q = sh + padx(gidx);
+        small_dif<R0>(x + g * (1 << R0), fw, f);
+        twiddle_group<M, R0, 1024>(x + g * (1 << R0), fw + F::t0(M), gidx, f);
+        typename F::T *q = sh + padx(gidx);
 #pragma unroll
         for (int k = 0; k < (1 << R0); ++k) q[1056 * k] = x[g * (1 << R0) + k];
     }
     __syncthreads();
     // pass 1: stages [R0, R0 + 5); lo = t mod 32, hi = t / 32
     {
-        uint32_t *q = sh + base_pass1(t);
+        typename F::T *q = sh + base_pass1(t);
 #pragma unroll
         for (int k = 0; k < 32; ++k) x[k] = q[33 * k];
-        small_dif<5>(x, fw, p);
-        twiddle_group<M, 5, 32>(x, fw + kNttT1, t & 31u, p);
+        small_dif<5>(x, fw, f);
+        twiddle_group<M, 5, 32>(x, fw + F::kT1, t & 31u, f);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 32; ++k) q[33 * k] = x[k];
@@ -187,37 +246,39 @@ __device__ __forceinline__ void ntt_forward(const uint32_t *__restrict__ src, ui
     }
     // pass 2: stages [R0 + 5, M); groups are the contiguous runs 32 t .. 32 t + 31
     {
-        const uint32_t *q = sh + 33 * t;
+        const typename F::T *q = sh + 33 * t;
 #pragma unroll
         for (int k = 0; k < 32; ++k) x[k] = q[k];
-        small_dif<5>(x, fw, p);
+        small_dif<5>(x, fw, f);
     }
 }
 
-// Inverse of ntt_forward applied to x (position 32 t + k), times L^-1 2^32;
-// the natural-order results for i < nout go to dst[i].
-template <int M>
-__device__ __forceinline__ void ntt_inverse(uint32_t (&x)[E], uint32_t *__restrict__ dst, uint32_t nout, uint32_t *sh,
-                                            const uint2 *__restrict__ iw, uint32_t p, uint32_t scale,
-                                            uint32_t scale_sh) {
+// Inverse of ntt_forward applied to x (position 32 t + k), times `scale`
+// (L^-1 times the Montgomery radix) and, when `untwist` is set, times
+// untwist[i 2^(kLogTab - M)] at natural position i; the results for i < nout
+// go to dst[i].
+template <int M, class F>
+__device__ __forceinline__ void ntt_inverse(typename F::T (&x)[E], typename F::T *__restrict__ dst, uint32_t nout,
+                                            typename F::T *sh, const typename F::W *__restrict__ iw, const F &f,
+                                            typename F::W scale, const typename F::W *__restrict__ untwist) {
     constexpr int R0 = M - 10;
     constexpr int G0 = E >> R0;
     constexpr uint32_t T = (1u << M) / E;
     const uint32_t t = threadIdx.x;
-    small_dit_inv<5>(x, iw, p);
+    small_dit_inv<5>(x, iw, f);
     __syncthreads();
     {
-        uint32_t *q = sh + 33 * t;
+        typename F::T *q = sh + 33 * t;
 #pragma unroll
         for (int k = 0; k < 32; ++k) q[k] = x[k];
     }
     __syncthreads();
     {
-        uint32_t *q = sh + base_pass1(t);
+        typename F::T *q = sh + base_pass1(t);
 #pragma unroll
         for (int k = 0; k < 32; ++k) x[k] = q[33 * k];
-        twiddle_group<M, 5, 32>(x, iw + kNttT1, t & 31u, p);
-        small_dit_inv<5>(x, iw, p);
+        twiddle_group<M, 5, 32>(x, iw + F::kT1, t & 31u, f);
+        small_dit_inv<5>(x, iw, f);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < 32; ++k) q[33 * k] = x[k];
@@ -226,14 +287,18 @@ __device__ __forceinline__ void ntt_inverse(uint32_t (&x)[E], uint32_t *__restri
 #pragma unroll
     for (int g = 0; g < G0; ++g) {
         const uint32_t gidx = t + T * g;
-        uint32_t *y = x + g * (1 << R0);
-        const uint32_t *q = sh + padx(gidx);
+        typename F::T *y = x + g * (1 << R0);
+        const typename F::T *q = sh + padx(gidx);
 #pragma unroll
         for (int k = 0; k < (1 << R0); ++k) y[k] = q[1056 * k];
-        twiddle_group<M, R0, 1024>(y, iw + ntt_t0_offset(M), gidx, p);
-        small_dit_inv<R0>(y, iw, p);
+        twiddle_group<M, R0, 1024>(y, iw + F::t0(M), gidx, f);
+        small_dit_inv<R0>(y, iw, f);
 #pragma unroll
-        for (int k = 0; k < (1 << R0); ++k) y[k] = mul_shoup(y[k], scale, scale_sh, p);
+        for (int k = 0; k < (1 << R0); ++k) {
+            y[k] = f.mulw(y[k], scale);
+            if (untwist) y[k] = f.mulw(y[k], untwist[(gidx + (uint32_t(k) << 10)) << (F::kLogTab - M)]);
+            if (F::kTw && (k & (F::kTw - 1)) == F::kTw - 1) __builtin_amdgcn_sched_barrier(0);
+        }
     }
     __syncthreads();
     // natural order, unpadded, then contiguous copy-out
@@ -270,7 +335,7 @@ __global__ __launch_bounds__((1 << M) / E) void ntt_fwd_kernel(NttConst K, Src s
         const InstRef in = src.get(base + (work >> 2));
         const int pr = int(work & 1), op = int((work >> 1) & 1);
         uint32_t x[E];
-        ntt_forward<M>(op ? in.b : in.a, in.n, x, sh, K.fwd[pr], K.p[pr]);
+        ntt_forward<M>(op ? in.b : in.a, in.n, x, sh, K.fwd[pr], Fp32{K.p[pr]}, static_cast<const uint2 *>(nullptr));
         uint4 *dst = reinterpret_cast<uint4 *>(tr + work * L + E * threadIdx.x);
 #pragma unroll
         for (int q = 0; q < E / 4; ++q) dst[q] = make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
@@ -306,19 +371,51 @@ __global__ __launch_bounds__((1 << M) / E) void ntt_inv_kernel(NttConst K, Src s
             x[4 * q + 3] = mul_mont(u.w, v.w, p, pneg);
         }
         __syncthreads();  // every thread has read its part of ta before residues overwrite it
-        ntt_inverse<M>(x, ta, nout, sh, K.inv[pr], p, K.scale[pr][M], K.scale_sh[pr][M]);
+        ntt_inverse<M>(x, ta, nout, sh, K.inv[pr], Fp32{p}, make_uint2(K.scale[pr][M], K.scale_sh[pr][M]),
+                       static_cast<const uint2 *>(nullptr));
         __syncthreads();
     }
 }
 
-// One workgroup per instance: CRT, per-thread combine of 8 coefficients,
-// L + H.  Residues of prime i for chunk slot q are at tr + (4 q + i) L.
-template <int NW, class Src>
-__global__ __launch_bounds__(64 * NW) void ntt_crt_carry_kernel(NttConst K, Src src, uint64_t base, uint64_t chunk,
-                                                                const uint32_t *__restrict__ tr, uint32_t L) {
+// Product coefficient k (16-bit position) of chunk slot q from the two
+// residues (Garner): residues of prime i at tr + (4 q + i) L.
+struct CrtCoef {
+    const uint32_t *tr;
+    uint32_t L, p1, p2, crt, crt_sh;
+    __device__ __forceinline__ uint64_t operator()(uint64_t q, uint32_t k) const {
+        const uint32_t a1 = tr[4 * q * L + k], a2 = tr[(4 * q + 1) * L + k];
+        const uint32_t tq = mul_shoup(sub_mod(a2, a1, p2), crt, crt_sh, p2);
+        return uint64_t(p1) * tq + a1;  // < p1 p2; equals the coefficient (< 2^46)
+    }
+};
+
+// Product coefficient k from the PrimeField64 half results: cyclic at
+// tr + 4 q H, negacyclic at tr + (4 q + 1) H.  c_lo = (cyc + neg) / 2 and
+// c_hi = (cyc - neg) / 2, each below 2^46 < p, so the sum (difference) mod p
+// is twice the coefficient exactly.
+struct Half64Coef {
+    const uint64_t *tr;
+    uint32_t H;
+    __device__ __forceinline__ uint64_t operator()(uint64_t q, uint32_t k) const {
+        const uint64_t *cyc = tr + 4 * q * H, *neg = cyc + H;
+        const uint32_t j = k < H ? k : k - H;
+        const uint64_t c = cyc[j], n = neg[j];
+        uint64_t v;
+        if (k < H) {
+            v = c + n;
+            if (v >= kP64) v -= kP64;
+        } else {
+            v = c >= n ? c - n : c - n + kP64;
+        }
+        return v >> 1;
+    }
+};
+
+// One workgroup per instance: coefficients from `coef`, per-thread combine of
+// 8 coefficients into 4 low words and 2 high words, L + H.
+template <int NW, class Src, class Coef>
+__global__ __launch_bounds__(64 * NW) void ntt_crt_carry_kernel(Coef coef, Src src, uint64_t base, uint64_t chunk) {
     extern __shared__ __align__(16) uint32_t lds[];
-    const uint32_t p1 = K.p[0];
-    const uint32_t p2 = K.p[1];
     const uint64_t cnt = chunk_count(src, base, chunk);
     for (uint64_t q = blockIdx.x; q < cnt; q += gridDim.x) {
         const InstRef in = src.get(base + q);
@@ -328,20 +425,13 @@ __global__ __launch_bounds__(64 * NW) void ntt_crt_carry_kernel(NttConst K, Src 
         uint32_t *Lsh = lds;                                          // [4 ngroups]
         uint2 *Hsh = reinterpret_cast<uint2 *>(Lsh + 4 * ngroups);    // [ngroups]
         uint32_t *summary = reinterpret_cast<uint32_t *>(Hsh + ngroups);
-        const uint32_t *r1 = tr + (4 * q) * L;
-        const uint32_t *r2 = r1 + L;
         for (uint32_t g = threadIdx.x; g < ngroups; g += 64 * NW) {
             // column sums of sum_e c_{8g+e} 2^(16 e), one 64-bit column per word
             uint64_t col[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const uint32_t k = 8 * g + e;
-                uint64_t c = 0;
-                if (k < nout) {
-                    const uint32_t a1 = r1[k], a2 = r2[k];
-                    const uint32_t tq = mul_shoup(sub_mod(a2, a1, p2), K.crt, K.crt_sh, p2);
-                    c = uint64_t(p1) * tq + a1;  // < p1 p2; equals the coefficient (< 2^46)
-                }
+                const uint64_t c = k < nout ? coef(q, k) : 0;
                 const uint64_t v = c << (16 * (e & 1));  // < 2^62
                 col[e >> 1] += uint32_t(v);
                 col[(e >> 1) + 1] += uint32_t(v >> 32);
@@ -364,21 +454,83 @@ __global__ __launch_bounds__(64 * NW) void ntt_crt_carry_kernel(NttConst K, Src 
     }
 }
 
-template <int NW, class Src>
-static hipError_t launch_crt(const NttConst &K, const Src &src, uint64_t base, uint64_t chunk, uint64_t grid,
-                             const uint32_t *tr, uint32_t L, uint32_t nmax, hipStream_t st) {
+// PrimeField64, one workgroup per (instance, operand, half): the forward
+// transform of length H = 2^M of the operand (half 1: twisted by psi^i), in
+// bit-reversed order to tr[work * H ...], work = 4 (instance - base) + 2
+// operand + half.
+template <int M, class Src>
+__global__ __launch_bounds__((1 << M) / E) void ntt64_fwd_kernel(NttConst64 K, Src src, uint64_t base, uint64_t chunk,
+                                                                 uint64_t *__restrict__ tr) {
+    extern __shared__ __align__(16) uint64_t sh64[];
+    constexpr uint32_t H = 1u << M;
+    const uint64_t cnt = chunk_count(src, base, chunk);
+    for (uint64_t work = blockIdx.x; work < 4 * cnt; work += gridDim.x) {
+        const InstRef in = src.get(base + (work >> 2));
+        const int half = int(work & 1), op = int((work >> 1) & 1);
+        uint64_t x[E];
+        ntt_forward<M>(op ? in.b : in.a, in.n, x, sh64, K.fwd, Fp64{}, half ? K.twist : nullptr);
+        ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(tr + work * H + E * threadIdx.x);
+#pragma unroll
+        for (int q = 0; q < E / 2; ++q) dst[q] = make_ulonglong2(x[2 * q], x[2 * q + 1]);
+        __syncthreads();
+    }
+}
+
+// PrimeField64, one workgroup per (instance, half): pointwise Montgomery
+// product of the two operands' transforms, inverse transform, scaling (and
+// for half 1 the untwist by psi^-i); the H results overwrite operand a's
+// transform of that half.
+template <int M, class Src>
+__global__ __launch_bounds__((1 << M) / E) void ntt64_inv_kernel(NttConst64 K, Src src, uint64_t base, uint64_t chunk,
+                                                                 uint64_t *__restrict__ tr) {
+    extern __shared__ __align__(16) uint64_t sh64[];
+    constexpr uint32_t H = 1u << M;
+    const uint64_t cnt = chunk_count(src, base, chunk);
+    for (uint64_t work = blockIdx.x; work < 2 * cnt; work += gridDim.x) {
+        const uint64_t q2 = work >> 1;
+        const int half = int(work & 1);
+        uint64_t *ta = tr + (4 * q2 + half) * H;  // operand a, this half
+        const uint64_t *tb = ta + 2 * H;          // operand b, this half
+        uint64_t x[E];
+        const ulonglong2 *va = reinterpret_cast<const ulonglong2 *>(ta + E * threadIdx.x);
+        const ulonglong2 *vb = reinterpret_cast<const ulonglong2 *>(tb + E * threadIdx.x);
+#pragma unroll
+        for (int q = 0; q < E / 2; ++q) {
+            const ulonglong2 u = va[q], v = vb[q];
+            x[2 * q] = mul_mont64(u.x, v.x);
+            x[2 * q + 1] = mul_mont64(u.y, v.y);
+        }
+        __syncthreads();  // every thread has read its part of ta before results overwrite it
+        ntt_inverse<M>(x, ta, H, sh64, K.inv, Fp64{}, K.scale[M], half ? K.untwist : nullptr);
+        __syncthreads();
+    }
+}
+
+template <int NW, class Src, class Coef>
+static hipError_t launch_crt_nw(const Coef &coef, const Src &src, uint64_t base, uint64_t chunk, uint64_t grid,
+                                uint32_t nmax, hipStream_t st) {
     const uint32_t ngroups = (2 * nmax + 3) / 4;
     const size_t lds = sizeof(uint32_t) * (4 * ngroups + 2 * ngroups + NW);
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_crt_carry_kernel<NW, Src>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_crt_carry_kernel<NW, Src, Coef>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((ntt_crt_carry_kernel<NW, Src>), dim3(uint32_t(grid)), dim3(64 * NW), lds, st, K, src, base,
-                       chunk, tr, L);
+    hipLaunchKernelGGL((ntt_crt_carry_kernel<NW, Src, Coef>), dim3(uint32_t(grid)), dim3(64 * NW), lds, st, coef, src,
+                       base, chunk);
     return hipGetLastError();
+}
+
+// Workgroup size of the carry by output size: up to 1024, 4096, 32768 words.
+template <class Src, class Coef>
+static hipError_t launch_crt(const Coef &coef, const Src &src, uint64_t base, uint64_t chunk, uint64_t grid,
+                             uint32_t nmax, hipStream_t st) {
+    const uint32_t ngroups = (2 * nmax + 3) / 4;
+    if (ngroups <= 256) return launch_crt_nw<4>(coef, src, base, chunk, grid, nmax, st);
+    if (ngroups <= 1024) return launch_crt_nw<8>(coef, src, base, chunk, grid, nmax, st);
+    return launch_crt_nw<16>(coef, src, base, chunk, grid, nmax, st);
 }
 
 // The three kernels of a product over instances [0, count_max) of src in
@@ -400,7 +552,7 @@ static hipError_t launch_ntt_m(const NttConst &K, const Src &src, uint32_t nmax,
     }
     const uint32_t T = (1u << M) / E;
     const uint32_t L = 1u << M;
-    const uint32_t ngroups = (2 * nmax + 3) / 4;
+    const CrtCoef coef{tr, L, K.p[0], K.p[1], K.crt, K.crt_sh};
     for (uint64_t base = 0; base < count_max; base += chunk) {
         const uint64_t c = std::min(chunk, count_max - base);
         hipLaunchKernelGGL((ntt_fwd_kernel<M, Src>), dim3(uint32_t(std::min(4 * c, cap))), dim3(T), lds, st, K, src, base,
@@ -411,10 +563,7 @@ static hipError_t launch_ntt_m(const NttConst &K, const Src &src, uint32_t nmax,
                            chunk, tr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        const uint64_t g = std::min(c, cap);
-        if (ngroups <= 256) e = launch_crt<4>(K, src, base, chunk, g, tr, L, nmax, st);
-        else if (ngroups <= 1024) e = launch_crt<8>(K, src, base, chunk, g, tr, L, nmax, st);
-        else e = launch_crt<16>(K, src, base, chunk, g, tr, L, nmax, st);
+        e = launch_crt(coef, src, base, chunk, std::min(c, cap), nmax, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -467,6 +616,87 @@ hipError_t launch_bigmul_ntt(const NttConst &K, const uint32_t *a, const uint32_
                              uint64_t batch, uint32_t *tr, hipStream_t st) {
     if (batch == 0) return hipSuccess;
     return launch_ntt(K, UniformInst{a, b, c, n32, batch}, n32, batch, batch, 65536, tr, st);
+}
+
+// The three PrimeField64 kernels over instances [0, count_max) of src in rounds
+// of `chunk` instances; grids capped at `cap` workgroups.
+template <int M, class Src>
+static hipError_t launch_ntt64_m(const NttConst64 &K, const Src &src, uint32_t nmax, uint64_t count_max,
+                                 uint64_t chunk, uint64_t cap, uint64_t *tr, hipStream_t st) {
+    const size_t lds = sizeof(uint64_t) * ((1u << M) + (1u << M) / 32);
+    const void *fns[2] = {reinterpret_cast<const void *>(&ntt64_fwd_kernel<M, Src>),
+                          reinterpret_cast<const void *>(&ntt64_inv_kernel<M, Src>)};
+    static bool attr = false;
+    if (!attr) {
+        for (const void *fn : fns) {
+            const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) return e;
+        }
+        attr = true;
+    }
+    const uint32_t T = (1u << M) / E;
+    const Half64Coef coef{tr, 1u << M};
+    for (uint64_t base = 0; base < count_max; base += chunk) {
+        const uint64_t c = std::min(chunk, count_max - base);
+        hipLaunchKernelGGL((ntt64_fwd_kernel<M, Src>), dim3(uint32_t(std::min(4 * c, cap))), dim3(T), lds, st, K, src,
+                           base, chunk, tr);
+        hipLaunchKernelGGL((ntt64_inv_kernel<M, Src>), dim3(uint32_t(std::min(2 * c, cap))), dim3(T), lds, st, K, src,
+                           base, chunk, tr);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = launch_crt(coef, src, base, chunk, std::min(c, cap), nmax, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <class Src>
+static hipError_t launch_ntt64(const NttConst64 &K, const Src &src, uint32_t nmax, uint64_t count_max,
+                               uint64_t chunk, uint64_t cap, uint64_t *tr, hipStream_t st) {
+    switch (ntt64_log_len(nmax)) {
+        case 11: return launch_ntt64_m<11>(K, src, nmax, count_max, chunk, cap, tr, st);
+        case 12: return launch_ntt64_m<12>(K, src, nmax, count_max, chunk, cap, tr, st);
+        case 13: return launch_ntt64_m<13>(K, src, nmax, count_max, chunk, cap, tr, st);
+        case 14: return launch_ntt64_m<14>(K, src, nmax, count_max, chunk, cap, tr, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// H covers the 2 n32 coefficients of an operand (the cyclic and negacyclic
+// halves together hold the 4 n32 coefficients of the product).
+uint32_t ntt64_log_len(uint32_t n32) {
+    uint32_t m = kP64LogHmin;
+    while ((1u << m) < 2 * n32) ++m;
+    return m <= uint32_t(kP64LogHmax) ? m : 0;
+}
+
+size_t ntt64_scratch_bytes(uint32_t n32, uint64_t batch) {
+    const uint32_t m = ntt64_log_len(n32);
+    return m ? size_t(batch) * 4 * (size_t(1) << m) * sizeof(uint64_t) : 0;
+}
+
+size_t ntt64_list_scratch_bytes(uint64_t count) {
+    const uint64_t c = count < kNttListChunk ? count : kNttListChunk;
+    return size_t(c) * 4 * kP64Hmax * sizeof(uint64_t);
+}
+
+hipError_t launch_bigmul_ntt64(const NttConst64 &K, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32,
+                               uint64_t batch, uint64_t *tr, hipStream_t st) {
+    if (batch == 0) return hipSuccess;
+    return launch_ntt64(K, UniformInst{a, b, c, n32, batch}, n32, batch, batch, 65536, tr, st);
+}
+
+hipError_t launch_bigmul_ntt64_list(const NttConst64 &K, const ListInst &src, uint32_t nmax, uint64_t count_max,
+                                    uint64_t *scratch, hipStream_t st, int num_cus) {
+    const uint32_t m = ntt64_log_len(nmax);
+    if (m == 0) return hipErrorInvalidValue;
+    if (count_max == 0) return hipSuccess;
+    // rounds of as many instances as the scratch holds at this length
+    const uint64_t cmax = count_max < kNttListChunk ? count_max : kNttListChunk;
+    const uint64_t chunk = cmax << (kP64LogHmax - m);
+    // about two resident workgroups per CU (2^(14-M) fit at length 2^M)
+    const uint64_t cap = uint64_t(num_cus) << (15 - m);
+    return launch_ntt64(K, src, nmax, count_max, chunk, cap, scratch, st);
 }
 
 }  // namespace bi

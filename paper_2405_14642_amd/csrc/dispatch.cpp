@@ -13,6 +13,7 @@ bool algo_supports(int algo, uint32_t n32) {
         case BI_MUL_SCHOOL_VALU: return n32 >= 1 && n32 <= kMaxLimbs32;
         case BI_MUL_SCHOOL_MFMA: return n32 >= 1 && n32 <= kMaxLimbs32;
         case BI_MUL_NTT: return n32 >= 1 && ntt_log_len(n32) != 0;
+        case BI_MUL_NTT_PF64: return n32 >= 1 && ntt64_log_len(n32) != 0;
         default: return false;
     }
 }
@@ -125,6 +126,15 @@ bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint3
             if (s != BI_OK) return s;
             e = launch_bigmul_ntt(c.ntt.c, static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
                                   static_cast<uint32_t *>(out), n32, batch, static_cast<uint32_t *>(resid), st);
+            break;
+        }
+        case BI_MUL_NTT_PF64: {
+            if (ntt64_log_len(n32) == 0) return set_error(BI_EALGO, "NTT (PrimeField64) supports up to %u limbs", kP64Hmax / 2);
+            void *resid = nullptr;
+            bi_status s = ctx_scratch(c, ntt64_scratch_bytes(n32, batch), st, &resid);
+            if (s != BI_OK) return s;
+            e = launch_bigmul_ntt64(c.ntt.c64, static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
+                                    static_cast<uint32_t *>(out), n32, batch, static_cast<uint64_t *>(resid), st);
             break;
         }
         default:

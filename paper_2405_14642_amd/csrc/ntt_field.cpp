@@ -11,6 +11,10 @@
 // with their Shoup companions w' = floor(w 2^32 / p), so a product by a fixed
 // twiddle needs one high and two low 32-bit multiplies; the pointwise product
 // of two transforms uses Montgomery reduction with R = 2^32.
+//
+// It also sets up the single 64-bit prime of Section 4.1 (PrimeField64):
+// twiddles, the twist powers of a root of twice the transform order, and the
+// output scales, all in Montgomery form with R = 2^64.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -157,12 +161,72 @@ bi_status ntt_setup(NttTables &t) {
         t.c.fwd[i] = t.dev + size_t(2 * i) * kNttTableWords;
         t.c.inv[i] = t.dev + size_t(2 * i + 1) * kNttTableWords;
     }
+    return ntt64_setup(t);
+}
+
+// PrimeField64: w of order Hmax for the half-length transforms, psi of order
+// 2 Hmax for the negacyclic twist (psi_H = psi^(Hmax/H) has order 2H, so
+// psi_H^H = -1).  Montgomery form m(x) = x 2^64 mod p.
+bi_status ntt64_setup(NttTables &t) {
+    bi_ntt_field_info fi;
+    if (field_info(kP64, &fi) != BI_OK || fi.two_adicity < kP64LogHmax + 1) return BI_EINVAL;
+    const uint64_t p = kP64;
+    const uint64_t R1 = uint64_t((u128(1) << 64) % p);
+    auto mform = [&](uint64_t x) { return mulmod(x, R1, p); };
+    const uint64_t w = powmod(fi.g, uint64_t(1) << (fi.two_adicity - kP64LogHmax), p);
+    const uint64_t psi = powmod(fi.g, uint64_t(1) << (fi.two_adicity - kP64LogHmax - 1), p);
+    const uint64_t wi = powmod(w, p - 2, p), psii = powmod(psi, p - 2, p);
+    std::vector<uint64_t> host(size_t(2) * kP64TableWords + 2 * size_t(kP64Hmax));
+    uint64_t *fw = host.data(), *iw = fw + kP64TableWords;
+    uint64_t *tw = iw + kP64TableWords, *utw = tw + kP64Hmax;
+    uint64_t f = 1, g = 1, x = 1, y = 1;
+    for (uint32_t e = 0; e < kP64Hmax; ++e) {
+        fw[e] = mform(f);
+        iw[e] = mform(g);
+        tw[e] = mform(x);
+        utw[e] = mform(y);
+        f = mulmod(f, w, p);
+        g = mulmod(g, wi, p);
+        x = mulmod(x, psi, p);
+        y = mulmod(y, psii, p);
+    }
+    for (int dir = 0; dir < 2; ++dir) {
+        uint64_t *base = dir ? iw : fw;
+        for (uint32_t j = 0; j < 32; ++j)
+            for (uint32_t lo = 0; lo < 32; ++lo)
+                base[kP64T1 + 32 * j + lo] = base[((lo * j) % 1024) * (kP64Hmax / 1024)];
+        for (uint32_t m = kP64LogHmin; m <= kP64LogHmax; ++m) {
+            uint64_t *t0 = base + p64_t0_offset(m);
+            const uint32_t H = 1u << m;
+            for (uint32_t j = 0; j < (H >> 10); ++j)
+                for (uint32_t gi = 0; gi < 1024; ++gi)
+                    t0[1024 * j + gi] = base[(uint64_t(gi) * j % H) * (kP64Hmax / H)];
+        }
+    }
+    for (uint32_t l = 0; l <= kP64LogHmax; ++l) {
+        const uint64_t linv = powmod(uint64_t(1) << l, p - 2, p);
+        t.c64.scale[l] = mform(mform(linv));
+    }
+    const size_t bytes = host.size() * sizeof(uint64_t);
+    void *d = nullptr;
+    if (hipMalloc(&d, bytes) != hipSuccess) return BI_ENOMEM;
+    if (hipMemcpy(d, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return BI_EHIP;
+    }
+    t.dev64 = static_cast<uint64_t *>(d);
+    t.c64.fwd = t.dev64;
+    t.c64.inv = t.dev64 + kP64TableWords;
+    t.c64.twist = t.dev64 + 2 * size_t(kP64TableWords);
+    t.c64.untwist = t.c64.twist + kP64Hmax;
     return BI_OK;
 }
 
 void ntt_release(NttTables &t) {
     if (t.dev) (void)hipFree(t.dev);
     t.dev = nullptr;
+    if (t.dev64) (void)hipFree(t.dev64);
+    t.dev64 = nullptr;
 }
 
 }  // namespace bi

@@ -9,7 +9,7 @@ from tests import gpu_util as G
 
 pytestmark = pytest.mark.gpu
 
-ALGOS = {"valu": 1, "mfma": 2, "ntt": 3}
+ALGOS = {"valu": 1, "mfma": 2, "ntt": 3, "ntt64": 4}
 
 
 @pytest.fixture(scope="module")
@@ -211,7 +211,7 @@ def test_autotune_and_auto_dispatch(B, orc):
     c = B.Context(0)
     try:
         algos = B.autotune(c)
-        assert len(algos) == B.NUM_CLASSES and all(a in (1, 2, 3) for a in algos)
+        assert len(algos) == B.NUM_CLASSES and all(a in (1, 2, 3, 4) for a in algos)
         assert B.tune_get(c) == algos
         rng = np.random.default_rng(99)
         for n in (16, 100, 700, 3000, 8192):
@@ -223,6 +223,8 @@ def test_autotune_and_auto_dispatch(B, orc):
         assert B.tune_get(c) == algos
         B.tune_set(c, [2] * B.NUM_CLASSES)
         assert B.tune_get(c) == [2] * B.NUM_CLASSES
+        B.tune_set(c, [4] * B.NUM_CLASSES)
+        assert B.tune_get(c) == [4] * B.NUM_CLASSES
         B.tune_set(c, [1] * B.NUM_CLASSES)
         assert B.tune_get(c) == [1] * B.NUM_CLASSES
     finally:

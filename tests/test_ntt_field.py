@@ -66,3 +66,51 @@ def test_crt_bound():
 def test_rejects_non_primes(B, bad):
     with pytest.raises(B.BigIntError):
         B.ntt_field(bad)
+
+
+PF64 = 4179340454199820289  # PrimeField64 of Section 4.1, the BI_MUL_NTT_PF64 modulus
+
+
+def test_pf64_single_prime_bound():
+    """One PrimeField64 residue determines every coefficient: 16-bit digits of
+    2^18-bit operands give coefficients below 2^14 (2^16 - 1)^2 < 2^46 < p, and
+    the half-length split needs (cyc +- neg) < 2p as well."""
+    fields = {f["name"]: f for f in json.load(open(GOLDEN))["fields"]}
+    assert fields["PrimeField64"]["p"] == PF64
+    bound = ((1 << 18) // 16) * (2 ** 16 - 1) ** 2
+    assert bound < 2 ** 46 and 2 * bound < PF64
+
+
+def test_pf64_montgomery_constants():
+    """p = 1 + 29 2^57, so -p^-1 mod 2^64 = 29 2^57 - 1 and m p = m + 29 m 2^57:
+    the shift forms the 64-bit Montgomery reduction uses."""
+    assert PF64 == 29 * (1 << 57) + 1
+    pinv_neg = (29 << 57) - 1
+    assert (PF64 * pinv_neg) % (1 << 64) == (1 << 64) - 1
+    assert pinv_neg == (-pow(PF64, -1, 1 << 64)) % (1 << 64)
+    # two-adicity 57 leaves room for the twist root of order 2^15
+    assert (PF64 - 1) % (1 << 15) == 0
+
+
+def test_negacyclic_split_identity():
+    """c = a b, c = c_lo + x^H c_hi: the cyclic convolution of length H gives
+    c_lo + c_hi and the negacyclic one c_lo - c_hi, so their half-sum and
+    half-difference are c_lo and c_hi (checked on integer vectors)."""
+    import random
+    rng = random.Random(5)
+    for H in (1, 2, 4, 8, 16):
+        a = [rng.randrange(1 << 16) for _ in range(H)]
+        b = [rng.randrange(1 << 16) for _ in range(H)]
+        c = [0] * (2 * H)
+        for i in range(H):
+            for j in range(H):
+                c[i + j] += a[i] * b[j]
+        cyc = [0] * H
+        neg = [0] * H
+        for i in range(H):
+            for j in range(H):
+                k = i + j
+                cyc[k % H] += a[i] * b[j]
+                neg[k % H] += a[i] * b[j] * (1 if k < H else -1)
+        assert [(x + y) // 2 for x, y in zip(cyc, neg)] == c[:H]
+        assert [(x - y) // 2 for x, y in zip(cyc, neg)] == c[H:]
