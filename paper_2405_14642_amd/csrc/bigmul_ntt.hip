@@ -34,6 +34,7 @@
 // coefficient is below 2^46 < p, so (cyc + neg)/2 and (cyc - neg)/2 mod p are
 // the coefficients themselves.
 #include <algorithm>
+#include <utility>
 
 #include "bi_common.hpp"
 #include "bi_internal.hpp"
@@ -114,6 +115,12 @@ struct Fp64 {  // PrimeField64; twiddles in Montgomery form
 
 __device__ __forceinline__ uint32_t padx(uint32_t i) { return i + (i >> 5); }
 
+// fn(std::integral_constant<int, g>) for every g of the sequence, in order.
+template <class Fn, int... G>
+__device__ __forceinline__ void for_each_index(Fn &&fn, std::integer_sequence<int, G...>) {
+    (fn(std::integral_constant<int, G>{}), ...);
+}
+
 template <int R>
 __device__ __forceinline__ uint32_t bitrev(uint32_t k) { return __brev(k) >> (32 - R); }
 
@@ -192,13 +199,14 @@ __device__ __forceinline__ uint32_t base_pass1(uint32_t t) {
 }
 
 // Forward transform of the 16-bit coefficients of `src` (n32 limbs, zero
-// beyond them up to 2^M coefficients), each first multiplied by twist[i
-// 2^(kLogTab - M)] when `twist` is set; on return x[k] holds position 32 t + k
-// of the bit-reversed-order transform.
-template <int M, class F>
+// beyond them up to 2^M coefficients); with TW each is first multiplied by
+// twist[(i 2^(kLogTab - M)) & tmask] (tmask 0 selects twist[0], which holds
+// 1, so both halves of a product run the same branch-free code).  On return
+// x[k] holds position 32 t + k of the bit-reversed-order transform.
+template <int M, class F, bool TW = false>
 __device__ __forceinline__ void ntt_forward(const uint32_t *__restrict__ src, uint32_t n32, typename F::T (&x)[E],
                                             typename F::T *sh, const typename F::W *__restrict__ fw, const F &f,
-                                            const typename F::W *__restrict__ twist) {
+                                            const typename F::W *__restrict__ twist = nullptr, uint32_t tmask = 0) {
     constexpr int R0 = M - 10;
     constexpr int G0 = E >> R0;
     constexpr uint32_t T = (1u << M) / E;
@@ -217,7 +225,8 @@ __device__ __forceinline__ void ntt_forward(const uint32_t *__restrict__ src, ui
         for (int k = 0; k < (1 << R0); ++k) {
             const uint32_t i = gidx + (uint32_t(k) << 10);
             x[g * (1 << R0) + k] = coef[i];
-            if (twist) x[g * (1 << R0) + k] = f.mulw(x[g * (1 << R0) + k], twist[i << (F::kLogTab - M)]);
+            if constexpr (TW)
+                x[g * (1 << R0) + k] = f.mulw(x[g * (1 << R0) + k], twist[(i << (F::kLogTab - M)) & tmask]);
             if (F::kTw && (k & (F::kTw - 1)) == F::kTw - 1) __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -254,13 +263,14 @@ __device__ __forceinline__ void ntt_forward(const uint32_t *__restrict__ src, ui
 }
 
 // Inverse of ntt_forward applied to x (position 32 t + k), times `scale`
-// (L^-1 times the Montgomery radix) and, when `untwist` is set, times
-// untwist[i 2^(kLogTab - M)] at natural position i; the results for i < nout
-// go to dst[i].
-template <int M, class F>
+// (L^-1 times the Montgomery radix) and, with TW, times
+// untwist[(i 2^(kLogTab - M)) & tmask] at natural position i; the results for
+// i < nout go to dst[i].
+template <int M, class F, bool TW = false>
 __device__ __forceinline__ void ntt_inverse(typename F::T (&x)[E], typename F::T *__restrict__ dst, uint32_t nout,
                                             typename F::T *sh, const typename F::W *__restrict__ iw, const F &f,
-                                            typename F::W scale, const typename F::W *__restrict__ untwist) {
+                                            typename F::W scale, const typename F::W *__restrict__ untwist = nullptr,
+                                            uint32_t tmask = 0) {
     constexpr int R0 = M - 10;
     constexpr int G0 = E >> R0;
     constexpr uint32_t T = (1u << M) / E;
@@ -284,8 +294,11 @@ __device__ __forceinline__ void ntt_inverse(typename F::T (&x)[E], typename F::T
         for (int k = 0; k < 32; ++k) q[33 * k] = x[k];
         __syncthreads();
     }
-#pragma unroll
-    for (int g = 0; g < G0; ++g) {
+    // one group per element of the index sequence: a compile-time group
+    // offset keeps x in registers (a counted loop over 64-bit groups is too
+    // large for the unroller and would leave x in scratch memory)
+    auto group = [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
         const uint32_t gidx = t + T * g;
         typename F::T *y = x + g * (1 << R0);
         const typename F::T *q = sh + padx(gidx);
@@ -296,10 +309,11 @@ __device__ __forceinline__ void ntt_inverse(typename F::T (&x)[E], typename F::T
 #pragma unroll
         for (int k = 0; k < (1 << R0); ++k) {
             y[k] = f.mulw(y[k], scale);
-            if (untwist) y[k] = f.mulw(y[k], untwist[(gidx + (uint32_t(k) << 10)) << (F::kLogTab - M)]);
+            if constexpr (TW) y[k] = f.mulw(y[k], untwist[((gidx + (uint32_t(k) << 10)) << (F::kLogTab - M)) & tmask]);
             if (F::kTw && (k & (F::kTw - 1)) == F::kTw - 1) __builtin_amdgcn_sched_barrier(0);
         }
-    }
+    };
+    for_each_index(group, std::make_integer_sequence<int, G0>{});
     __syncthreads();
     // natural order, unpadded, then contiguous copy-out
 #pragma unroll
@@ -335,7 +349,7 @@ __global__ __launch_bounds__((1 << M) / E) void ntt_fwd_kernel(NttConst K, Src s
         const InstRef in = src.get(base + (work >> 2));
         const int pr = int(work & 1), op = int((work >> 1) & 1);
         uint32_t x[E];
-        ntt_forward<M>(op ? in.b : in.a, in.n, x, sh, K.fwd[pr], Fp32{K.p[pr]}, static_cast<const uint2 *>(nullptr));
+        ntt_forward<M>(op ? in.b : in.a, in.n, x, sh, K.fwd[pr], Fp32{K.p[pr]});
         uint4 *dst = reinterpret_cast<uint4 *>(tr + work * L + E * threadIdx.x);
 #pragma unroll
         for (int q = 0; q < E / 4; ++q) dst[q] = make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
@@ -371,8 +385,7 @@ __global__ __launch_bounds__((1 << M) / E) void ntt_inv_kernel(NttConst K, Src s
             x[4 * q + 3] = mul_mont(u.w, v.w, p, pneg);
         }
         __syncthreads();  // every thread has read its part of ta before residues overwrite it
-        ntt_inverse<M>(x, ta, nout, sh, K.inv[pr], Fp32{p}, make_uint2(K.scale[pr][M], K.scale_sh[pr][M]),
-                       static_cast<const uint2 *>(nullptr));
+        ntt_inverse<M>(x, ta, nout, sh, K.inv[pr], Fp32{p}, make_uint2(K.scale[pr][M], K.scale_sh[pr][M]));
         __syncthreads();
     }
 }
@@ -468,7 +481,7 @@ __global__ __launch_bounds__((1 << M) / E) void ntt64_fwd_kernel(NttConst64 K, S
         const InstRef in = src.get(base + (work >> 2));
         const int half = int(work & 1), op = int((work >> 1) & 1);
         uint64_t x[E];
-        ntt_forward<M>(op ? in.b : in.a, in.n, x, sh64, K.fwd, Fp64{}, half ? K.twist : nullptr);
+        ntt_forward<M, Fp64, true>(op ? in.b : in.a, in.n, x, sh64, K.fwd, Fp64{}, K.twist, half ? ~0u : 0u);
         ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(tr + work * H + E * threadIdx.x);
 #pragma unroll
         for (int q = 0; q < E / 2; ++q) dst[q] = make_ulonglong2(x[2 * q], x[2 * q + 1]);
@@ -501,7 +514,7 @@ __global__ __launch_bounds__((1 << M) / E) void ntt64_inv_kernel(NttConst64 K, S
             x[2 * q + 1] = mul_mont64(u.y, v.y);
         }
         __syncthreads();  // every thread has read its part of ta before results overwrite it
-        ntt_inverse<M>(x, ta, H, sh64, K.inv, Fp64{}, K.scale[M], half ? K.untwist : nullptr);
+        ntt_inverse<M, Fp64, true>(x, ta, H, sh64, K.inv, Fp64{}, K.scale[M], K.untwist, half ? ~0u : 0u);
         __syncthreads();
     }
 }
