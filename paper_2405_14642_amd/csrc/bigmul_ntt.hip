@@ -467,6 +467,61 @@ __global__ __launch_bounds__(64 * NW) void ntt_crt_carry_kernel(Coef coef, Src s
     }
 }
 
+// Coefficients to words, one thread per group of 8 coefficients (16-bit
+// positions) over all instances of the round: their column sums are folded
+// into 4 low words L[4 g ..] and a high pair H[g] (positions 4 g + 4, 4 g + 5)
+// in the instance's word area lh + q * lh_stride (L, then H at 4 gmax).
+template <class Src, class Coef>
+__global__ __launch_bounds__(256) void ntt_fold_kernel(Coef coef, Src src, uint64_t base, uint64_t chunk,
+                                                       uint32_t *__restrict__ lh, uint64_t lh_stride, uint32_t gmax) {
+    const uint64_t cnt = chunk_count(src, base, chunk);
+    for (uint64_t item = uint64_t(blockIdx.x) * 256 + threadIdx.x; item < cnt * gmax;
+         item += uint64_t(gridDim.x) * 256) {
+        const uint64_t q = item / gmax;
+        const uint32_t g = uint32_t(item - q * gmax);
+        const uint32_t n = src.get(base + q).n;
+        const uint32_t nout = 4 * n, ngroups = (2 * n + 3) / 4;
+        if (g >= ngroups) continue;
+        // column sums of sum_e c_{8g+e} 2^(16 e), one 64-bit column per word
+        uint64_t col[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t k = 8 * g + e;
+            const uint64_t c = k < nout ? coef(q, k) : 0;
+            const uint64_t v = c << (16 * (e & 1));  // < 2^62
+            col[e >> 1] += uint32_t(v);
+            col[(e >> 1) + 1] += uint32_t(v >> 32);
+        }
+        uint64_t carry = 0;
+        uint32_t R[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const uint64_t sv = col[j] + carry;
+            R[j] = uint32_t(sv);
+            carry = sv >> 32;
+        }
+        uint32_t *L = lh + q * lh_stride;
+        *reinterpret_cast<uint4 *>(L + 4 * g) = make_uint4(R[0], R[1], R[2], R[3]);
+        reinterpret_cast<uint2 *>(L + 4 * gmax)[g] = make_uint2(R[4], R[5]);
+    }
+}
+
+// One workgroup per instance: the product = L + H with the ballot-adder.
+template <int NW, class Src>
+__global__ __launch_bounds__(64 * NW) void ntt_carry_kernel(Src src, uint64_t base, uint64_t chunk,
+                                                            const uint32_t *__restrict__ lh, uint64_t lh_stride,
+                                                            uint32_t gmax) {
+    __shared__ uint32_t summary[NW];
+    const uint64_t cnt = chunk_count(src, base, chunk);
+    for (uint64_t q = blockIdx.x; q < cnt; q += gridDim.x) {
+        const InstRef in = src.get(base + q);
+        const uint32_t nwords = 2 * in.n;
+        const uint32_t *L = lh + q * lh_stride;
+        wg_add_rows<NW>(LHSrc4{L, reinterpret_cast<const uint2 *>(L + 4 * gmax), nwords}, in.c, nwords, summary);
+        __syncthreads();
+    }
+}
+
 // PrimeField64, one workgroup per (instance, operand, half): the forward
 // transform of length H = 2^M of the operand (half 1: twisted by psi^i), in
 // bit-reversed order to tr[work * H ...], work = 4 (instance - base) + 2
@@ -536,14 +591,26 @@ static hipError_t launch_crt_nw(const Coef &coef, const Src &src, uint64_t base,
     return hipGetLastError();
 }
 
-// Workgroup size of the carry by output size: up to 1024, 4096, 32768 words.
+// Coefficients to product for the `chunk`-instance round starting at base;
+// `grid` caps the per-instance workgroups.  Up to 8192 output words one
+// workgroup per instance recombines, folds into LDS and carries (enough
+// instances fill the GPU); above, a wide kernel folds all instances' words
+// into lh (each instance's area of 6 gmax words at lh + q lh_stride, the free
+// second-operand half of its transform scratch) and a workgroup per instance
+// only carries, since few instances of that size would leave CUs idle.
 template <class Src, class Coef>
 static hipError_t launch_crt(const Coef &coef, const Src &src, uint64_t base, uint64_t chunk, uint64_t grid,
-                             uint32_t nmax, hipStream_t st) {
-    const uint32_t ngroups = (2 * nmax + 3) / 4;
-    if (ngroups <= 256) return launch_crt_nw<4>(coef, src, base, chunk, grid, nmax, st);
-    if (ngroups <= 1024) return launch_crt_nw<8>(coef, src, base, chunk, grid, nmax, st);
-    return launch_crt_nw<16>(coef, src, base, chunk, grid, nmax, st);
+                             uint32_t nmax, uint32_t *lh, uint64_t lh_stride, hipStream_t st) {
+    const uint32_t gmax = (2 * nmax + 3) / 4;
+    if (gmax <= 256) return launch_crt_nw<4>(coef, src, base, chunk, grid, nmax, st);
+    if (gmax <= 1024) return launch_crt_nw<8>(coef, src, base, chunk, grid, nmax, st);
+    if (gmax <= 2048) return launch_crt_nw<16>(coef, src, base, chunk, grid, nmax, st);
+    const uint64_t items = std::min(chunk, grid * 65536) * gmax;
+    hipLaunchKernelGGL((ntt_fold_kernel<Src, Coef>), dim3(uint32_t(std::min<uint64_t>((items + 255) / 256, 65536))),
+                       dim3(256), 0, st, coef, src, base, chunk, lh, lh_stride, gmax);
+    hipLaunchKernelGGL((ntt_carry_kernel<16, Src>), dim3(uint32_t(grid)), dim3(1024), 0, st, src, base, chunk, lh,
+                       lh_stride, gmax);
+    return hipGetLastError();
 }
 
 // The three kernels of a product over instances [0, count_max) of src in
@@ -576,7 +643,8 @@ static hipError_t launch_ntt_m(const NttConst &K, const Src &src, uint32_t nmax,
                            chunk, tr);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = launch_crt(coef, src, base, chunk, std::min(c, cap), nmax, st);
+        // words go to the second operand's transforms (slots 4 q + 2, 4 q + 3)
+        e = launch_crt(coef, src, base, chunk, std::min(c, cap), nmax, tr + 2 * L, 4 * uint64_t(L), st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -657,7 +725,9 @@ static hipError_t launch_ntt64_m(const NttConst64 &K, const Src &src, uint32_t n
                            base, chunk, tr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = launch_crt(coef, src, base, chunk, std::min(c, cap), nmax, st);
+        // words go to the second operand's transforms (slots 4 q + 2, 4 q + 3)
+        uint32_t *lh = reinterpret_cast<uint32_t *>(tr + 2 * (uint64_t(1) << M));
+        e = launch_crt(coef, src, base, chunk, std::min(c, cap), nmax, lh, 8 * (uint64_t(1) << M), st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
