@@ -286,10 +286,15 @@ def bench_mul(args, kind):
                                  "peak": round(NTT64_BFLY_PEAK / 1e12, 3), "unit": "T butterflies/s (PF64)",
                                  "frac": round(bfly / (us * 1e-6) / NTT64_BFLY_PEAK, 4)}
             elif name == "mfma":
+                # min(int8 peak, arithmetic intensity x HBM): the operands and
+                # the product (16 n bytes per pair) bound the small sizes
                 ops = 2.0 * batch * (4 * n) ** 2
-                r["roofline"] = {"bound": "mfma", "achieved": round(ops / (us * 1e-6) / 1e12, 1),
-                                 "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "TOP/s (int8)",
-                                 "frac": round(ops / (us * 1e-6) / MFMA_I8_PEAK_OPS, 4)}
+                hbm_roof = ops / (16.0 * n * batch) * HBM_PEAK_GBS * 1e9
+                peak = min(MFMA_I8_PEAK_OPS, hbm_roof)
+                r["roofline"] = {"bound": "mfma" if peak == MFMA_I8_PEAK_OPS else "hbm",
+                                 "achieved": round(ops / (us * 1e-6) / 1e12, 1),
+                                 "peak": round(peak / 1e12, 1), "unit": "TOP/s (int8)",
+                                 "frac": round(ops / (us * 1e-6) / peak, 4)}
             results.setdefault(str(bits), {})[name] = r
             if best is None or us < best[1]:
                 best = (name, us)
