@@ -115,6 +115,27 @@ bi_status bigmul(bi_ctx *ctx, const void *a, const void *b, void *out,
                  uint32_t n_limbs, uint32_t limb_bits, uint64_t batch, int algo, void *stream);
 
 /*
+ * bi_fused -- the paper's fused programs (Section 6.1): several same-length
+ * operations per instance in one kernel, each instance in one workgroup with
+ * its intermediates in LDS (operands read once, the result written once).
+ * All arithmetic is mod 2^(n_limbs * limb_bits), as the paper's add and its
+ * same-length product (the low n limbs of eq. (1)):
+ *   BI_PROG_ADD6  six additions in a chain, a + b, then + a, + b, + a, + b,
+ *                 + a: out = 4 a + 3 b.
+ *   BI_PROG_POLY  out = (a a + b) (b b + b) + a b (four products, three
+ *                 additions).
+ * a, b, out: batch * n_limbs limbs; out must not overlap a or b (BI_EALIAS).
+ * Unknown program: BI_EINVAL; n_limbs * limb_bits > BI_MAX_BITS: BI_ESIZE.
+ */
+typedef enum bi_program {
+    BI_PROG_ADD6 = 1,
+    BI_PROG_POLY = 2
+} bi_program;
+
+bi_status bi_fused(bi_ctx *ctx, int program, const void *a, const void *b, void *out, uint32_t n_limbs,
+                   uint32_t limb_bits, uint64_t batch, void *stream);
+
+/*
  * Ragged batches: instance p has desc[p].n_limbs limbs (>= 1) starting at limb
  * offset desc[p].a_off in a and desc[p].b_off in b; its result starts at limb
  * offset desc[p].out_off in out (n_limbs limbs for bigadd_v, 2 n_limbs for

@@ -12,6 +12,10 @@ What it computes (plain definitions, Section 2 and eq. (1) of Section 3.1):
   beside the paper's same-length sum.
 * ``mul(a, b)``  -> the full 2n-limb product a * b (schoolbook rows); the
   paper's same-length product is its low n limbs.
+* ``add6(a, b)`` and ``poly(a, b)`` -> the fused programs of Section 6.1 in
+  same-length arithmetic (mod 2^(n w)), composed from ``add`` and the low n
+  limbs of ``mul`` in the order the program states: six additions in a chain
+  (a + b, then + a, + b, + a, + b, + a), and (a a + b)(b b + b) + a b.
 
 Arrays are numpy (batch, n) of uint32 or uint64 limbs, little-endian,
 instance-major.  uint64 limbs are processed as twice as many uint32 limbs,
@@ -138,6 +142,26 @@ def mul(a, b, threads: int = 0):
 
 def mul_ragged(pairs, threads: int = 0):
     return get().mul_ragged(pairs, threads)
+
+
+def _mul_low(a, b, threads: int = 0):
+    """Same-length product: the low n limbs of the full product."""
+    return np.ascontiguousarray(get().mul(a, b, threads)[:, : a.shape[1]])
+
+
+def add6(a, b, threads: int = 0):
+    """Six additions in a chain, each mod 2^(n w) (Section 6.1, 6-Add)."""
+    x = add(a, b, threads)[0]
+    for y in (a, b, a, b, a):
+        x = add(x, y, threads)[0]
+    return x
+
+
+def poly(a, b, threads: int = 0):
+    """(a a + b) (b b + b) + a b mod 2^(n w) (Section 6.1, Poly)."""
+    s1 = add(_mul_low(a, a, threads), b, threads)[0]
+    s2 = add(_mul_low(b, b, threads), b, threads)[0]
+    return add(_mul_low(s1, s2, threads), _mul_low(a, b, threads), threads)[0]
 
 
 # ------------------------------------------------------------ conversions

@@ -6,21 +6,23 @@ of addition and multiplication runs in the library's HIP kernels.  Device
 memory and streams come from PyTorch (tensors are used as raw limb buffers).
 
 The names follow the C ABI: ``bigadd``, ``bigmul``, ``bigadd_v``,
-``bigmul_v``; ``Context`` wraps ``bi_ctx``.
+``bigmul_v``, ``fused`` (``bi_fused``); ``Context`` wraps ``bi_ctx``.
 """
 from __future__ import annotations
 
 import ctypes
 import os
 
-__all__ = ["Context", "BigIntError", "bigadd", "bigmul", "bigadd_v", "bigmul_v", "ntt_field", "StreamQueue",
+__all__ = ["Context", "BigIntError", "bigadd", "bigmul", "bigadd_v", "bigmul_v", "fused", "ntt_field", "StreamQueue",
            "DESC_DTYPE", "lib", "library_path",
-           "MUL_AUTO", "MUL_SCHOOL_VALU", "MUL_SCHOOL_MFMA", "MUL_NTT", "MUL_NTT_PF64", "MAX_BITS", "STATUS"]
+           "MUL_AUTO", "MUL_SCHOOL_VALU", "MUL_SCHOOL_MFMA", "MUL_NTT", "MUL_NTT_PF64", "PROG_ADD6", "PROG_POLY", "MAX_BITS",
+           "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libbigint.so")
 
 MUL_AUTO, MUL_SCHOOL_VALU, MUL_SCHOOL_MFMA, MUL_NTT, MUL_NTT_PF64 = 0, 1, 2, 3, 4
+PROG_ADD6, PROG_POLY = 1, 2
 MAX_BITS = 1 << 18
 STATUS = {0: "BI_OK", -1: "BI_EINVAL", -2: "BI_ESIZE", -3: "BI_ELIMB", -4: "BI_EALIAS", -5: "BI_EHIP",
           -6: "BI_ENOMEM", -7: "BI_EALGO", -8: "BI_ENODEV"}
@@ -28,7 +30,7 @@ STATUS = {0: "BI_OK", -1: "BI_EINVAL", -2: "BI_ESIZE", -3: "BI_ELIMB", -4: "BI_E
 EXPORTS = ("bi_ctx_create", "bi_ctx_destroy", "bi_status_str", "bi_last_error",
            "bigadd", "bigmul", "bigadd_v", "bigmul_v", "bi_ntt_field", "bi_autotune", "bi_tune_get",
            "bi_tune_set", "bi_stream_open", "bi_stream_submit", "bi_stream_poll", "bi_stream_wait",
-           "bi_stream_close")
+           "bi_stream_close", "bi_fused")
 NUM_CLASSES = 10
 
 
@@ -78,9 +80,10 @@ def _load():
     L.bi_stream_poll.argtypes = [P, U64, ctypes.POINTER(I)]
     L.bi_stream_wait.argtypes = [P, U64]
     L.bi_stream_close.argtypes = [P]
+    L.bi_fused.argtypes = [P, I, P, P, P, U32, U32, U64, P]
     for f in (L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field, L.bi_autotune,
               L.bi_tune_get, L.bi_tune_set, L.bi_stream_open, L.bi_stream_submit, L.bi_stream_poll,
-              L.bi_stream_wait, L.bi_stream_close):
+              L.bi_stream_wait, L.bi_stream_close, L.bi_fused):
         f.restype = I
     return L
 
@@ -165,6 +168,16 @@ def bigmul(ctx, a, b, out, algo=MUL_AUTO, n_limbs=None, limb_bits=None, batch=No
     n = n_limbs if n_limbs is not None else a.shape[-1]
     bt = batch if batch is not None else (a.numel() // n if n else 0)
     _check(lib.bigmul(_h(ctx), _ptr(a), _ptr(b), _ptr(out), n, lb, bt, int(algo), _stream(stream, a)))
+    return out
+
+
+def fused(ctx, program, a, b, out, n_limbs=None, limb_bits=None, batch=None, stream=None):
+    """out (batch, n) = the fused program (PROG_ADD6: 4a + 3b; PROG_POLY:
+    (a a + b)(b b + b) + a b), mod 2^(n * limb_bits) per instance."""
+    lb = _limb_bits(a, limb_bits)
+    n = n_limbs if n_limbs is not None else a.shape[-1]
+    bt = batch if batch is not None else (a.numel() // n if n else 0)
+    _check(lib.bi_fused(_h(ctx), int(program), _ptr(a), _ptr(b), _ptr(out), n, lb, bt, _stream(stream, a)))
     return out
 
 

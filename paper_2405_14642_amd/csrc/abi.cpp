@@ -163,6 +163,31 @@ bi_status bigmul(bi_ctx *ctx, const void *a, const void *b, void *out, uint32_t 
     return bi::dispatch_bigmul(ctx->impl, a, b, out, n32, batch, algo, static_cast<hipStream_t>(stream));
 }
 
+bi_status bi_fused(bi_ctx *ctx, int program, const void *a, const void *b, void *out, uint32_t n_limbs,
+                   uint32_t limb_bits, uint64_t batch, void *stream) {
+    uint64_t ib = 0;
+    bi_status s = check_shape(n_limbs, limb_bits, batch, &ib);
+    if (s != BI_OK) return s;
+    if (program != BI_PROG_ADD6 && program != BI_PROG_POLY) return fail(BI_EINVAL, "unknown program %d", program);
+    if (batch == 0) return ctx ? BI_OK : fail(BI_EINVAL, "ctx is NULL");
+    if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
+    if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;
+    if ((s = check_ptr(out, limb_bits, "out")) != BI_OK) return s;
+    const uint64_t tot = ib * batch;
+    if (overlaps(out, tot, a, tot) || overlaps(out, tot, b, tot)) return fail(BI_EALIAS, "out overlaps an input");
+    if (!ctx) return fail(BI_EINVAL, "ctx is NULL");
+    const uint32_t n32 = n_limbs * (limb_bits / 32);
+    if (bi::fused_lds_bytes(program, n32) > 160 * 1024)
+        return fail(BI_ESIZE, "program %d does not fit one workgroup's LDS at %u words", program, n32);
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    const hipError_t e = bi::launch_fused(program, static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
+                                          static_cast<uint32_t *>(out), n32, batch, static_cast<hipStream_t>(stream),
+                                          ctx->impl.num_cus);
+    if (e != hipSuccess) return hip_fail(e, "fused program launch");
+    return BI_OK;
+}
+
 bi_status bigadd_v(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t *carry_out, const bi_desc *desc,
                    uint64_t count, uint32_t limb_bits, void *stream) {
     if (limb_bits != 32 && limb_bits != 64) return fail(BI_ELIMB, "limb_bits must be 32 or 64 (got %u)", limb_bits);

@@ -203,6 +203,11 @@ hipError_t launch_bigmul_mfma_big_list(const ListInst &src, uint32_t nmax, uint6
 hipError_t launch_bigmul_mfma(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
                               hipStream_t st, int num_cus);
 
+// Fused programs (BI_PROG_*), one workgroup per instance of n32 words.
+size_t fused_lds_bytes(int program, uint32_t n32);
+hipError_t launch_fused(int program, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
+                        hipStream_t st, int num_cus);
+
 bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint32_t n32, uint64_t batch, int algo,
                           hipStream_t st);
 bi_status dispatch_bigadd_v(Ctx &c, const void *a, const void *b, void *out, uint8_t *carry, const bi_desc *desc,

@@ -26,6 +26,7 @@
 //    L + H with the ballot-adder carry scan.
 #include "bi_common.hpp"
 #include "bi_internal.hpp"
+#include "bi_valu.hpp"
 #include "bi_wgadd.hpp"
 
 namespace bi {
@@ -36,16 +37,6 @@ namespace {
 // loop runs over 4-aligned groups, so B is indexed from -(64 Q + 3) up to
 // n + 64 Q + 1.
 template <int Q> constexpr uint32_t pad_words() { return 64 * Q + 4; }
-
-// acc += a * b (64-bit), cnt += carry out of that addition: one
-// v_mad_u64_u32 (whose carry-out lands in an SGPR pair) and one
-// v_addc_co_u32.  The compiler otherwise splits this into a multiply, an add,
-// a 64-bit compare and a select.
-__device__ __forceinline__ void mac(uint64_t &acc, uint32_t &cnt, uint32_t a, uint32_t b) {
-    uint64_t cc, unused;
-    asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc), "=s"(cc) : "s"(a), "v"(b));
-    asm("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(cnt), "=s"(unused) : "s"(cc));
-}
 
 // Block b of the cost-sorted order: 0, NB-1, 1, NB-2, ... (costs rise toward
 // the middle of the product, Fig. 4).

@@ -1,0 +1,450 @@
+// Fused multi-operation programs (Section 6.1): several same-length
+// operations on one instance inside one workgroup, the intermediates kept in
+// LDS, the operands read from HBM once and the result written once.
+//
+//   BI_PROG_ADD6  six additions, a + b, then + a, + b, + a, + b, + a in turn:
+//                 4 a + 3 b mod 2^N (the paper names only "six additions";
+//                 this alternating chain is the reading taken).
+//   BI_PROG_POLY  (a a + b) (b b + b) + a b mod 2^N: four same-length products
+//                 (the low n limbs of eq. (1)) and three additions.
+//
+// The six additions keep every operand in registers: each lane holds the
+// same 4-word chunks of a, b and the running sum throughout.  Instances of up
+// to 256 words are packed several to a wave (a segmented ballot-adder: the
+// last chunk of an instance neither generates nor propagates into the next),
+// larger ones take a workgroup whose waves exchange one carry summary per
+// addition.  In Poly every addition is a workgroup ballot-adder pass
+// (Section 2) from LDS to LDS.
+// A same-length product is the VALU schoolbook of Section 3 restricted to the
+// output words below n: waves take blocks of 64 Q consecutive coefficients in
+// a snake order (cost grows with the block index), the factor read uniformly
+// from LDS is the scalar operand of v_mad_u64_u32 and the other factor is read
+// as a sliding window from a zero-padded LDS buffer; each lane folds its Q
+// (accumulator, overflow count) pairs into Q low words (written to the result
+// buffer) and a (high, carry) pair, and a ballot-adder pass adds the pairs in
+// place.  Words at or above n are dropped: arithmetic is mod 2^N.
+#include <algorithm>
+#include <atomic>
+
+#include "bi_common.hpp"
+#include "bi_internal.hpp"
+#include "bi_valu.hpp"
+#include "bi_wgadd.hpp"
+
+namespace bi {
+
+namespace {
+
+// Zero words on each side of a buffer used as the windowed factor of a
+// product: a block spans 64 Q coefficients and its step loop runs in groups
+// of 4, so the window reaches 64 Q + 3 words below 0 and 64 Q words above n.
+template <int Q> constexpr uint32_t fused_pad() { return 64 * Q + 4; }
+
+// x = X + Y over n words, in place in LDS.
+struct AddSrc {
+    const uint32_t *X, *Y;
+    uint32_t n;
+    __device__ __forceinline__ void operator()(uint32_t c, uint32_t (&x)[4], uint32_t (&y)[4]) const {
+        const uint4 u = *reinterpret_cast<const uint4 *>(X + 4 * c);
+        const uint4 v = *reinterpret_cast<const uint4 *>(Y + 4 * c);
+        x[0] = u.x; x[1] = u.y; x[2] = u.z; x[3] = u.w;
+        y[0] = v.x; y[1] = v.y; y[2] = v.z; y[3] = v.w;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (4 * c + t >= n) { x[t] = 0; y[t] = 0; }
+    }
+};
+
+struct LdsSink {
+    uint32_t *Z;
+    uint32_t n;
+    __device__ __forceinline__ void operator()(uint32_t c, const uint32_t (&s)[4]) const {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (4 * c + t < n) Z[4 * c + t] = s[t];
+    }
+};
+
+template <int NW>
+__device__ __forceinline__ void wg_add_lds(uint32_t *Z, const uint32_t *X, const uint32_t *Y, uint32_t n,
+                                           uint32_t *summary) {
+    (void)wg_add_rows_sink<NW>(AddSrc{X, Y, n}, LdsSink{Z, n}, n, summary);
+    __syncthreads();
+}
+
+// Low n words of the (Q low words, high / carry pair) per lane group: H of
+// group g belongs at words Q (g + 1) and Q (g + 1) + 1.
+template <int Q>
+struct MulLowSrc {
+    const uint32_t *L;
+    const uint2 *H;
+    uint32_t n;
+    __device__ __forceinline__ void operator()(uint32_t c, uint32_t (&x)[4], uint32_t (&y)[4]) const {
+        const uint4 l = *reinterpret_cast<const uint4 *>(L + 4 * c);
+        x[0] = l.x; x[1] = l.y; x[2] = l.z; x[3] = l.w;
+        if constexpr (Q == 4) {
+            if (c >= 1) {
+                const uint2 h = H[c - 1];
+                y[0] = h.x; y[1] = h.y;
+            }
+        } else {
+            if (c >= 1) {
+                const uint2 h = H[2 * c - 1];
+                y[0] = h.x; y[1] = h.y;
+            }
+            const uint2 h2 = H[2 * c];
+            y[2] = h2.x; y[3] = h2.y;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (4 * c + t >= n) { x[t] = 0; y[t] = 0; }
+    }
+};
+
+// Z = (U V) mod 2^(32 n).  U: read uniformly, words up to n + 2 (zero above
+// n); V: zero at least fused_pad<Q>() words on each side; Z: n words (may not
+// alias U or V); H: scratch of 64 entries per block.
+template <int Q, int NW>
+__device__ __forceinline__ void wg_mul_low(uint32_t *Z, const uint32_t *U, const uint32_t *V, uint2 *H, uint32_t n,
+                                           uint32_t *summary) {
+    constexpr uint32_t span = 64 * Q;
+    const uint32_t lane = lane_id(), wave = wave_in_block();
+    const uint32_t NB = (n + span - 1) / span;
+    for (uint32_t r = 0;; ++r) {
+        const uint32_t slot = (r & 1u) ? (NW - 1 - wave) : wave;  // snake over rising block costs
+        const uint32_t blk = r * NW + slot;
+        if (blk >= NB) break;
+        const uint32_t k0 = blk * span, kl = k0 + Q * lane;
+        const uint32_t ihi = min(k0 + span - 1, n - 1);  // steps i <= k for every coefficient k of the block
+        uint64_t acc[Q];
+        uint32_t cnt[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) { acc[q] = 0; cnt[q] = 0; }
+        // window w[q] = V[kl + q - i] at the current step i
+        uint32_t w[4];
+        auto window = [&](int32_t at, uint32_t (&x)[4]) {
+            if constexpr (Q == 4) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(V + at);
+                x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+            } else {
+                const uint2 v0 = *reinterpret_cast<const uint2 *>(V + at);
+                const uint2 v1 = *reinterpret_cast<const uint2 *>(V + at + 2);
+                x[0] = v0.x; x[1] = v0.y; x[2] = v1.x; x[3] = v1.y;
+            }
+        };
+        window(int32_t(kl), w);
+        for (uint32_t i = 0; i <= ihi; i += 4) {
+            uint32_t x[4];  // V[kl - i - 4 .. kl - i - 1]
+            window(int32_t(kl) - int32_t(i) - 4, x);
+            uint32_t av[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) av[u] = __builtin_amdgcn_readfirstlane(U[i + u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int t = q - u + 4;
+                    mac(acc[q], cnt[q], av[u], t >= 4 ? w[t - 4] : x[t]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) w[q] = x[q];
+        }
+        // position p collects lo(acc[p]) + hi(acc[p-1]) + cnt[p-2] and the running carry
+        uint32_t R[Q + 2];
+        uint64_t carry = 0;
+#pragma unroll
+        for (int p = 0; p < Q + 2; ++p) {
+            uint64_t s = carry;
+            if (p < Q) s += uint32_t(acc[p]);
+            if (p >= 1 && p <= Q) s += uint32_t(acc[p - 1] >> 32);
+            if (p >= 2) s += cnt[p - 2];
+            R[p] = uint32_t(s);
+            carry = s >> 32;
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (kl + q < n) Z[kl + q] = R[q];
+        H[blk * 64 + lane] = make_uint2(R[Q], R[Q + 1]);
+    }
+    __syncthreads();
+    // Z = L + H in place: each chunk is read and written by the same lane
+    (void)wg_add_rows_sink<NW>(MulLowSrc<Q>{Z, H, n}, LdsSink{Z, n}, n, summary);
+    __syncthreads();
+}
+
+__device__ __forceinline__ void load_operand(uint32_t *dst, const uint32_t *src, uint32_t n) {
+    for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) dst[t] = src[t];
+}
+
+}  // namespace
+
+namespace {
+
+// The six additions on one lane's chunk: x = a + b, then + a, + b, + a, + b,
+// + a.  `step` adds y to x given the wave's G / P masks; see the kernels.
+__device__ __forceinline__ void load_chunk(const uint32_t *p, uint32_t n, uint32_t c, bool valid, uint32_t (&x)[4]) {
+    const uint32_t base = 4 * c;
+    if (valid && base + 4 <= n && (reinterpret_cast<uintptr_t>(p + base) & 15) == 0) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(p + base);
+        x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x[t] = (valid && base + t < n) ? p[base + t] : 0u;
+    }
+}
+
+__device__ __forceinline__ void store_chunk(uint32_t *p, uint32_t n, uint32_t c, bool valid, const uint32_t (&x)[4]) {
+    if (!valid) return;
+    const uint32_t base = 4 * c;
+    if (base + 4 <= n && (reinterpret_cast<uintptr_t>(p + base) & 15) == 0) {
+        *reinterpret_cast<uint4 *>(p + base) = make_uint4(x[0], x[1], x[2], x[3]);
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (base + t < n) p[base + t] = x[t];
+    }
+}
+
+}  // namespace
+
+// Instances of up to 256 words (64 chunks): 64 / 2^seg_log instances per
+// wave, lane j of segment s holding chunk j of instance s.  `keep` masks the
+// lanes whose carry may reach the next lane: not an instance's last chunk
+// (its carry out is dropped, mod 2^N) and not past the instance's end.
+__global__ __launch_bounds__(256) void fused_add6_packed_kernel(const uint32_t *__restrict__ a,
+                                                                const uint32_t *__restrict__ b,
+                                                                uint32_t *__restrict__ out, uint32_t n,
+                                                                uint64_t batch, uint32_t seg_log) {
+    const uint32_t lane = lane_id(), wave = wave_in_block();
+    const uint32_t nchunks = (n + 3) / 4, ipw = 64u >> seg_log;
+    const uint32_t j = lane & ((1u << seg_log) - 1u);
+    for (uint64_t g = uint64_t(blockIdx.x) * 4 + wave; g * ipw < batch; g += uint64_t(gridDim.x) * 4) {
+        const uint64_t inst = g * ipw + (lane >> seg_log);
+        const bool valid = inst < batch && j < nchunks;
+        uint32_t A[4], B[4], X[4];
+        load_chunk(a + inst * n, n, j, valid, A);
+        load_chunk(b + inst * n, n, j, valid, B);
+        const uint64_t keep = ballot(valid && j + 1 < nchunks);
+        auto add = [&](const uint32_t (&y)[4]) {
+            uint32_t s[4];
+            const uint32_t gen = add_words<4>(X, y, s);
+            const uint64_t G = ballot(gen != 0) & keep, P = ballot(all_ones<4>(s)) & keep;
+            add_carry_words<4>(s, uint32_t(wave_carry(G, P, 0).into >> lane) & 1u);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) X[t] = s[t];
+        };
+#pragma unroll
+        for (int t = 0; t < 4; ++t) X[t] = A[t];
+        add(B);
+        add(A);
+        add(B);
+        add(A);
+        add(B);
+        add(A);
+        store_chunk(out + inst * n, n, j, valid, X);
+    }
+}
+
+// Instances above 256 words: one workgroup of NW waves, wave w holding rows
+// w R .. w R + R - 1 (64 chunks each) in registers.  Per addition each wave
+// scans its rows, publishes (carry out, all-propagate) in one LDS word,
+// and after one barrier applies the carry from the waves below; the summary
+// words alternate between two arrays so one barrier per addition suffices.
+template <int NW, int R>
+__global__ __launch_bounds__(64 * NW) void fused_add6_rows_kernel(const uint32_t *__restrict__ a,
+                                                                  const uint32_t *__restrict__ b,
+                                                                  uint32_t *__restrict__ out, uint32_t n,
+                                                                  uint64_t batch) {
+    __shared__ uint32_t summary[2][NW];
+    const uint32_t lane = lane_id(), w = wave_in_block();
+    const uint32_t nchunks = (n + 3) / 4;
+    for (uint64_t q = blockIdx.x; q < batch; q += gridDim.x) {
+        uint32_t A[R][4], B[R][4], X[R][4];
+        uint64_t vmask[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t row = w * R + r, c = row * 64 + lane;
+            const bool valid = c < nchunks;
+            load_chunk(a + q * n, n, c, valid, A[r]);
+            load_chunk(b + q * n, n, c, valid, B[r]);
+            vmask[r] = ballot(valid);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) X[r][t] = A[r][t];
+        }
+        uint32_t par = 0;
+        auto add = [&](const uint32_t (&y)[R][4]) {
+            uint32_t s[R][4];
+            uint64_t G[R], P[R];
+            uint32_t cin = 0, allp = 1;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t gen = add_words<4>(X[r], y[r], s[r]);
+                G[r] = ballot(gen != 0) & vmask[r];
+                P[r] = ballot(all_ones<4>(s[r])) & vmask[r];
+                cin = wave_carry(G[r], P[r], cin).out;  // past the last chunk: dropped (mod 2^N)
+                allp &= P[r] == vmask[r] ? 1u : 0u;
+            }
+            if (lane == 0) summary[par][w] = cin | (allp << 1);
+            __syncthreads();
+            cin = 0;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) {
+                const uint32_t sv = summary[par][v];
+                if (v < int(w)) cin = (sv & 1u) | ((sv >> 1) & cin);
+            }
+            par ^= 1u;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const WaveCarry wc = wave_carry(G[r], P[r], cin);
+                add_carry_words<4>(s[r], uint32_t(wc.into >> lane) & 1u);
+                cin = wc.out;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) X[r][t] = s[r][t];
+            }
+        };
+        add(B);
+        add(A);
+        add(B);
+        add(A);
+        add(B);
+        add(A);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t c = (w * R + r) * 64 + lane;
+            store_chunk(out + q * n, n, c, c < nchunks, X[r]);
+        }
+    }
+}
+
+// LDS of the polynomial program: four padded buffers (a, b and two
+// intermediates at most are live at once) and the products' H scratch.
+struct PolyLayout {
+    uint32_t stride, pad, h_off, sum_off, words;
+};
+
+static PolyLayout poly_layout(uint32_t n, int Q, int NW) {
+    PolyLayout l;
+    l.pad = 64 * Q + 4;
+    l.stride = ((n + 3) & ~3u) + 2 * l.pad;
+    const uint32_t NB = (n + 64 * Q - 1) / (64 * Q);
+    l.h_off = 4 * l.stride;
+    l.sum_off = l.h_off + 2 * NB * 64;
+    l.words = l.sum_off + NW;
+    return l;
+}
+
+template <int Q, int NW>
+__global__ __launch_bounds__(64 * NW) void fused_poly_kernel(const uint32_t *__restrict__ a,
+                                                             const uint32_t *__restrict__ b, uint32_t *__restrict__ out,
+                                                             uint32_t n, uint64_t batch) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    constexpr uint32_t pad = fused_pad<Q>();
+    const uint32_t stride = ((n + 3) & ~3u) + 2 * pad;
+    const uint32_t NB = (n + 64 * Q - 1) / (64 * Q);
+    uint32_t *buf[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) buf[k] = lds + k * stride + pad;
+    uint2 *H = reinterpret_cast<uint2 *>(lds + 4 * stride);
+    uint32_t *summary = lds + 4 * stride + 2 * NB * 64;
+    // pads and tails are zero for the whole launch: results only write [0, n)
+    for (uint32_t t = threadIdx.x; t < 4 * stride; t += 64 * NW) lds[t] = 0;
+    __syncthreads();
+    for (uint64_t q = blockIdx.x; q < batch; q += gridDim.x) {
+        uint32_t *A = buf[0], *B = buf[1], *Z1 = buf[2], *Z2 = buf[3];
+        load_operand(A, a + q * n, n);
+        load_operand(B, b + q * n, n);
+        __syncthreads();
+        wg_mul_low<Q, NW>(Z1, A, B, H, n, summary);  // a b
+        wg_mul_low<Q, NW>(Z2, A, A, H, n, summary);  // a a
+        wg_add_lds<NW>(Z2, Z2, B, n, summary);        // a a + b
+        wg_mul_low<Q, NW>(A, B, B, H, n, summary);    // b b (a is no longer needed)
+        wg_add_lds<NW>(A, A, B, n, summary);          // b b + b
+        wg_mul_low<Q, NW>(B, Z2, A, H, n, summary);   // (a a + b)(b b + b)
+        wg_add_rows<NW>(AddSrc{B, Z1, n}, out + q * n, n, summary);
+        __syncthreads();
+    }
+}
+
+namespace {
+
+// Waves per workgroup for n words: enough 64-chunk rows (six additions) or
+// block pairs (products) to give each wave work, a power of two up to 16.
+uint32_t pow2_waves(uint32_t units) {
+    return units >= 16 ? 16 : units >= 8 ? 8 : units >= 4 ? 4 : units >= 2 ? 2 : 1;
+}
+
+// Persistent grid of resident workgroups (each loops over instances).  One
+// instantiation per kernel, so each keeps its own occupancy record.
+using FusedKernel = void (*)(const uint32_t *, const uint32_t *, uint32_t *, uint32_t, uint64_t);
+template <FusedKernel kernel>
+hipError_t launch_persistent(uint32_t threads, size_t lds, const uint32_t *a, const uint32_t *b, uint32_t *c,
+                             uint32_t n, uint64_t batch, hipStream_t st, int num_cus) {
+    const void *fn = reinterpret_cast<const void *>(kernel);
+    // ((LDS bytes + 1) << 32 | resident workgroups per CU) of the last launch
+    // of this kernel (0: none yet)
+    static std::atomic<uint64_t> occ{0};
+    uint64_t o = occ.load(std::memory_order_relaxed);
+    if ((o >> 32) != lds + 1) {
+        hipError_t e = hipSuccess;
+        if (lds > 0) {  // kernels with dynamic LDS may use all of a CU's
+            e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) return e;
+        }
+        int nblk = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, fn, int(threads), lds);
+        if (e != hipSuccess) return e;
+        o = (uint64_t(lds + 1) << 32) | uint32_t(nblk < 1 ? 1 : nblk);
+        occ.store(o, std::memory_order_relaxed);
+    }
+    const uint64_t cap = uint64_t(uint32_t(o)) * uint64_t(num_cus > 0 ? num_cus : 1);
+    const uint32_t grid = uint32_t(batch < cap ? batch : cap);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, st, a, b, c, n, batch);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t fused_lds_bytes(int program, uint32_t n32) {
+    if (program == BI_PROG_ADD6) return 0;  // registers only
+    const int Q = n32 > 4096 ? 4 : 2;
+    const uint32_t NB = (n32 + 64 * Q - 1) / (64 * Q);
+    return 4ull * poly_layout(n32, Q, int(pow2_waves((NB + 1) / 2))).words;
+}
+
+hipError_t launch_fused(int program, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n, uint64_t batch,
+                        hipStream_t st, int num_cus) {
+    if (batch == 0) return hipSuccess;
+    if (program == BI_PROG_ADD6) {
+        const uint32_t nchunks = (n + 3) / 4, rows = (nchunks + 63) / 64;
+        if (rows == 1) {
+            uint32_t seg_log = 0;
+            while ((1u << seg_log) < nchunks) ++seg_log;
+            const uint64_t waves = (batch + (64u >> seg_log) - 1) / (64u >> seg_log);
+            const uint64_t cap = uint64_t(num_cus > 0 ? num_cus : 1) * 32;
+            const uint32_t grid = uint32_t(std::min((waves + 3) / 4, cap));
+            hipLaunchKernelGGL(fused_add6_packed_kernel, dim3(grid), dim3(256), 0, st, a, b, c, n, batch, seg_log);
+            return hipGetLastError();
+        }
+        const uint32_t nw = pow2_waves(rows), r = (rows + nw - 1) / nw;
+#define BI_ADD6_CASE(W, RR) \
+    if (nw == W && r == RR) return launch_persistent<&fused_add6_rows_kernel<W, RR>>(64 * W, 0, a, b, c, n, batch, st, num_cus);
+        BI_ADD6_CASE(2, 1) BI_ADD6_CASE(2, 2) BI_ADD6_CASE(4, 1) BI_ADD6_CASE(4, 2)
+        BI_ADD6_CASE(8, 1) BI_ADD6_CASE(8, 2) BI_ADD6_CASE(16, 1) BI_ADD6_CASE(16, 2)
+#undef BI_ADD6_CASE
+        return hipErrorInvalidValue;
+    }
+    const int Q = n > 4096 ? 4 : 2;
+    const uint32_t NB = (n + 64 * Q - 1) / (64 * Q);
+    const uint32_t nw = pow2_waves((NB + 1) / 2);
+    const size_t lds = 4ull * poly_layout(n, Q, int(nw)).words;
+#define BI_POLY_CASE(QQ, W)                                                                                         \
+    if (Q == QQ && nw == W)                                                                                         \
+        return launch_persistent<&fused_poly_kernel<QQ, W>>(64 * W, lds, a, b, c, n, batch, st, num_cus);
+    BI_POLY_CASE(2, 1) BI_POLY_CASE(2, 2) BI_POLY_CASE(2, 4) BI_POLY_CASE(2, 8) BI_POLY_CASE(2, 16)
+    BI_POLY_CASE(4, 1) BI_POLY_CASE(4, 2) BI_POLY_CASE(4, 4) BI_POLY_CASE(4, 8) BI_POLY_CASE(4, 16)
+#undef BI_POLY_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace bi

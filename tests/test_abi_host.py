@@ -82,6 +82,26 @@ def test_bigmul_validation(B, args, status):
     assert st == status, B.lib.bi_last_error()
 
 
+@pytest.mark.parametrize("args,status", [
+    (dict(program=0), -1),
+    (dict(program=3), -1),
+    (dict(limb_bits=16), -3),
+    (dict(n=0), -1),
+    (dict(n=8193), -2),
+    (dict(n=4097, limb_bits=64), -2),
+    (dict(out=FAKE), -4),                         # the result may not alias a
+    (dict(out=FAKE + (1 << 24) - 8), -4),         # overlaps b
+    (dict(b=FAKE + 2), -3),
+    (dict(), -1),                                 # all valid, but ctx is NULL
+    (dict(program=2), -1),
+])
+def test_fused_validation(B, args, status):
+    p = dict(program=1, a=FAKE, b=FAKE + (1 << 24), out=FAKE + (2 << 24), n=4, limb_bits=32, batch=8)
+    p.update(args)
+    st = B.lib.bi_fused(None, p["program"], p["a"], p["b"], p["out"], p["n"], p["limb_bits"], p["batch"], None)
+    assert st == status, B.lib.bi_last_error()
+
+
 def test_empty_batch_needs_only_ctx(B):
     assert B.lib.bigadd(None, None, None, None, None, 4, 32, 0, None) == -1
     assert B.lib.bigmul(None, None, None, None, 4, 32, 0, 0, None) == -1

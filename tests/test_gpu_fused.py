@@ -1,0 +1,95 @@
+"""Fused programs of Section 6.1 (bi_fused): 6-Add and Poly in one workgroup
+per instance, bit-exact against the oracle's compositions of add and the
+same-length product."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+PROGRAMS = {"add6": 1, "poly": 2}
+
+
+@pytest.fixture(scope="module")
+def B():
+    import paper_2405_14642_amd as B
+    return B
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def want(orc, name, a, b):
+    return O.add6(a, b) if name == "add6" else O.poly(a, b)
+
+
+def run(B, ctx, prog, a, b):
+    A, Bt = G.to_dev(a), G.to_dev(b)
+    out = G.empty_dev(a.shape, a.dtype)
+    B.fused(ctx, prog, A, Bt, out)
+    G.sync()
+    return G.from_dev(out, a.dtype)
+
+
+def operands(rng, batch, n, dt=np.uint32):
+    info = np.iinfo(dt)
+    a = rng.integers(0, info.max, (batch, n), dtype=dt, endpoint=True)
+    b = rng.integers(0, info.max, (batch, n), dtype=dt, endpoint=True)
+    a[0] = b[0] = info.max                       # every carry chain runs the full length
+    if batch > 1:
+        a[1] = info.max
+        b[1] = 0
+        b[1, 0] = 1                               # all-ones + 1 wraps to 0
+    if batch > 2:
+        a[2] = 0                                  # zero operand
+    if batch > 3:
+        a[3] = info.max // 255 * 0x80
+        b[3] = info.max // 255 * 0x7F
+    return a, b
+
+
+SIZES = [1, 2, 3, 4, 5, 7, 8, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1000,
+         1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192]
+
+
+@pytest.mark.parametrize("name", list(PROGRAMS))
+@pytest.mark.parametrize("n", SIZES)
+def test_sizes(B, ctx, orc, name, n):
+    rng = np.random.default_rng(n)
+    batch = 6 if n <= 1024 else 3
+    a, b = operands(rng, batch, n)
+    got = run(B, ctx, PROGRAMS[name], a, b)
+    exp = want(orc, name, a, b)
+    bad = np.nonzero((got != exp).any(axis=1))[0]
+    assert bad.size == 0, f"{name} n={n}: rows {bad.tolist()} differ"
+
+
+@pytest.mark.parametrize("name", list(PROGRAMS))
+def test_u64_limbs(B, ctx, orc, name):
+    rng = np.random.default_rng(64)
+    for n in (1, 3, 64, 513, 4096):
+        a, b = operands(rng, 4, n, np.uint64)
+        got = run(B, ctx, PROGRAMS[name], a, b)
+        assert (got == want(orc, name, a, b)).all(), (name, n)
+
+
+@pytest.mark.parametrize("name", list(PROGRAMS))
+@pytest.mark.parametrize("bits", [1 << 12, 1 << 15, 1 << 18])
+def test_paper_workload_sampled(B, ctx, orc, name, bits):
+    """NumBits x NumInsts = 2^32 (the paper's batches, u64 limbs); every
+    instance runs, 8 sampled instances are checked against the oracle."""
+    n = bits // 64
+    batch = (1 << 32) // bits
+    rng = np.random.default_rng(bits)
+    a, b = operands(rng, batch, n, np.uint64)
+    got = run(B, ctx, PROGRAMS[name], a, b)
+    pick = np.unique(np.concatenate([[0, 1, 2, 3, batch - 1], rng.integers(0, batch, 3)]))
+    assert (got[pick] == want(orc, name, a[pick], b[pick])).all(), (name, bits)

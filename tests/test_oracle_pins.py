@@ -100,3 +100,25 @@ def test_planted_mistake_is_caught(name):
             except AssertionError:
                 caught.append(check.__name__)
         assert caught, f"planted mistake {name} passed every pin"
+
+
+@pytest.mark.parametrize("dt", [np.uint32, np.uint64])
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 33, 128])
+def test_fused_programs_against_python(dt, n):
+    """Section 6.1 programs: 6-Add equals the closed form 4a + 3b mod 2^N (a
+    different computation from the oracle's chain of additions), Poly equals
+    Python's own bignum arithmetic; carry-heavy rows (all ones) included."""
+    rng = np.random.default_rng(n)
+    info = np.iinfo(dt)
+    a = rng.integers(0, info.max, (4, n), dtype=dt, endpoint=True)
+    b = rng.integers(0, info.max, (4, n), dtype=dt, endpoint=True)
+    a[0] = b[0] = info.max
+    a[1] = info.max
+    b[1] = 0
+    b[1, 0] = 1
+    M = 1 << (n * 8 * np.dtype(dt).itemsize)
+    got6, gotp = O.add6(a, b), O.poly(a, b)
+    for i in range(a.shape[0]):
+        A, B = O.to_int(a[i]), O.to_int(b[i])
+        assert O.to_int(got6[i]) == (4 * A + 3 * B) % M
+        assert O.to_int(gotp[i]) == ((A * A + B) * (B * B + B) + A * B) % M
