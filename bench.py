@@ -483,8 +483,8 @@ def cpu_baseline_stream(args, a, b, off, nn):
 
 def bench_fused(args):
     """The paper's fused programs (Section 6.1) over the addition sweep's
-    batches (NumBits x NumInsts = 2^32, u64 limbs): 1-Add (bigadd), 6-Add and
-    Poly, one launch each.  6-Add is memory-bound: 3 N/8 bytes per instance
+    batches (NumBits x NumInsts = 2^32, u64 limbs): 1-Add (bigadd), 6-Add,
+    Poly and the same-length product 1-Mul (Figs. 4-5), one launch each.  6-Add is memory-bound: 3 N/8 bytes per instance
     (two operands in, one result out) against HBM.  Poly is four same-length
     VALU products of n (n + 1) / 2 u32 terms each (n 32-bit words) against the
     VALU multiply-accumulate peak."""
@@ -529,6 +529,7 @@ def bench_fused(args):
         us1 = timed(lambda: B.bigadd(ctx, A, Bt, out, None, n_limbs=n, limb_bits=64, batch=batch, stream=cs))
         us6 = timed(lambda: B.fused(ctx, B.PROG_ADD6, A, Bt, out, n_limbs=n, limb_bits=64, batch=batch, stream=cs))
         usp = timed(lambda: B.fused(ctx, B.PROG_POLY, A, Bt, out, n_limbs=n, limb_bits=64, batch=batch, stream=cs))
+        usm = timed(lambda: B.fused(ctx, B.PROG_MUL_LOW, A, Bt, out, n_limbs=n, limb_bits=64, batch=batch, stream=cs))
         nbytes = 3 * batch * bits // 8
         n32 = 2 * n
         macs = 4.0 * batch * n32 * (n32 + 1) / 2
@@ -537,7 +538,11 @@ def bench_fused(args):
             "instances": batch, "add1_us": round(us1, 2), "add6_us": round(us6, 2),
             "add6_over_add1": round(us6 / us1, 3), "add6_GB_per_s": round(gbs, 1),
             "add6_hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "poly_us": round(usp, 2),
-            "poly_u32_macs_per_s": macs / (usp * 1e-6),
+            "poly_u32_macs_per_s": macs / (usp * 1e-6), "mul_low_us": round(usm, 2),
+            "poly_over_mul_low": round(usp / usm, 3),
+            "mul_low_roofline": {"bound": "alu", "achieved": round(macs / 4 / (usm * 1e-6) / 1e12, 3),
+                                 "peak": round(VALU_MAC_PEAK / 1e12, 3), "unit": "T u32-MAC/s",
+                                 "frac": round(macs / 4 / (usm * 1e-6) / VALU_MAC_PEAK, 4)},
             "poly_roofline": {"bound": "alu", "achieved": round(macs / (usp * 1e-6) / 1e12, 3),
                               "peak": round(VALU_MAC_PEAK / 1e12, 3), "unit": "T u32-MAC/s",
                               "frac": round(macs / (usp * 1e-6) / VALU_MAC_PEAK, 4)}}

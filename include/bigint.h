@@ -124,12 +124,16 @@ bi_status bigmul(bi_ctx *ctx, const void *a, const void *b, void *out,
  *                 + a: out = 4 a + 3 b.
  *   BI_PROG_POLY  out = (a a + b) (b b + b) + a b (four products, three
  *                 additions).
+ *   BI_PROG_MUL_LOW  out = a b: the paper's same-length product (Section 3,
+ *                 Figs. 4-5), the low n limbs of eq. (1), computing only the
+ *                 coefficients below n (about half the work of bigmul).
  * a, b, out: batch * n_limbs limbs; out must not overlap a or b (BI_EALIAS).
  * Unknown program: BI_EINVAL; n_limbs * limb_bits > BI_MAX_BITS: BI_ESIZE.
  */
 typedef enum bi_program {
     BI_PROG_ADD6 = 1,
-    BI_PROG_POLY = 2
+    BI_PROG_POLY = 2,
+    BI_PROG_MUL_LOW = 3
 } bi_program;
 
 bi_status bi_fused(bi_ctx *ctx, int program, const void *a, const void *b, void *out, uint32_t n_limbs,

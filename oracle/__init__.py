@@ -12,6 +12,8 @@ What it computes (plain definitions, Section 2 and eq. (1) of Section 3.1):
   beside the paper's same-length sum.
 * ``mul(a, b)``  -> the full 2n-limb product a * b (schoolbook rows); the
   paper's same-length product is its low n limbs.
+* ``mul_low(a, b)`` -> the paper's same-length product (Figs. 4-5): the low
+  n limbs of ``mul``.
 * ``add6(a, b)`` and ``poly(a, b)`` -> the fused programs of Section 6.1 in
   same-length arithmetic (mod 2^(n w)), composed from ``add`` and the low n
   limbs of ``mul`` in the order the program states: six additions in a chain
@@ -144,9 +146,12 @@ def mul_ragged(pairs, threads: int = 0):
     return get().mul_ragged(pairs, threads)
 
 
-def _mul_low(a, b, threads: int = 0):
+def mul_low(a, b, threads: int = 0):
     """Same-length product: the low n limbs of the full product."""
     return np.ascontiguousarray(get().mul(a, b, threads)[:, : a.shape[1]])
+
+
+_mul_low = mul_low
 
 
 def add6(a, b, threads: int = 0):

@@ -15,14 +15,14 @@ import os
 
 __all__ = ["Context", "BigIntError", "bigadd", "bigmul", "bigadd_v", "bigmul_v", "fused", "ntt_field", "StreamQueue",
            "DESC_DTYPE", "lib", "library_path",
-           "MUL_AUTO", "MUL_SCHOOL_VALU", "MUL_SCHOOL_MFMA", "MUL_NTT", "MUL_NTT_PF64", "PROG_ADD6", "PROG_POLY", "MAX_BITS",
+           "MUL_AUTO", "MUL_SCHOOL_VALU", "MUL_SCHOOL_MFMA", "MUL_NTT", "MUL_NTT_PF64", "PROG_ADD6", "PROG_POLY", "PROG_MUL_LOW", "MAX_BITS",
            "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libbigint.so")
 
 MUL_AUTO, MUL_SCHOOL_VALU, MUL_SCHOOL_MFMA, MUL_NTT, MUL_NTT_PF64 = 0, 1, 2, 3, 4
-PROG_ADD6, PROG_POLY = 1, 2
+PROG_ADD6, PROG_POLY, PROG_MUL_LOW = 1, 2, 3
 MAX_BITS = 1 << 18
 STATUS = {0: "BI_OK", -1: "BI_EINVAL", -2: "BI_ESIZE", -3: "BI_ELIMB", -4: "BI_EALIAS", -5: "BI_EHIP",
           -6: "BI_ENOMEM", -7: "BI_EALGO", -8: "BI_ENODEV"}
@@ -173,7 +173,8 @@ def bigmul(ctx, a, b, out, algo=MUL_AUTO, n_limbs=None, limb_bits=None, batch=No
 
 def fused(ctx, program, a, b, out, n_limbs=None, limb_bits=None, batch=None, stream=None):
     """out (batch, n) = the fused program (PROG_ADD6: 4a + 3b; PROG_POLY:
-    (a a + b)(b b + b) + a b), mod 2^(n * limb_bits) per instance."""
+    (a a + b)(b b + b) + a b; PROG_MUL_LOW: a b), mod 2^(n * limb_bits) per
+    instance."""
     lb = _limb_bits(a, limb_bits)
     n = n_limbs if n_limbs is not None else a.shape[-1]
     bt = batch if batch is not None else (a.numel() // n if n else 0)

@@ -168,7 +168,7 @@ bi_status bi_fused(bi_ctx *ctx, int program, const void *a, const void *b, void 
     uint64_t ib = 0;
     bi_status s = check_shape(n_limbs, limb_bits, batch, &ib);
     if (s != BI_OK) return s;
-    if (program != BI_PROG_ADD6 && program != BI_PROG_POLY) return fail(BI_EINVAL, "unknown program %d", program);
+    if (program < BI_PROG_ADD6 || program > BI_PROG_MUL_LOW) return fail(BI_EINVAL, "unknown program %d", program);
     if (batch == 0) return ctx ? BI_OK : fail(BI_EINVAL, "ctx is NULL");
     if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
     if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;

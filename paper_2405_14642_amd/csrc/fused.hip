@@ -7,6 +7,8 @@
 //                 this alternating chain is the reading taken).
 //   BI_PROG_POLY  (a a + b) (b b + b) + a b mod 2^N: four same-length products
 //                 (the low n limbs of eq. (1)) and three additions.
+//   BI_PROG_MUL_LOW  a b mod 2^N alone: the paper's same-length product of
+//                 Figs. 4-5 (only the coefficients below n are formed).
 //
 // The six additions keep every operand in registers: each lane holds the
 // same 4-word chunks of a, b and the running sum throughout.  Instances of up
@@ -366,6 +368,31 @@ __global__ __launch_bounds__(64 * NW) void fused_poly_kernel(const uint32_t *__r
     }
 }
 
+// Same-length product alone: a and b in two padded buffers, the result
+// formed in a third and copied out.
+template <int Q, int NW>
+__global__ __launch_bounds__(64 * NW) void fused_mullow_kernel(const uint32_t *__restrict__ a,
+                                                               const uint32_t *__restrict__ b,
+                                                               uint32_t *__restrict__ out, uint32_t n, uint64_t batch) {
+    extern __shared__ __align__(16) uint32_t lds[];
+    constexpr uint32_t pad = fused_pad<Q>();
+    const uint32_t stride = ((n + 3) & ~3u) + 2 * pad;
+    const uint32_t NB = (n + 64 * Q - 1) / (64 * Q);
+    uint32_t *U = lds + pad, *V = U + stride, *Z = V + stride;
+    uint2 *H = reinterpret_cast<uint2 *>(lds + 3 * stride);
+    uint32_t *summary = lds + 3 * stride + 2 * NB * 64;
+    for (uint32_t t = threadIdx.x; t < 3 * stride; t += 64 * NW) lds[t] = 0;
+    __syncthreads();
+    for (uint64_t q = blockIdx.x; q < batch; q += gridDim.x) {
+        load_operand(U, a + q * n, n);
+        load_operand(V, b + q * n, n);
+        __syncthreads();
+        wg_mul_low<Q, NW>(Z, U, V, H, n, summary);
+        for (uint32_t t = threadIdx.x; t < n; t += 64 * NW) out[q * n + t] = Z[t];
+        __syncthreads();
+    }
+}
+
 namespace {
 
 // Waves per workgroup for n words: enough 64-chunk rows (six additions) or
@@ -405,11 +432,20 @@ hipError_t launch_persistent(uint32_t threads, size_t lds, const uint32_t *a, co
 
 }  // namespace
 
+// LDS words of the same-length product: three padded buffers, H, summary.
+static uint32_t mullow_lds_words(uint32_t n, int Q, int NW) {
+    const uint32_t stride = ((n + 3) & ~3u) + 2 * (64 * Q + 4);
+    const uint32_t NB = (n + 64 * Q - 1) / (64 * Q);
+    return 3 * stride + 2 * NB * 64 + NW;
+}
+
 size_t fused_lds_bytes(int program, uint32_t n32) {
     if (program == BI_PROG_ADD6) return 0;  // registers only
     const int Q = n32 > 4096 ? 4 : 2;
     const uint32_t NB = (n32 + 64 * Q - 1) / (64 * Q);
-    return 4ull * poly_layout(n32, Q, int(pow2_waves((NB + 1) / 2))).words;
+    const int nw = int(pow2_waves((NB + 1) / 2));
+    if (program == BI_PROG_MUL_LOW) return 4ull * mullow_lds_words(n32, Q, nw);
+    return 4ull * poly_layout(n32, Q, nw).words;
 }
 
 hipError_t launch_fused(int program, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n, uint64_t batch,
@@ -437,6 +473,16 @@ hipError_t launch_fused(int program, const uint32_t *a, const uint32_t *b, uint3
     const int Q = n > 4096 ? 4 : 2;
     const uint32_t NB = (n + 64 * Q - 1) / (64 * Q);
     const uint32_t nw = pow2_waves((NB + 1) / 2);
+    if (program == BI_PROG_MUL_LOW) {
+        const size_t lds = 4ull * mullow_lds_words(n, Q, int(nw));
+#define BI_MULLOW_CASE(QQ, W)                                                                                       \
+    if (Q == QQ && nw == W)                                                                                         \
+        return launch_persistent<&fused_mullow_kernel<QQ, W>>(64 * W, lds, a, b, c, n, batch, st, num_cus);
+        BI_MULLOW_CASE(2, 1) BI_MULLOW_CASE(2, 2) BI_MULLOW_CASE(2, 4) BI_MULLOW_CASE(2, 8) BI_MULLOW_CASE(2, 16)
+        BI_MULLOW_CASE(4, 1) BI_MULLOW_CASE(4, 2) BI_MULLOW_CASE(4, 4) BI_MULLOW_CASE(4, 8) BI_MULLOW_CASE(4, 16)
+#undef BI_MULLOW_CASE
+        return hipErrorInvalidValue;
+    }
     const size_t lds = 4ull * poly_layout(n, Q, int(nw)).words;
 #define BI_POLY_CASE(QQ, W)                                                                                         \
     if (Q == QQ && nw == W)                                                                                         \

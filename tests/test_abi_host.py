@@ -84,7 +84,7 @@ def test_bigmul_validation(B, args, status):
 
 @pytest.mark.parametrize("args,status", [
     (dict(program=0), -1),
-    (dict(program=3), -1),
+    (dict(program=4), -1),
     (dict(limb_bits=16), -3),
     (dict(n=0), -1),
     (dict(n=8193), -2),
@@ -94,6 +94,7 @@ def test_bigmul_validation(B, args, status):
     (dict(b=FAKE + 2), -3),
     (dict(), -1),                                 # all valid, but ctx is NULL
     (dict(program=2), -1),
+    (dict(program=3), -1),
 ])
 def test_fused_validation(B, args, status):
     p = dict(program=1, a=FAKE, b=FAKE + (1 << 24), out=FAKE + (2 << 24), n=4, limb_bits=32, batch=8)

@@ -11,7 +11,7 @@ from tests import gpu_util as G
 
 pytestmark = pytest.mark.gpu
 
-PROGRAMS = {"add6": 1, "poly": 2}
+PROGRAMS = {"add6": 1, "poly": 2, "mullow": 3}
 
 
 @pytest.fixture(scope="module")
@@ -28,7 +28,7 @@ def ctx(B):
 
 
 def want(orc, name, a, b):
-    return O.add6(a, b) if name == "add6" else O.poly(a, b)
+    return {"add6": O.add6, "poly": O.poly, "mullow": O.mul_low}[name](a, b)
 
 
 def run(B, ctx, prog, a, b):

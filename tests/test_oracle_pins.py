@@ -117,8 +117,9 @@ def test_fused_programs_against_python(dt, n):
     b[1] = 0
     b[1, 0] = 1
     M = 1 << (n * 8 * np.dtype(dt).itemsize)
-    got6, gotp = O.add6(a, b), O.poly(a, b)
+    got6, gotp, gotm = O.add6(a, b), O.poly(a, b), O.mul_low(a, b)
     for i in range(a.shape[0]):
         A, B = O.to_int(a[i]), O.to_int(b[i])
+        assert O.to_int(gotm[i]) == (A * B) % M
         assert O.to_int(got6[i]) == (4 * A + 3 * B) % M
         assert O.to_int(gotp[i]) == ((A * A + B) * (B * B + B) + A * B) % M
