@@ -462,11 +462,15 @@ hipError_t launch_fused(int program, const uint32_t *a, const uint32_t *b, uint3
             hipLaunchKernelGGL(fused_add6_packed_kernel, dim3(grid), dim3(256), 0, st, a, b, c, n, batch, seg_log);
             return hipGetLastError();
         }
-        const uint32_t nw = pow2_waves(rows), r = (rows + nw - 1) / nw;
+        // up to 4 rows per lane group: fewer waves per instance, more
+        // instances resident per CU to hide the per-addition barrier
+        uint32_t nw = 1;
+        while (4 * nw < rows) nw *= 2;
+        const uint32_t r = (rows + nw - 1) / nw;
 #define BI_ADD6_CASE(W, RR) \
     if (nw == W && r == RR) return launch_persistent<&fused_add6_rows_kernel<W, RR>>(64 * W, 0, a, b, c, n, batch, st, num_cus);
-        BI_ADD6_CASE(2, 1) BI_ADD6_CASE(2, 2) BI_ADD6_CASE(4, 1) BI_ADD6_CASE(4, 2)
-        BI_ADD6_CASE(8, 1) BI_ADD6_CASE(8, 2) BI_ADD6_CASE(16, 1) BI_ADD6_CASE(16, 2)
+        BI_ADD6_CASE(1, 2) BI_ADD6_CASE(1, 3) BI_ADD6_CASE(1, 4) BI_ADD6_CASE(2, 3) BI_ADD6_CASE(2, 4)
+        BI_ADD6_CASE(4, 3) BI_ADD6_CASE(4, 4) BI_ADD6_CASE(8, 3) BI_ADD6_CASE(8, 4)
 #undef BI_ADD6_CASE
         return hipErrorInvalidValue;
     }
