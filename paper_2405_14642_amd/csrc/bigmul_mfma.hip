@@ -136,8 +136,13 @@ __device__ __forceinline__ void recode_chunks(Chunks &x, uint32_t nchunks, uint3
 
 }  // namespace
 
-template <int NW, class Src>
-__global__ __launch_bounds__(64 * NW) void bigmul_mfma_kernel(Src src) {
+// OCC: minimum waves per SIMD the registers are sized for (1: no bound).
+// The smallest products (up to 160 limbs) take 4: LDS allows 5 one-wave
+// workgroups per SIMD, their per-product phases are latency chains, and the
+// unbounded kernel's 180 registers allow only 2.  Larger ones keep the
+// compiler's choice.
+template <int NW, int OCC, class Src>
+__global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
     extern __shared__ __align__(16) uint8_t lds[];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = wave_in_block();
     constexpr uint32_t T = 64 * NW;
@@ -292,10 +297,10 @@ static uint32_t mfma_waves(uint32_t nmax) {
     return h <= 1 ? 1 : h <= 2 ? 2 : 4;
 }
 
-template <int NW, class Src>
+template <int NW, int OCC, class Src>
 static hipError_t launch_nw(const Src &src, uint32_t nmax, uint64_t count, hipStream_t st, int num_cus) {
     const MfmaLayout lo = mfma_layout((nmax + 7) & ~7u);
-    const void *fn = reinterpret_cast<const void *>(&bigmul_mfma_kernel<NW, Src>);
+    const void *fn = reinterpret_cast<const void *>(&bigmul_mfma_kernel<NW, OCC, Src>);
     // (LDS bytes << 32 | resident workgroups per CU) of the last launch shape
     static std::atomic<uint64_t> occ{0};
     uint64_t o = occ.load(std::memory_order_relaxed);
@@ -312,7 +317,7 @@ static hipError_t launch_nw(const Src &src, uint32_t nmax, uint64_t count, hipSt
     const uint64_t cap = uint64_t(uint32_t(o)) * uint64_t(num_cus > 0 ? num_cus : 1);
     const uint32_t grid = uint32_t(count < cap ? count : cap);
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((bigmul_mfma_kernel<NW, Src>), dim3(grid), dim3(64 * NW), lo.total, st, src);
+    hipLaunchKernelGGL((bigmul_mfma_kernel<NW, OCC, Src>), dim3(grid), dim3(64 * NW), lo.total, st, src);
     return hipGetLastError();
 }
 
@@ -320,9 +325,14 @@ template <class Src>
 static hipError_t launch_mfma(const Src &src, uint32_t nmax, uint64_t count, hipStream_t st, int num_cus) {
     if (nmax > mfma_max_limbs()) return hipErrorInvalidValue;
     switch (mfma_waves(nmax)) {
-        case 1: return launch_nw<1>(src, nmax, count, st, num_cus);
-        case 2: return launch_nw<2>(src, nmax, count, st, num_cus);
-        default: return launch_nw<4>(src, nmax, count, st, num_cus);
+        case 1:
+            // one-wave workgroups: registers for 4 per SIMD when LDS holds 16
+            // per CU (3, sized the same way at 2^13 bits, measured slower)
+            if (mfma_layout((nmax + 7) & ~7u).total * 16 <= 160 * 1024)
+                return launch_nw<1, 4>(src, nmax, count, st, num_cus);
+            return launch_nw<1, 1>(src, nmax, count, st, num_cus);
+        case 2: return launch_nw<2, 1>(src, nmax, count, st, num_cus);
+        default: return launch_nw<4, 1>(src, nmax, count, st, num_cus);
     }
 }
 
