@@ -165,11 +165,13 @@ bi_status bigmul_v(bi_ctx *ctx, const void *a, const void *b, void *out,
 /*
  * Tuning.  Ragged batches and BI_MUL_AUTO pick a multiplication algorithm per
  * size class: class k holds instances of (16 << (k-1), 16 << k] 32-bit limbs
- * (class 0: up to 16), k < BI_NUM_CLASSES.  bi_autotune times every algorithm
- * on synthetic operands of each class's largest size on the context's device
- * (and the addition schedules for 2-, 4- and 8-row instances), keeps the
- * fastest, and copies the per-class choice to algo_out[0 .. n_out) if not
- * NULL.  It allocates and frees 64 MiB of device memory and synchronises
+ * (class 0: up to 16), k < BI_NUM_CLASSES.  bi_autotune first picks, per
+ * class, the VALU schoolbook's schedule (Q = 2 or 4 output words per lane --
+ * the paper's sequentialisation factor, Section 3 -- and 1..16 waves per
+ * workgroup), then times every algorithm on synthetic operands of each
+ * class's largest size on the context's device (and the addition schedules
+ * for 2-, 4- and 8-row instances), keeps the fastest, and copies the
+ * per-class choice to algo_out[0 .. n_out) if not NULL.  It allocates and frees 64 MiB of device memory and synchronises
  * `stream`.  bi_tune_get / bi_tune_set read or replace the per-class choice
  * (BI_EALGO if an algorithm cannot run a class's sizes; nothing is changed
  * then).  Until tuned, a context uses a built-in table.
@@ -179,6 +181,14 @@ bi_status bigmul_v(bi_ctx *ctx, const void *a, const void *b, void *out,
 bi_status bi_autotune(bi_ctx *ctx, void *stream, int *algo_out, uint32_t n_out);
 bi_status bi_tune_get(const bi_ctx *ctx, int *algo_out, uint32_t n_out);
 bi_status bi_tune_set(bi_ctx *ctx, const int *algo_in, uint32_t n_in);
+/* The VALU schoolbook schedule per class: q_out[k], waves_out[k] (0, 0 until
+ * tuned: the built-in size rule applies).  Either array may be NULL.
+ * bi_tune_set_valu replaces entries 0 .. n_in-1: (0, 0) restores the size
+ * rule; otherwise q must be 2 or 4, waves 1, 2, 4, 8 or 16, and the schedule's
+ * LDS must fit one CU for the class's largest size (BI_EINVAL otherwise;
+ * nothing is changed then). */
+bi_status bi_tune_get_valu(const bi_ctx *ctx, int *q_out, int *waves_out, uint32_t n_out);
+bi_status bi_tune_set_valu(bi_ctx *ctx, const int *q_in, const int *waves_in, uint32_t n_in);
 
 /*
  * Stream mode: a queue of ragged multiplication bursts over caller-owned

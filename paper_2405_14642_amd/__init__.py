@@ -30,7 +30,8 @@ STATUS = {0: "BI_OK", -1: "BI_EINVAL", -2: "BI_ESIZE", -3: "BI_ELIMB", -4: "BI_E
 EXPORTS = ("bi_ctx_create", "bi_ctx_destroy", "bi_status_str", "bi_last_error",
            "bigadd", "bigmul", "bigadd_v", "bigmul_v", "bi_ntt_field", "bi_autotune", "bi_tune_get",
            "bi_tune_set", "bi_stream_open", "bi_stream_submit", "bi_stream_poll", "bi_stream_wait",
-           "bi_stream_close", "bi_fused")
+           "bi_stream_close", "bi_fused", "bi_tune_get_valu",
+           "bi_tune_set_valu")
 NUM_CLASSES = 10
 
 
@@ -81,9 +82,12 @@ def _load():
     L.bi_stream_wait.argtypes = [P, U64]
     L.bi_stream_close.argtypes = [P]
     L.bi_fused.argtypes = [P, I, P, P, P, U32, U32, U64, P]
+    L.bi_tune_get_valu.argtypes = [P, P, P, U32]
+    L.bi_tune_set_valu.argtypes = [P, P, P, U32]
     for f in (L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field, L.bi_autotune,
               L.bi_tune_get, L.bi_tune_set, L.bi_stream_open, L.bi_stream_submit, L.bi_stream_poll,
-              L.bi_stream_wait, L.bi_stream_close, L.bi_fused):
+              L.bi_stream_wait, L.bi_stream_close, L.bi_fused, L.bi_tune_get_valu,
+              L.bi_tune_set_valu):
         f.restype = I
     return L
 
@@ -207,6 +211,23 @@ def tune_get(ctx):
 def tune_set(ctx, algos):
     arr = (ctypes.c_int * len(algos))(*algos)
     _check(lib.bi_tune_set(_h(ctx), arr, len(algos)))
+
+
+def tune_get_valu(ctx):
+    """The VALU schoolbook schedule per class: list of (Q, waves), (0, 0)
+    where the built-in size rule applies."""
+    q = (ctypes.c_int * NUM_CLASSES)()
+    w = (ctypes.c_int * NUM_CLASSES)()
+    _check(lib.bi_tune_get_valu(_h(ctx), q, w, NUM_CLASSES))
+    return list(zip(list(q), list(w)))
+
+
+def tune_set_valu(ctx, schedule):
+    """Set the VALU schoolbook schedule per class from a list of (Q, waves)
+    pairs ((0, 0): the built-in size rule)."""
+    q = (ctypes.c_int * len(schedule))(*[int(x[0]) for x in schedule])
+    w = (ctypes.c_int * len(schedule))(*[int(x[1]) for x in schedule])
+    _check(lib.bi_tune_set_valu(_h(ctx), q, w, len(schedule)))
 
 
 def ntt_field(p: int) -> NttFieldInfo:

@@ -243,4 +243,29 @@ bi_status bi_tune_set(bi_ctx *ctx, const int *algo_in, uint32_t n_in) {
     return BI_OK;
 }
 
+bi_status bi_tune_set_valu(bi_ctx *ctx, const int *q_in, const int *waves_in, uint32_t n_in) {
+    if (!ctx || !q_in || !waves_in) return fail(BI_EINVAL, "NULL argument");
+    const uint32_t m = n_in < bi::kNumClasses ? n_in : bi::kNumClasses;
+    for (uint32_t k = 0; k < m; ++k) {
+        if (q_in[k] == 0 && waves_in[k] == 0) continue;
+        if (!bi::valu_plan_fits(bi::class_nmax(k), q_in[k], waves_in[k], nullptr))
+            return fail(BI_EINVAL, "class %u: schedule (Q %d, %d waves) is not valid for its sizes", k, q_in[k],
+                        waves_in[k]);
+    }
+    for (uint32_t k = 0; k < m; ++k) {
+        ctx->impl.tune.valu_q[k] = uint8_t(q_in[k]);
+        ctx->impl.tune.valu_nw[k] = uint8_t(waves_in[k]);
+    }
+    return BI_OK;
+}
+
+bi_status bi_tune_get_valu(const bi_ctx *ctx, int *q_out, int *waves_out, uint32_t n_out) {
+    if (!ctx) return fail(BI_EINVAL, "ctx is NULL");
+    for (uint32_t k = 0; k < n_out && k < bi::kNumClasses; ++k) {
+        if (q_out) q_out[k] = ctx->impl.tune.valu_q[k];
+        if (waves_out) waves_out[k] = ctx->impl.tune.valu_nw[k];
+    }
+    return BI_OK;
+}
+
 }  // extern "C"

@@ -1,7 +1,9 @@
-// On-device autotuning: times every multiplication algorithm on synthetic
-// operands of each ragged size class and keeps the fastest per class (used by
-// BI_MUL_AUTO and bigmul_v), and picks the addition schedule for instances of
-// 2, 3-4 and 5-8 rows.  The paper tunes code-version thresholds the same way
+// On-device autotuning: per ragged size class it first picks the VALU
+// schoolbook's schedule (output words per lane Q = 2 or 4, the paper's
+// sequentialisation factor, and waves per workgroup), then times every
+// multiplication algorithm on synthetic operands of the class's largest size
+// and keeps the fastest (used by BI_MUL_AUTO and bigmul_v); it also picks the
+// addition schedule for instances of 2, 3-4 and 5-8 rows.  The paper tunes code-version thresholds the same way
 // (Section 5.1, Futhark's autotuned thresholds); here the choices are the
 // kernel families and their schedules.
 #include <hip/hip_runtime.h>
@@ -64,6 +66,31 @@ bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out) {
         const uint32_t n = class_nmax(k);
         uint64_t batch = limbs / n;
         if (batch > 65536) batch = 65536;
+        // VALU schedule: every (Q, waves) whose LDS fits, fastest kept
+        {
+            float best_v = 0;
+            uint8_t bq = 0, bw = 0;
+            for (int Q : {2, 4}) {
+                for (int NW : {1, 2, 4, 8, 16}) {
+                    if (!valu_plan_fits(n, Q, NW, nullptr)) continue;
+                    c.tune.valu_q[k] = uint8_t(Q);
+                    c.tune.valu_nw[k] = uint8_t(NW);
+                    float us = 0;
+                    s = time_us(st, tm, 3, [&]() { return dispatch_bigmul(c, a, b, o, n, batch, BI_MUL_SCHOOL_VALU, st); },
+                                &us);
+                    if (s != BI_OK) break;
+                    if (best_v == 0 || us < best_v) {
+                        best_v = us;
+                        bq = uint8_t(Q);
+                        bw = uint8_t(NW);
+                    }
+                }
+                if (s != BI_OK) break;
+            }
+            c.tune.valu_q[k] = bq;
+            c.tune.valu_nw[k] = bw;
+            if (s != BI_OK) break;
+        }
         float best = 0;
         int best_algo = c.tune.mul_algo[k];
         for (int al : algos) {

@@ -81,7 +81,9 @@ hipError_t launch_bigmul_v_core(const Ctx &c, const Tune &tune, const void *a, c
                 e = launch_bigmul_ntt64_list(c.ntt.c64, src, nmax, count_max, reinterpret_cast<uint64_t *>(ntt_scr), st,
                                              c.num_cus);
                 break;
-            default: e = launch_bigmul_valu_list(src, nmax, count_max, st, c.num_cus); break;
+            default:
+                e = launch_bigmul_valu_list(src, nmax, count_max, valu_plan_tuned(nmax, tune), st, c.num_cus);
+                break;
         }
         if (e != hipSuccess) return e;
     }

@@ -24,6 +24,10 @@ uint32_t class_nmax(uint32_t c);
 // Per-context tuning: multiplication algorithm per size class (BI_MUL_AUTO).
 struct Tune {
     int mul_algo[kNumClasses];
+    // VALU schoolbook schedule per class: output words per lane (Q = 2 or 4)
+    // and waves per workgroup; 0 = the size rule of valu_plan.
+    uint8_t valu_q[kNumClasses];
+    uint8_t valu_nw[kNumClasses];
 };
 bool algo_supports(int algo, uint32_t n32);
 
@@ -154,9 +158,12 @@ struct ValuPlan {
     int NW = 1;      // waves per workgroup
     size_t lds = 0;  // dynamic LDS bytes
 };
-ValuPlan valu_plan(uint32_t n);
+ValuPlan valu_plan(uint32_t n);                                // the size rule
+bool valu_plan_fits(uint32_t n, int Q, int NW, ValuPlan *out);   // LDS of (Q, NW) for n fits a CU
+ValuPlan valu_plan_tuned(uint32_t n, const Tune &t);             // the class's tuned plan, else the rule
+uint32_t size_class_host(uint32_t n32);
 hipError_t launch_bigmul_valu(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n, uint64_t batch,
-                              hipStream_t st, int num_cus);
+                              const ValuPlan &p, hipStream_t st, int num_cus);
 
 // NTT multiplication of n32-limb operands: the four transforms of every pair
 // (2 operands x 2 primes, L words each) go to the scratch `tr`
@@ -169,8 +176,8 @@ hipError_t launch_bigmul_ntt(const NttConst &k, const uint32_t *a, const uint32_
 // Ragged (descriptor-list) launches of one size class; nmax bounds the
 // class's limb counts, count_max bounds the class size (the true size is read
 // on the device).
-hipError_t launch_bigmul_valu_list(const ListInst &src, uint32_t nmax, uint64_t count_max, hipStream_t st,
-                                   int num_cus);
+hipError_t launch_bigmul_valu_list(const ListInst &src, uint32_t nmax, uint64_t count_max, const ValuPlan &p,
+                                   hipStream_t st, int num_cus);
 hipError_t launch_bigmul_mfma_list(const ListInst &src, uint32_t nmax, uint64_t count_max, hipStream_t st,
                                    int num_cus);
 hipError_t launch_bigmul_ntt_list(const NttConst &K, const ListInst &src, uint32_t nmax, uint64_t count_max,

@@ -207,11 +207,25 @@ ValuPlan valu_plan(uint32_t n) {
     return p;
 }
 
+bool valu_plan_fits(uint32_t n, int Q, int NW, ValuPlan *out) {
+    if ((Q != 2 && Q != 4) || (NW != 1 && NW != 2 && NW != 4 && NW != 8 && NW != 16)) return false;
+    const size_t lds = valu_lds_bytes(n, Q, NW);
+    if (lds > 160 * 1024) return false;
+    if (out) *out = ValuPlan{Q, NW, lds};
+    return true;
+}
+
+ValuPlan valu_plan_tuned(uint32_t n, const Tune &t) {
+    const uint32_t k = size_class_host(n);
+    ValuPlan p;
+    if (t.valu_q[k] && valu_plan_fits(n, t.valu_q[k], t.valu_nw[k], &p)) return p;
+    return valu_plan(n);
+}
+
 // A plan sized for instances of up to nmax limbs (Q, waves and LDS of the
 // largest); smaller instances of a ragged class run with the same plan.
 template <class Src>
-static hipError_t launch_plan(const Src &src, uint32_t nmax, uint64_t count, hipStream_t st, int num_cus) {
-    const ValuPlan p = valu_plan(nmax);
+static hipError_t launch_plan(const Src &src, const ValuPlan &p, uint64_t count, hipStream_t st, int num_cus) {
     const uint64_t cap = uint64_t(num_cus) * 32;
     const uint32_t grid = uint32_t(count < cap ? count : cap);
     if (grid == 0) return hipSuccess;
@@ -224,14 +238,15 @@ static hipError_t launch_plan(const Src &src, uint32_t nmax, uint64_t count, hip
 }
 
 hipError_t launch_bigmul_valu(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n, uint64_t batch,
-                              hipStream_t st, int num_cus) {
+                              const ValuPlan &p, hipStream_t st, int num_cus) {
     if (batch == 0) return hipSuccess;
-    return launch_plan(UniformInst{a, b, c, n, batch}, n, batch, st, num_cus);
+    return launch_plan(UniformInst{a, b, c, n, batch}, p, batch, st, num_cus);
 }
 
-hipError_t launch_bigmul_valu_list(const ListInst &src, uint32_t nmax, uint64_t count_max, hipStream_t st,
-                                   int num_cus) {
-    return launch_plan(src, nmax, count_max, st, num_cus);
+hipError_t launch_bigmul_valu_list(const ListInst &src, uint32_t nmax, uint64_t count_max, const ValuPlan &p,
+                                   hipStream_t st, int num_cus) {
+    (void)nmax;  // p is sized for the class's largest instance
+    return launch_plan(src, p, count_max, st, num_cus);
 }
 
 }  // namespace bi

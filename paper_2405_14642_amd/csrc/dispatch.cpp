@@ -23,6 +23,7 @@ static void default_tune(Tune &t) {
     for (uint32_t k = 0; k < kNumClasses; ++k) {
         const uint32_t n = class_nmax(k);
         t.mul_algo[k] = n <= 1024 ? BI_MUL_SCHOOL_VALU : BI_MUL_NTT;
+        t.valu_q[k] = t.valu_nw[k] = 0;  // the size rule of valu_plan
     }
 }
 
@@ -103,7 +104,8 @@ bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint3
     switch (algo) {
         case BI_MUL_SCHOOL_VALU:
             e = launch_bigmul_valu(static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
-                                   static_cast<uint32_t *>(out), n32, batch, st, c.num_cus);
+                                   static_cast<uint32_t *>(out), n32, batch, valu_plan_tuned(n32, c.tune), st,
+                                   c.num_cus);
             break;
         case BI_MUL_SCHOOL_MFMA:
             if (n32 <= mfma_max_limbs()) {

@@ -103,6 +103,14 @@ def test_fused_validation(B, args, status):
     assert st == status, B.lib.bi_last_error()
 
 
+def test_valu_schedule_validation(B):
+    import ctypes
+    q = (ctypes.c_int * 1)(2)
+    w = (ctypes.c_int * 1)(1)
+    assert B.lib.bi_tune_set_valu(None, q, w, 1) == -1
+    assert B.lib.bi_tune_get_valu(None, q, w, 1) == -1
+
+
 def test_empty_batch_needs_only_ctx(B):
     assert B.lib.bigadd(None, None, None, None, None, 4, 32, 0, None) == -1
     assert B.lib.bigmul(None, None, None, None, 4, 32, 0, 0, None) == -1

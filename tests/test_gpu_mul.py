@@ -213,6 +213,8 @@ def test_autotune_and_auto_dispatch(B, orc):
         algos = B.autotune(c)
         assert len(algos) == B.NUM_CLASSES and all(a in (1, 2, 3, 4) for a in algos)
         assert B.tune_get(c) == algos
+        for q, w in B.tune_get_valu(c):
+            assert q in (2, 4) and w in (1, 2, 4, 8, 16), (q, w)
         rng = np.random.default_rng(99)
         for n in (16, 100, 700, 3000, 8192):
             a, b = patterned(rng, 3, n)
@@ -227,5 +229,50 @@ def test_autotune_and_auto_dispatch(B, orc):
         assert B.tune_get(c) == [4] * B.NUM_CLASSES
         B.tune_set(c, [1] * B.NUM_CLASSES)
         assert B.tune_get(c) == [1] * B.NUM_CLASSES
+    finally:
+        c.close()
+
+
+def test_valu_schedules(B, orc):
+    """Every VALU schoolbook schedule (Q = 2 or 4 output words per lane, 1..16
+    waves) that fits a class's sizes is bit-exact, for the class's largest
+    size and a smaller one, uniform and ragged; invalid ones are rejected."""
+    c = B.Context(0)
+    try:
+        rng = np.random.default_rng(123)
+        for k in range(B.NUM_CLASSES):
+            nmax = 16 << k
+            sizes = [nmax, nmax // 2 + 1] if k else [16, 5]
+            for q in (2, 4):
+                for w in (1, 2, 4, 8, 16):
+                    sched = [(0, 0)] * B.NUM_CLASSES
+                    sched[k] = (q, w)
+                    try:
+                        B.tune_set_valu(c, sched)
+                    except B.BigIntError as e:
+                        assert e.status == -1
+                        continue
+                    assert B.tune_get_valu(c)[k] == (q, w)
+                    for n in sizes:
+                        a, b = patterned(rng, 3, n)
+                        check(orc, a, b, run_mul(B, c, a, b, 1))
+                    # ragged: one class, two sizes, through bigmul_v
+                    ns = np.array(sizes, dtype=np.int64)
+                    A = rng.integers(0, 2**32, int(ns.sum()), dtype=np.uint32)
+                    Bv = rng.integers(0, 2**32, int(ns.sum()), dtype=np.uint32)
+                    off = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.uint64)
+                    oo = 2 * off
+                    out = G.empty_dev((2 * int(ns.sum()),), np.uint32)
+                    B.bigmul_v(c, G.to_dev(A), G.to_dev(Bv), out, G.desc_dev(off, off, oo, ns), len(ns), 32, algo=1)
+                    G.sync()
+                    got = G.from_dev(out, np.uint32)
+                    for i, n in enumerate(ns.tolist()):
+                        o = int(off[i])
+                        want = orc.mul(A[o: o + n][None], Bv[o: o + n][None])[0]
+                        assert (got[2 * o: 2 * o + 2 * n] == want).all(), (k, q, w, n)
+        with pytest.raises(B.BigIntError):
+            B.tune_set_valu(c, [(3, 1)] + [(0, 0)] * (B.NUM_CLASSES - 1))
+        with pytest.raises(B.BigIntError):
+            B.tune_set_valu(c, [(2, 3)] + [(0, 0)] * (B.NUM_CLASSES - 1))
     finally:
         c.close()
