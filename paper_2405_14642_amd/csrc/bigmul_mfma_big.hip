@@ -38,7 +38,7 @@ constexpr uint32_t kNBS = 255 + kSU;         // B entries per plane and segment
 constexpr uint32_t kLdsE8 = 0, kLdsStage = 8 * kNEs, kLdsB = kLdsStage + kStage;
 constexpr uint32_t kLdsTotal = kLdsB + 2 * 16 * kNBS;
 constexpr int kGroupSt = 8;                  // supertiles per workgroup (4 waves x 2)
-constexpr int kNWRecode = 16, kNWCarry = 16;
+constexpr int kNWCarry = 16;
 
 // Byte offsets inside one product's scratch slot (n32p = limbs rounded up to 8).
 struct BigSlot {
@@ -64,11 +64,13 @@ __device__ __forceinline__ uint64_t big_count(const Src &src, uint64_t base, uin
 
 }  // namespace
 
-template <class Src>
-__global__ __launch_bounds__(64 * kNWRecode) void mfma_big_recode_kernel(Src src, uint64_t base, uint64_t chunk,
+// NW waves: one 64-chunk row of each operand per wave at the largest size
+// (8 at up to 2^16 bits, 16 above), so no wave idles through the scans.
+template <int NW, class Src>
+__global__ __launch_bounds__(64 * NW) void mfma_big_recode_kernel(Src src, uint64_t base, uint64_t chunk,
                                                                           uint8_t *__restrict__ scr,
                                                                           uint64_t stride) {
-    __shared__ uint32_t summary[2 * kNWRecode];
+    __shared__ uint32_t summary[2 * NW];
     const uint64_t cnt = big_count(src, base, chunk);
     for (uint64_t q = blockIdx.x; q < cnt; q += gridDim.x) {
         const InstRef in = src.get(base + q);
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(64 * kNWRecode) void mfma_big_recode_kernel(Src src
             *reinterpret_cast<uint4 *>(ad + kPadA + 16 * c) =
                 make_uint4(s[0] ^ kR8, s[1] ^ kR8, s[2] ^ kR8, s[3] ^ kR8);
         };
-        const uint32_t tA = wg_add_rows_sink<kNWRecode>(src_a, sink_a, n32p, summary);
+        const uint32_t tA = wg_add_rows_sink<NW>(src_a, sink_a, n32p, summary);
         auto src_b = [&](uint32_t c, uint32_t (&x)[4], uint32_t (&y)[4]) {
             load4(b, n32, c, x);
             y[0] = y[1] = y[2] = y[3] = kR8;
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(64 * kNWRecode) void mfma_big_recode_kernel(Src src
                 make_uint4(__builtin_bswap32(s[3] ^ kR8), __builtin_bswap32(s[2] ^ kR8),
                            __builtin_bswap32(s[1] ^ kR8), __builtin_bswap32(s[0] ^ kR8));
         };
-        const uint32_t tB = wg_add_rows_sink<kNWRecode>(src_b, sink_b, n32p, summary + kNWRecode);
+        const uint32_t tB = wg_add_rows_sink<NW>(src_b, sink_b, n32p, summary + NW);
         const uint32_t t = threadIdx.x;
         if (t < 2 * kPadA / 16) {
             const uint32_t off = t < kPadA / 16 ? 16 * t : kPadA + D + 16 * (t - kPadA / 16);
@@ -264,8 +266,12 @@ static hipError_t launch_big(const Src &src, uint32_t nmax, uint64_t count_max, 
     const uint64_t cap = uint64_t(num_cus > 0 ? num_cus : 1) * 2;
     for (uint64_t b = 0; b < count_max; b += chunk) {
         const uint64_t c = std::min(chunk, count_max - b);
-        hipLaunchKernelGGL((mfma_big_recode_kernel<Src>), dim3(uint32_t(std::min(c, cap * 4))), dim3(64 * kNWRecode), 0,
-                           st, src, b, chunk, scr, stride);
+        if (n32p <= 2048)
+            hipLaunchKernelGGL((mfma_big_recode_kernel<8, Src>), dim3(uint32_t(std::min(c, cap * 8))), dim3(512), 0,
+                               st, src, b, chunk, scr, stride);
+        else
+            hipLaunchKernelGGL((mfma_big_recode_kernel<16, Src>), dim3(uint32_t(std::min(c, cap * 4))), dim3(1024), 0,
+                               st, src, b, chunk, scr, stride);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         const uint64_t items = c * groups;
