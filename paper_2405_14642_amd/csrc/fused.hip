@@ -179,12 +179,7 @@ __device__ __forceinline__ void load_operand(uint32_t *dst, const uint32_t *src,
     for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) dst[t] = src[t];
 }
 
-}  // namespace
-
-namespace {
-
-// The six additions on one lane's chunk: x = a + b, then + a, + b, + a, + b,
-// + a.  `step` adds y to x given the wave's G / P masks; see the kernels.
+// A lane's 4-word chunk c of an n-word operand (zero past n or when invalid).
 __device__ __forceinline__ void load_chunk(const uint32_t *p, uint32_t n, uint32_t c, bool valid, uint32_t (&x)[4]) {
     const uint32_t base = 4 * c;
     if (valid && base + 4 <= n && (reinterpret_cast<uintptr_t>(p + base) & 15) == 0) {
@@ -196,6 +191,7 @@ __device__ __forceinline__ void load_chunk(const uint32_t *p, uint32_t n, uint32
     }
 }
 
+// Stores the words of chunk c below n when valid.
 __device__ __forceinline__ void store_chunk(uint32_t *p, uint32_t n, uint32_t c, bool valid, const uint32_t (&x)[4]) {
     if (!valid) return;
     const uint32_t base = 4 * c;
