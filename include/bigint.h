@@ -195,9 +195,10 @@ bi_status bi_tune_set_valu(bi_ctx *ctx, const int *q_in, const int *waves_in, ui
  * operand buffers a (a_limbs limbs), b (b_limbs) and out (out_limbs), all of
  * `limb_bits`-bit limbs, executed in submission order on `stream`.
  *
- * bi_stream_open allocates the queue's device descriptor buffer (max_descs
- * entries), its binning and transform scratch and a few pinned host staging
- * slots, and (use_graph != 0) captures the launch sequence of one burst --
+ * bi_stream_open allocates a few staging slots (each a pinned host buffer and
+ * a device buffer of max_descs descriptors), the binning and transform
+ * scratch and a side stream for the descriptor copies, and (use_graph != 0)
+ * captures, for each slot, the launch sequence of one burst --
  * device-side binning into size classes, then one persistent list kernel per
  * class that reads its instance count on the device -- into a HIP graph that
  * every submission replays.  The per-class algorithm is `algo`, or for
@@ -206,7 +207,8 @@ bi_status bi_tune_set_valu(bi_ctx *ctx, const int *q_in, const int *waves_in, ui
  * on allocation or capture failure (nothing is left allocated then).
  *
  * bi_stream_submit copies `count` (1 .. max_descs) HOST descriptors through a
- * pinned slot to the device and enqueues the burst; it validates every
+ * slot to the device (on the side stream, ordered before the burst) and
+ * enqueues the burst on `stream`; it validates every
  * descriptor first (1 <= n_limbs, n_limbs * limb_bits <= BI_MAX_BITS,
  * reserved == 0, input ranges inside a and b, output range inside out;
  * BI_EINVAL / BI_ESIZE and nothing enqueued otherwise).  It blocks only when

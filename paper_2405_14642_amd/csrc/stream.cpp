@@ -4,8 +4,11 @@
 // then one persistent list kernel per class, each reading its instance count
 // on the device), so the launch sequence does not depend on the burst: it is
 // captured once into a HIP graph and each submission is one descriptor copy
-// plus one graph launch.  Descriptors pass through pinned staging slots; a
-// slot is reused only after the event of its previous burst has completed.
+// plus one graph launch.  Descriptors pass through staging slots, each a
+// pinned host buffer and a device buffer of its own; a slot is reused only
+// after the event of its previous burst has completed.  The copies run on a
+// side stream, so the copy of a burst overlaps the bursts queued before it
+// and the queue's stream only waits on a copy that has already finished.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -20,7 +23,10 @@ constexpr size_t kHeader = 256;  // device buffer: count (u64) at 0, descriptors
 
 struct Slot {
     void *host = nullptr;  // pinned: header + descriptors
-    hipEvent_t done = nullptr;
+    void *dev = nullptr;   // device copy of the same
+    hipEvent_t copied = nullptr;  // on the copy stream
+    hipEvent_t done = nullptr;    // on the queue's stream, after the burst
+    hipGraphExec_t exec = nullptr;  // the captured burst that reads this slot's device copy
     uint64_t ticket = ~0ull;
 };
 
@@ -36,31 +42,32 @@ struct bi_stream {
     int algo = BI_MUL_AUTO;
     bi::Tune tune{};
     hipStream_t st = nullptr;
-    void *dev = nullptr;      // header + descriptors
+    hipStream_t copy_st = nullptr;  // descriptor copies
     void *scratch = nullptr;  // binning lists and transform scratch
     Slot slots[kSlots];
     uint64_t next = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    bool graphs = false;
 };
 
 namespace {
 
 void release(bi_stream *q) {
     for (Slot &s : q->slots) {
+        if (s.exec) (void)hipGraphExecDestroy(s.exec);
         if (s.done) (void)hipEventDestroy(s.done);
+        if (s.copied) (void)hipEventDestroy(s.copied);
         if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
     }
-    if (q->exec) (void)hipGraphExecDestroy(q->exec);
-    if (q->graph) (void)hipGraphDestroy(q->graph);
+    if (q->copy_st) (void)hipStreamDestroy(q->copy_st);
     if (q->scratch) (void)hipFree(q->scratch);
-    if (q->dev) (void)hipFree(q->dev);
     delete q;
 }
 
-hipError_t launch_burst(bi_stream *q, hipStream_t st) {
-    const bi_desc *d = reinterpret_cast<const bi_desc *>(static_cast<char *>(q->dev) + kHeader);
-    const uint64_t *cnt = static_cast<const uint64_t *>(q->dev);
+// One burst over the descriptors in the device copy of `slot`.
+hipError_t launch_burst(bi_stream *q, const Slot &slot, hipStream_t st) {
+    const bi_desc *d = reinterpret_cast<const bi_desc *>(static_cast<char *>(slot.dev) + kHeader);
+    const uint64_t *cnt = static_cast<const uint64_t *>(slot.dev);
     return bi::launch_bigmul_v_core(q->ctx->impl, q->tune, q->a, q->b, q->out, d, q->max_descs, cnt, q->limb_bits,
                                     q->algo, q->scratch, st);
 }
@@ -99,25 +106,31 @@ bi_status bi_stream_open(bi_ctx *ctx, const void *a, uint64_t a_limbs, const voi
     q->tune = ctx->impl.tune;
     q->st = static_cast<hipStream_t>(stream);
     const size_t dbytes = kHeader + max_descs * sizeof(bi_desc);
-    if (hipMalloc(&q->dev, dbytes) != hipSuccess ||
-        hipMalloc(&q->scratch, bi::batch_scratch_bytes(max_descs, ctx->impl.num_cus)) != hipSuccess) {
+    if (hipMalloc(&q->scratch, bi::batch_scratch_bytes(max_descs, ctx->impl.num_cus)) != hipSuccess) {
         release(q);
         return set_error(BI_ENOMEM, "queue device buffers");
     }
+    if (hipStreamCreateWithFlags(&q->copy_st, hipStreamNonBlocking) != hipSuccess) {
+        release(q);
+        return set_error(BI_EHIP, "copy stream creation");
+    }
     for (Slot &s : q->slots) {
-        if (hipHostMalloc(&s.host, dbytes, hipHostMallocDefault) != hipSuccess) {
+        if (hipMalloc(&s.dev, dbytes) != hipSuccess || hipHostMalloc(&s.host, dbytes, hipHostMallocDefault) != hipSuccess) {
             release(q);
-            return set_error(BI_ENOMEM, "pinned staging");
+            return set_error(BI_ENOMEM, "staging slot buffers");
         }
-        if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+        if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&s.copied, hipEventDisableTiming) != hipSuccess) {
             release(q);
             return set_error(BI_EHIP, "event creation");
         }
     }
-    // One empty burst outside capture: sets up the launchers' per-kernel
-    // attributes, and leaves a valid count (0) on the device.
-    hipError_t e = hipMemsetAsync(q->dev, 0, kHeader, q->st);
-    if (e == hipSuccess) e = launch_burst(q, q->st);
+    // Every slot's device count starts at 0; one empty burst outside capture
+    // sets up the launchers' per-kernel attributes.
+    hipError_t e = hipSuccess;
+    for (Slot &s : q->slots)
+        if (e == hipSuccess) e = hipMemsetAsync(s.dev, 0, kHeader, q->st);
+    if (e == hipSuccess) e = launch_burst(q, q->slots[0], q->st);
     if (e == hipSuccess) e = hipStreamSynchronize(q->st);
     if (e != hipSuccess) {
         release(q);
@@ -126,13 +139,17 @@ bi_status bi_stream_open(bi_ctx *ctx, const void *a, uint64_t a_limbs, const voi
     if (use_graph) {
         hipStream_t cap = nullptr;
         e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
-        if (e == hipSuccess) {
-            const hipError_t le = launch_burst(q, cap);
-            e = hipStreamEndCapture(cap, &q->graph);
+        for (Slot &s : q->slots) {
+            hipGraph_t graph = nullptr;
+            if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) break;
+            const hipError_t le = launch_burst(q, s, cap);
+            e = hipStreamEndCapture(cap, &graph);
             if (le != hipSuccess) e = le;
+            if (e == hipSuccess) e = hipGraphInstantiate(&s.exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
         }
-        if (e == hipSuccess) e = hipGraphInstantiate(&q->exec, q->graph, nullptr, nullptr, 0);
+        q->graphs = e == hipSuccess;
         if (cap) (void)hipStreamDestroy(cap);
         if (e != hipSuccess) {
             release(q);
@@ -172,8 +189,10 @@ bi_status bi_stream_submit(bi_stream *q, const bi_desc *descs, uint64_t count, u
     std::memset(s.host, 0, kHeader);
     std::memcpy(s.host, &count, sizeof count);
     std::memcpy(static_cast<char *>(s.host) + kHeader, descs, count * sizeof(bi_desc));
-    hipError_t e = hipMemcpyAsync(q->dev, s.host, kHeader + count * sizeof(bi_desc), hipMemcpyHostToDevice, q->st);
-    if (e == hipSuccess) e = q->exec ? hipGraphLaunch(q->exec, q->st) : launch_burst(q, q->st);
+    hipError_t e = hipMemcpyAsync(s.dev, s.host, kHeader + count * sizeof(bi_desc), hipMemcpyHostToDevice, q->copy_st);
+    if (e == hipSuccess) e = hipEventRecord(s.copied, q->copy_st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(q->st, s.copied, 0);
+    if (e == hipSuccess) e = q->graphs ? hipGraphLaunch(s.exec, q->st) : launch_burst(q, s, q->st);
     if (e == hipSuccess) e = hipEventRecord(s.done, q->st);
     if (e != hipSuccess) return set_error(BI_EHIP, "burst launch: %s", hipGetErrorString(e));
     s.ticket = t;
