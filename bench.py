@@ -42,7 +42,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="add", choices=["add", "mulq", "ntt", "stream", "copy", "fused"])
+    p.add_argument("--workload", default="add", choices=["add", "add_large", "mulq", "ntt", "stream", "copy", "fused"])
     p.add_argument("--stream-pairs", type=int, default=100000, help="pairs in the mixed-size stream")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU baseline budget")
@@ -630,6 +630,97 @@ def bench_copy(args):
             "cpu_baseline": None}
 
 
+def bench_add_large(args):
+    """One integer pair per size, 2^20..2^34 bits (u32 limbs), added by
+    bigadd_large (tile pass, summary scan, carry fix-up: one call).  Uniform
+    operands, and the ripple pattern (a = all-ones, b = 1), whose carry
+    crosses every limb so the fix-up rewrites the whole sum."""
+    import torch
+
+    import paper_2405_14642_amd as B
+    import workloads as W
+    from tests import gpu_util as G
+
+    ctx = B.Context(0)
+    stream = torch.cuda.current_stream()
+    sizes = W.LARGE_ADD_BITS
+    if args.sizes:
+        sizes = tuple(int(x) for x in args.sizes.split(","))
+    per_size = {}
+    main_bits = 1 << 32
+    step_ms = 0.0
+    for bits in sizes:
+        n = bits // 32
+        for pattern in ("uniform", "ripple"):
+            a, b = W.large_add_inputs(n, pattern)
+            A, Bt = G.to_dev(a), G.to_dev(b)
+            del a, b
+            out = torch.empty_like(A)
+            carry = torch.empty(1, dtype=torch.uint8, device="cuda")
+
+            def launch():
+                B.bigadd_large(ctx, A, Bt, out, carry, stream=stream.cuda_stream)
+
+            for _ in range(args.warmup):
+                launch()
+            torch.cuda.synchronize()
+            evs = []
+            for _ in range(args.steps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                launch()
+                e1.record(stream)
+                evs.append((e0, e1))
+            torch.cuda.synchronize()
+            us = 1e3 * float(np.mean([x.elapsed_time(y) for x, y in evs]))
+            nbytes = 12 * n  # read a and b, write the sum
+            gbs = nbytes / (us * 1e-6) / 1e9
+            per_size.setdefault(str(bits), {})[pattern] = {
+                "us_per_call": round(us, 2), "GB_per_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                "adds_per_s": 1e6 / us}
+            if pattern == "uniform":
+                step_ms += us / 1e3
+            del A, Bt, out
+            torch.cuda.empty_cache()
+    ctx.close()
+    key = str(main_bits) if str(main_bits) in per_size else str(sizes[-1])
+    main = per_size[key]["uniform"]
+    nb = 12 * (int(key) // 32)
+    roofline = {"bound": "hbm", "kernel": "bigadd_large call (large_add_tile_kernel + scan + fix-up)",
+                "achieved": main["GB_per_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(main["GB_per_s"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": main["us_per_call"], "algorithmic_bytes_per_launch": nb}
+    cpu = None if args.no_cpu else cpu_baseline_add_large(args, W, int(key))
+    return {
+        "metric": f"bigadd_large additions/s of one 2^{int(key).bit_length() - 1}-bit integer pair (u32 limbs)",
+        "value": main["adds_per_s"], "unit": "adds/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic (seeded splitmix64, uniform; ripple = all-ones + 1)",
+        "config": {"workload": "add_large", "sizes_bits": list(sizes), "limb_bits": 32,
+                   "parallelism": "single-gpu"},
+        "roofline": roofline, "per_size": per_size, "cpu_baseline": cpu,
+    }
+
+
+def cpu_baseline_add_large(args, W, bits):
+    import oracle
+    oracle.build()
+    orc = oracle.get()
+    a, b = W.large_add_inputs(bits // 32)
+    a, b = a[None, :], b[None, :]
+    reps, secs = 0, 0.0
+    while secs < args.cpu_seconds:
+        t = time.perf_counter()
+        orc.add(a, b)
+        secs += time.perf_counter() - t
+        reps += 1
+    # The oracle parallelises over instances: one instance keeps one thread busy.
+    return {"value": reps / secs, "unit": "adds/s", "cores": min(orc.last_threads, 1), "kind": "oracle",
+            "sample": f"the uniform 2^{bits.bit_length() - 1}-bit pair, {reps} additions",
+            "cpu_model": cpu_info(), "seconds": round(secs, 2)}
+
+
 def cpu_baseline_add(args, W):
     import oracle
     oracle.build()
@@ -664,6 +755,8 @@ def main():
         sys.exit(2)
     if args.workload == "add":
         res = bench_add(args)
+    elif args.workload == "add_large":
+        res = bench_add_large(args)
     elif args.workload == "stream":
         res = bench_stream(args)
     elif args.workload == "copy":

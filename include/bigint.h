@@ -37,6 +37,7 @@ extern "C" {
 #endif
 
 #define BI_MAX_BITS (1u << 18) /* largest integer, in bits (Section 1: up to ~2^18 bits) */
+#define BI_MAX_LARGE_BITS (1ull << 40) /* largest single integer of bigadd_large, in bits */
 
 typedef enum bi_status {
     BI_OK = 0,
@@ -87,6 +88,28 @@ const char *bi_last_error(void);
  */
 bi_status bigadd(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t *carry_out,
                  uint32_t n_limbs, uint32_t limb_bits, uint64_t batch, void *stream);
+
+/*
+ * bigadd_large -- Section 2's addition (a carry-propagation scan) for ONE
+ * integer of any length, carried across workgroups; the paper's kernels stop
+ * at one block and leave longer integers to slower fall-back versions
+ * (Section 5.1).  Computes
+ *     out        = (a + b) mod 2^(n_limbs * limb_bits)
+ *     *carry_out = floor((a + b) / 2^(n_limbs * limb_bits))  (0 or 1)
+ * a, b, out: n_limbs limbs of limb_bits (32 or 64) bits each, little-endian,
+ * device memory owned by the caller; 1 <= n_limbs and n_limbs * limb_bits <=
+ * BI_MAX_LARGE_BITS (BI_EINVAL / BI_ESIZE), and device memory bounds it
+ * further.  carry_out: one device byte, or NULL.  out may be identical to a or
+ * to b (in-place); any other overlap of out or carry_out with the inputs is
+ * BI_EALIAS.  Pointers must be limb-aligned (BI_ELIMB); 16-byte alignment of
+ * a, b and out gives the widest accesses.  Runs four kernels on `stream`
+ * (tile sums with tile carry summaries, a scan of the summaries, carry
+ * fix-up, a walk of tiles the carry crosses) using about 6 bytes of context
+ * scratch per tile of 1024 chunks; BI_ENOMEM if that scratch cannot grow.
+ * Asynchronous like every call.
+ */
+bi_status bigadd_large(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t *carry_out,
+                       uint64_t n_limbs, uint32_t limb_bits, void *stream);
 
 /*
  * bigmul -- full product, eq. (1) of Section 3.1 without truncation: for each

@@ -31,7 +31,7 @@ EXPORTS = ("bi_ctx_create", "bi_ctx_destroy", "bi_status_str", "bi_last_error",
            "bigadd", "bigmul", "bigadd_v", "bigmul_v", "bi_ntt_field", "bi_autotune", "bi_tune_get",
            "bi_tune_set", "bi_stream_open", "bi_stream_submit", "bi_stream_poll", "bi_stream_wait",
            "bi_stream_close", "bi_fused", "bi_tune_get_valu",
-           "bi_tune_set_valu")
+           "bi_tune_set_valu", "bigadd_large")
 NUM_CLASSES = 10
 
 
@@ -70,6 +70,7 @@ def _load():
     L.bi_last_error.restype = ctypes.c_char_p
     L.bigadd.argtypes = [P, P, P, P, P, U32, U32, U64, P]
     L.bigmul.argtypes = [P, P, P, P, U32, U32, U64, I, P]
+    L.bigadd_large.argtypes = [P, P, P, P, P, U64, U32, P]
     L.bigadd_v.argtypes = [P, P, P, P, P, P, U64, U32, P]
     L.bigmul_v.argtypes = [P, P, P, P, P, U64, U32, I, P]
     L.bi_ntt_field.argtypes = [U64, P]
@@ -87,7 +88,7 @@ def _load():
     for f in (L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field, L.bi_autotune,
               L.bi_tune_get, L.bi_tune_set, L.bi_stream_open, L.bi_stream_submit, L.bi_stream_poll,
               L.bi_stream_wait, L.bi_stream_close, L.bi_fused, L.bi_tune_get_valu,
-              L.bi_tune_set_valu):
+              L.bi_tune_set_valu, L.bigadd_large):
         f.restype = I
     return L
 
@@ -163,6 +164,15 @@ def bigadd(ctx, a, b, out, carry=None, n_limbs=None, limb_bits=None, batch=None,
     n = n_limbs if n_limbs is not None else a.shape[-1]
     bt = batch if batch is not None else (a.numel() // n if n else 0)
     _check(lib.bigadd(_h(ctx), _ptr(a), _ptr(b), _ptr(out), _ptr(carry), n, lb, bt, _stream(stream, a)))
+    return out
+
+
+def bigadd_large(ctx, a, b, out, carry=None, n_limbs=None, limb_bits=None, stream=None):
+    """out = a + b for ONE integer of any length (1-D limb tensors); carry is
+    a one-byte device tensor or None."""
+    lb = _limb_bits(a, limb_bits)
+    n = n_limbs if n_limbs is not None else a.numel()
+    _check(lib.bigadd_large(_h(ctx), _ptr(a), _ptr(b), _ptr(out), _ptr(carry), n, lb, _stream(stream, a)))
     return out
 
 

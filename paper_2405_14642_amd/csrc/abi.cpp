@@ -142,6 +142,35 @@ bi_status bigadd(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t *
     return BI_OK;
 }
 
+bi_status bigadd_large(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t *carry_out, uint64_t n_limbs,
+                       uint32_t limb_bits, void *stream) {
+    if (limb_bits != 32 && limb_bits != 64) return fail(BI_ELIMB, "limb_bits must be 32 or 64 (got %u)", limb_bits);
+    if (n_limbs == 0) return fail(BI_EINVAL, "n_limbs must be >= 1");
+    if (n_limbs > BI_MAX_LARGE_BITS / limb_bits)
+        return fail(BI_ESIZE, "n_limbs * limb_bits exceeds 2^40 bits (n_limbs = %llu)", (unsigned long long)n_limbs);
+    bi_status s;
+    if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
+    if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;
+    if ((s = check_ptr(out, limb_bits, "out")) != BI_OK) return s;
+    const uint64_t tot = n_limbs * (limb_bits / 8);
+    if (out != a && overlaps(out, tot, a, tot)) return fail(BI_EALIAS, "out partially overlaps a");
+    if (out != b && overlaps(out, tot, b, tot)) return fail(BI_EALIAS, "out partially overlaps b");
+    if (overlaps(carry_out, 1, a, tot) || overlaps(carry_out, 1, b, tot) || overlaps(carry_out, 1, out, tot))
+        return fail(BI_EALIAS, "carry_out overlaps an operand");
+    if (!ctx) return fail(BI_EINVAL, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint64_t n32 = n_limbs * (limb_bits / 32);
+    const uint64_t tiles = bi::large_add_tiles(n32, bi::large_add_chunk_words(a, b, out));
+    void *scr = nullptr;
+    if ((s = bi::ctx_scratch(ctx->impl, bi::large_add_scratch_bytes(tiles), st, &scr)) != BI_OK) return s;
+    hipError_t e = bi::launch_bigadd_large(a, b, out, carry_out, n32, static_cast<uint8_t *>(scr), st,
+                                           ctx->impl.num_cus);
+    if (e != hipSuccess) return hip_fail(e, "bigadd_large launch");
+    return BI_OK;
+}
+
 bi_status bigmul(bi_ctx *ctx, const void *a, const void *b, void *out, uint32_t n_limbs, uint32_t limb_bits,
                  uint64_t batch, int algo, void *stream) {
     uint64_t ib = 0;

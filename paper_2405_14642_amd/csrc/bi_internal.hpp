@@ -150,6 +150,14 @@ void ctx_release(Ctx &c);
 // out = a + b over `batch` instances of `inst_bytes` bytes each (a multiple of 4).
 hipError_t launch_bigadd(const void *a, const void *b, void *out, uint8_t *carry, uint64_t inst_bytes,
                          uint64_t batch, hipStream_t st, const AddTune &t);
+// Addition of one integer of n32 32-bit words across workgroups; scratch
+// holds large_add_scratch_bytes(large_add_tiles(n32, large_add_chunk_words(a,
+// b, out))) bytes, 16-byte aligned.
+int large_add_chunk_words(const void *a, const void *b, const void *out);
+uint64_t large_add_tiles(uint64_t n32, int w);
+size_t large_add_scratch_bytes(uint64_t tiles);
+hipError_t launch_bigadd_large(const void *a, const void *b, void *out, uint8_t *carry, uint64_t n32,
+                               uint8_t *scratch, hipStream_t st, int num_cus);
 hipError_t launch_bigadd_ragged(const void *a, const void *b, void *out, uint8_t *carry, const bi_desc *desc,
                                 uint64_t count, uint32_t limb_bits, hipStream_t st, const AddTune &t);
 

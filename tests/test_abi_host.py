@@ -65,6 +65,30 @@ def test_bigadd_validation(B, args, status):
 
 
 @pytest.mark.parametrize("args,status", [
+    (dict(limb_bits=16), -3),
+    (dict(n=0), -1),
+    (dict(n=(1 << 40) // 32 + 1), -2),
+    (dict(n=(1 << 40) // 64 + 1, limb_bits=64), -2),
+    (dict(n=1 << 63), -2),
+    (dict(a=None), -1),
+    (dict(out=None), -1),
+    (dict(b=FAKE + 2), -3),
+    (dict(out=FAKE + 4), -4),                     # out partially overlaps a
+    (dict(b=FAKE + 8, out=FAKE + 8), -4),         # out == b but partially overlaps a
+    (dict(carry=FAKE + (1 << 24) + 3), -4),       # carry byte inside b
+    (dict(), -1),                                 # all valid, but ctx is NULL
+    (dict(out=FAKE), -1),                         # in-place is allowed: fails only on ctx
+    (dict(n=(1 << 40) // 32, b=FAKE + (1 << 38), out=FAKE + (1 << 39)), -1),  # largest size passes
+])
+def test_bigadd_large_validation(B, args, status):
+    p = dict(a=FAKE, b=FAKE + (1 << 24), out=FAKE + (2 << 24), carry=None, n=4, limb_bits=32)
+    p.update(args)
+    st = B.lib.bigadd_large(None, p["a"], p["b"], p["out"], p["carry"], p["n"], p["limb_bits"], None)
+    assert st == status, B.lib.bi_last_error()
+    assert B.lib.bi_last_error()
+
+
+@pytest.mark.parametrize("args,status", [
     (dict(limb_bits=8), -3),
     (dict(n=0), -1),
     (dict(n=8193), -2),

@@ -20,6 +20,12 @@ Workloads (sizes in bits; limbs little-endian, instance-major, contiguous):
 * ``mul_ntt``    (2^15, 4096), (2^16, 1024), (2^17, 256), (2^18, 64) pairs.
 * ``stream``     mixed-size pairs, n = max(1, round(2^u / 32)), u ~ U[10, 18];
                  90 % uniform, 10 % a = b = all-ones.
+* ``add_large``  ONE pair of 2^20..2^34-bit integers (the add sweep's 2^32 bits
+                 of a+b as a single instance at 2^32), u32 limbs, uniform;
+                 pattern variants for tests: ``ripple`` (a = all-ones, b = 1:
+                 the carry crosses every limb), ``chains`` (b = ~a except a
+                 seeded 1/4096 of the limbs, which are uniform: carry chains
+                 of thousands of limbs, many spanning whole tiles).
 """
 from __future__ import annotations
 
@@ -36,12 +42,13 @@ _LIB = os.path.join(_HERE, "libwlgen.so")
 DEFAULT_SEED = 0x240514642
 EXTRA_SEEDS = (0x5EED0001, 0x5EED0002)
 
-CFG_SMALL, CFG_ADD, CFG_MULQ, CFG_NTT, CFG_STREAM = 1, 2, 3, 4, 5
+CFG_SMALL, CFG_ADD, CFG_MULQ, CFG_NTT, CFG_STREAM, CFG_LARGE = 1, 2, 3, 4, 5, 6
 
 ADD_SWEEP_BITS = (1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18)
 MULQ_BITS = (1 << 12, 1 << 13, 1 << 14, 1 << 15)
 NTT_CASES = ((1 << 15, 4096), (1 << 16, 1024), (1 << 17, 256), (1 << 18, 64))
 MAX_BITS = 1 << 18
+LARGE_ADD_BITS = (1 << 20, 1 << 24, 1 << 28, 1 << 32, 1 << 34)
 
 _GAMMA = 0x9E3779B97F4A7C15
 _STEP = 0xD1B54A32D192ED03
@@ -185,6 +192,27 @@ def add_sweep_inputs(bits: int, seed: int = DEFAULT_SEED, pairs=None, limb_bits:
     k = (n + 7) // 8
     b[np.ix_(low, np.arange(k, n))] = 0
     return a, b
+
+
+def large_add_inputs(n: int, pattern: str = "uniform", seed: int = DEFAULT_SEED, limb_bits: int = 32):
+    """One pair (a, b) of n-limb integers as 1-D arrays (pattern: uniform,
+    ripple or chains; see the module docstring)."""
+    dt = np.uint32 if limb_bits == 32 else np.uint64
+    if pattern == "ripple":
+        a = np.full(n, np.iinfo(dt).max, dtype=dt)
+        b = np.zeros(n, dtype=dt)
+        b[0] = 1
+        return a, b
+    a = uniform(seed, CFG_LARGE, 0, n, limb_bits, 0, 1)[0]
+    if pattern == "uniform":
+        return a, uniform(seed, CFG_LARGE, 1, n, limb_bits, 0, 1)[0]
+    if pattern == "chains":
+        b = ~a
+        r = uniform(seed, CFG_LARGE, 1, n, limb_bits, 0, 1)[0]
+        sel = (uniform(seed, CFG_LARGE, 2, n, 32, 0, 1)[0] & np.uint32(4095)) == 0
+        b[sel] = r[sel]
+        return a, b
+    raise ValueError(f"unknown pattern {pattern!r}")
 
 
 def mul_quad_pairs(bits: int) -> int:
