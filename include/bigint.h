@@ -219,9 +219,12 @@ bi_status bi_tune_set_valu(bi_ctx *ctx, const int *q_in, const int *waves_in, ui
  * `limb_bits`-bit limbs, executed in submission order on `stream`.
  *
  * bi_stream_open allocates a few staging slots (each a pinned host buffer and
- * a device buffer of max_descs descriptors), the binning and transform
- * scratch and a side stream for the descriptor copies, and (use_graph != 0)
- * captures, for each slot, the launch sequence of one burst --
+ * a device buffer of max_descs descriptors and class-list entries), the
+ * binning and transform scratch and a side stream for the descriptor copies.
+ * With use_graph == 0 every submission is binned into size classes on the
+ * host and only the classes present are launched, grids sized to their
+ * counts.  With use_graph != 0 it captures, for each slot, the launch
+ * sequence of one burst --
  * device-side binning into size classes, then one persistent list kernel per
  * class that reads its instance count on the device -- into a HIP graph that
  * every submission replays.  The per-class algorithm is `algo`, or for

@@ -48,6 +48,47 @@ size_t batch_scratch_bytes(uint64_t count, int num_cus) {
     return 256 + lists_bytes(count) + std::max(ntt_list_scratch_bytes(count), ntt64_list_scratch_bytes(count));
 }
 
+// The list kernel of size class k's algorithm (the tuned one, or `algo` when
+// it is forced and supports the class) over at most count_max instances.
+static hipError_t launch_class(const Ctx &c, const Tune &tune, const ListInst &src, uint32_t k, uint64_t count_max,
+                               int algo, uint32_t *ntt_scr, hipStream_t st) {
+    const uint32_t nmax = class_nmax(k);
+    int alg = tune.mul_algo[k];
+    if (algo != BI_MUL_AUTO && algo_supports(algo, nmax)) alg = algo;
+    switch (alg) {
+        case BI_MUL_SCHOOL_MFMA:
+            return nmax <= mfma_max_limbs()
+                       ? launch_bigmul_mfma_list(src, nmax, count_max, st, c.num_cus)
+                       : launch_bigmul_mfma_big_list(src, nmax, count_max, reinterpret_cast<uint8_t *>(ntt_scr),
+                                                     ntt_list_scratch_bytes(count_max), st, c.num_cus);
+        case BI_MUL_NTT: return launch_bigmul_ntt_list(c.ntt.c, src, nmax, count_max, ntt_scr, st, c.num_cus);
+        case BI_MUL_NTT_PF64:
+            return launch_bigmul_ntt64_list(c.ntt.c64, src, nmax, count_max, reinterpret_cast<uint64_t *>(ntt_scr), st,
+                                            c.num_cus);
+        default: return launch_bigmul_valu_list(src, nmax, count_max, valu_plan_tuned(nmax, tune), st, c.num_cus);
+    }
+}
+
+hipError_t launch_bigmul_v_binned(const Ctx &c, const Tune &tune, const void *a, const void *b, void *out,
+                                  const bi_desc *desc, const uint32_t *lists, const uint32_t *counts,
+                                  const uint32_t *host_counts, uint32_t limb_bits, int algo, void *scratch,
+                                  hipStream_t st) {
+    const uint32_t wpl = limb_bits / 32;
+    auto A = static_cast<const uint32_t *>(a);
+    auto B = static_cast<const uint32_t *>(b);
+    auto C = static_cast<uint32_t *>(out);
+    uint64_t off = 0;
+    for (uint32_t k = 0; k < kNumClasses; ++k) {
+        const uint64_t n = host_counts[k];
+        if (n == 0) continue;
+        const ListInst src{A, B, C, desc, lists + off, counts + k, wpl};
+        const hipError_t e = launch_class(c, tune, src, k, n, algo, static_cast<uint32_t *>(scratch), st);
+        if (e != hipSuccess) return e;
+        off += n;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_bigmul_v_core(const Ctx &c, const Tune &tune, const void *a, const void *b, void *out,
                                 const bi_desc *desc, uint64_t count_max, const uint64_t *count_ptr,
                                 uint32_t limb_bits, int algo, void *scratch, hipStream_t st) {
@@ -65,26 +106,8 @@ hipError_t launch_bigmul_v_core(const Ctx &c, const Tune &tune, const void *a, c
     auto B = static_cast<const uint32_t *>(b);
     auto C = static_cast<uint32_t *>(out);
     for (uint32_t k = 0; k < kNumClasses; ++k) {
-        const uint32_t nmax = class_nmax(k);
         const ListInst src{A, B, C, desc, lists + uint64_t(k) * count_max, counts + k, wpl};
-        int alg = tune.mul_algo[k];
-        if (algo != BI_MUL_AUTO && algo_supports(algo, nmax)) alg = algo;
-        switch (alg) {
-            case BI_MUL_SCHOOL_MFMA:
-                e = nmax <= mfma_max_limbs()
-                        ? launch_bigmul_mfma_list(src, nmax, count_max, st, c.num_cus)
-                        : launch_bigmul_mfma_big_list(src, nmax, count_max, reinterpret_cast<uint8_t *>(ntt_scr),
-                                                      ntt_list_scratch_bytes(count_max), st, c.num_cus);
-                break;
-            case BI_MUL_NTT: e = launch_bigmul_ntt_list(c.ntt.c, src, nmax, count_max, ntt_scr, st, c.num_cus); break;
-            case BI_MUL_NTT_PF64:
-                e = launch_bigmul_ntt64_list(c.ntt.c64, src, nmax, count_max, reinterpret_cast<uint64_t *>(ntt_scr), st,
-                                             c.num_cus);
-                break;
-            default:
-                e = launch_bigmul_valu_list(src, nmax, count_max, valu_plan_tuned(nmax, tune), st, c.num_cus);
-                break;
-        }
+        e = launch_class(c, tune, src, k, count_max, algo, ntt_scr, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -235,6 +235,15 @@ size_t batch_scratch_bytes(uint64_t count, int num_cus);
 hipError_t launch_bigmul_v_core(const Ctx &c, const Tune &tune, const void *a, const void *b, void *out,
                                 const bi_desc *desc, uint64_t count_max, const uint64_t *count_ptr,
                                 uint32_t limb_bits, int algo, void *scratch, hipStream_t st);
+// The same with the binning done on the host: class k's descriptor indices are
+// the host_counts[k] entries of `lists` after those of classes 0..k-1, and
+// counts (device) holds the same counts.  Classes with no instance launch
+// nothing; the others get grids sized to their count.  scratch holds
+// batch_scratch_bytes(max count) bytes.
+hipError_t launch_bigmul_v_binned(const Ctx &c, const Tune &tune, const void *a, const void *b, void *out,
+                                  const bi_desc *desc, const uint32_t *lists, const uint32_t *counts,
+                                  const uint32_t *host_counts, uint32_t limb_bits, int algo, void *scratch,
+                                  hipStream_t st);
 bi_status dispatch_bigmul_v(Ctx &c, const void *a, const void *b, void *out, const bi_desc *desc, uint64_t count,
                             uint32_t limb_bits, int algo, hipStream_t st);
 

@@ -1,10 +1,13 @@
 // Stream mode (bi_stream_*): a queue of ragged multiplication bursts.
 //
-// Every burst runs the ragged path (device-side binning into size classes,
-// then one persistent list kernel per class, each reading its instance count
-// on the device), so the launch sequence does not depend on the burst: it is
-// captured once into a HIP graph and each submission is one descriptor copy
-// plus one graph launch.  Descriptors pass through staging slots, each a
+// With a graph, every burst runs the ragged path with device-side binning
+// into size classes and one persistent list kernel per class, each reading
+// its instance count on the device, so the launch sequence does not depend on
+// the burst: it is captured into a HIP graph and each submission is one
+// descriptor copy plus one graph launch.  Without a graph the host, which
+// validates every descriptor anyway, also bins them: the copy carries the
+// class lists and counts too, and only the classes present are launched, each
+// with a grid sized to its count.  Descriptors pass through staging slots, each a
 // pinned host buffer and a device buffer of its own; a slot is reused only
 // after the event of its previous burst has completed.  The copies run on a
 // side stream, so the copy of a burst overlaps the bursts queued before it
@@ -19,7 +22,11 @@
 namespace {
 
 constexpr int kSlots = 4;
-constexpr size_t kHeader = 256;  // device buffer: count (u64) at 0, descriptors from 256
+// Staging layout: count (u64) at 0, per-class counts (u32, host binning) at
+// kCountsAt, descriptors from kHeader, then (host binning) the class lists.
+constexpr size_t kHeader = 256;
+constexpr size_t kCountsAt = 64;
+static_assert(kCountsAt + 4 * bi::kNumClasses <= kHeader, "class counts fit the header");
 
 struct Slot {
     void *host = nullptr;  // pinned: header + descriptors
@@ -105,7 +112,7 @@ bi_status bi_stream_open(bi_ctx *ctx, const void *a, uint64_t a_limbs, const voi
     q->algo = algo;
     q->tune = ctx->impl.tune;
     q->st = static_cast<hipStream_t>(stream);
-    const size_t dbytes = kHeader + max_descs * sizeof(bi_desc);
+    const size_t dbytes = kHeader + max_descs * (sizeof(bi_desc) + sizeof(uint32_t));
     if (hipMalloc(&q->scratch, bi::batch_scratch_bytes(max_descs, ctx->impl.num_cus)) != hipSuccess) {
         release(q);
         return set_error(BI_ENOMEM, "queue device buffers");
@@ -186,13 +193,40 @@ bi_status bi_stream_submit(bi_stream *q, const bi_desc *descs, uint64_t count, u
         const hipError_t e = hipEventSynchronize(s.done);
         if (e != hipSuccess) return set_error(BI_EHIP, "staging slot wait: %s", hipGetErrorString(e));
     }
-    std::memset(s.host, 0, kHeader);
-    std::memcpy(s.host, &count, sizeof count);
-    std::memcpy(static_cast<char *>(s.host) + kHeader, descs, count * sizeof(bi_desc));
-    hipError_t e = hipMemcpyAsync(s.dev, s.host, kHeader + count * sizeof(bi_desc), hipMemcpyHostToDevice, q->copy_st);
+    char *h = static_cast<char *>(s.host);
+    std::memset(h, 0, kHeader);
+    std::memcpy(h, &count, sizeof count);
+    std::memcpy(h + kHeader, descs, count * sizeof(bi_desc));
+    size_t bytes = kHeader + count * sizeof(bi_desc);
+    uint32_t counts[bi::kNumClasses] = {};
+    if (!q->graphs) {  // bin on the host: counts, then the lists in class order
+        const uint32_t wpl = q->limb_bits / 32;
+        uint32_t next[bi::kNumClasses];
+        for (uint64_t i = 0; i < count; ++i) ++counts[bi::size_class_host(descs[i].n_limbs * wpl)];
+        for (uint32_t k = 0, o = 0; k < bi::kNumClasses; ++k) {
+            next[k] = o;
+            o += counts[k];
+        }
+        uint32_t *lists = reinterpret_cast<uint32_t *>(h + bytes);
+        for (uint64_t i = 0; i < count; ++i) lists[next[bi::size_class_host(descs[i].n_limbs * wpl)]++] = uint32_t(i);
+        std::memcpy(h + kCountsAt, counts, sizeof counts);
+        bytes += count * sizeof(uint32_t);
+    }
+    hipError_t e = hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, q->copy_st);
     if (e == hipSuccess) e = hipEventRecord(s.copied, q->copy_st);
     if (e == hipSuccess) e = hipStreamWaitEvent(q->st, s.copied, 0);
-    if (e == hipSuccess) e = q->graphs ? hipGraphLaunch(s.exec, q->st) : launch_burst(q, s, q->st);
+    if (e == hipSuccess) {
+        if (q->graphs) {
+            e = hipGraphLaunch(s.exec, q->st);
+        } else {
+            char *d = static_cast<char *>(s.dev);
+            e = bi::launch_bigmul_v_binned(q->ctx->impl, q->tune, q->a, q->b, q->out,
+                                           reinterpret_cast<const bi_desc *>(d + kHeader),
+                                           reinterpret_cast<const uint32_t *>(d + kHeader + count * sizeof(bi_desc)),
+                                           reinterpret_cast<const uint32_t *>(d + kCountsAt), counts, q->limb_bits,
+                                           q->algo, q->scratch, q->st);
+        }
+    }
     if (e == hipSuccess) e = hipEventRecord(s.done, q->st);
     if (e != hipSuccess) return set_error(BI_EHIP, "burst launch: %s", hipGetErrorString(e));
     s.ticket = t;

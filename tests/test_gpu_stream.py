@@ -132,3 +132,33 @@ def test_stream_validation(B, ctx):
         t = q.submit(d)
         q.wait(t)
         assert t == 0 and q.poll(t)
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_stream_u64_limbs(B, ctx, orc, use_graph):
+    """64-bit limbs: classes come from n_limbs * 2 words (device binning with
+    a graph, host binning without), products bit-exact against the oracle."""
+    rng = np.random.default_rng(64)
+    count = 48
+    ns = np.maximum(1, np.rint(2.0 ** rng.uniform(0, 12, count))).astype(np.int64)  # 1 .. 4096 u64 limbs
+    ns[:4] = (1, 4096, 8, 2048)
+    tot = int(ns.sum())
+    A = rng.integers(0, 2**64, tot, dtype=np.uint64, endpoint=False)
+    Bv = rng.integers(0, 2**64, tot, dtype=np.uint64, endpoint=False)
+    off = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.uint64)
+    out_off = 2 * off
+    d = np.zeros(count, dtype=G.DESC_DTYPE)
+    d["a_off"], d["b_off"], d["out_off"], d["n_limbs"] = off, off, out_off, ns
+    dA, dB = G.to_dev(A), G.to_dev(Bv)
+    out = G.empty_dev((2 * tot,), np.uint64)
+    out.zero_()
+    with B.StreamQueue(ctx, dA, dB, out, 64, max_descs=32, use_graph=use_graph) as q:
+        t0 = q.submit(d[:32])
+        t1 = q.submit(d[32:])
+        q.wait(t0)
+        q.wait(t1)
+    got = G.from_dev(out, np.uint64)
+    for i in range(count):
+        n, ao, oo = int(ns[i]), int(off[i]), int(out_off[i])
+        want = orc.mul(A[ao: ao + n][None], Bv[ao: ao + n][None])[0]
+        assert (got[oo: oo + 2 * n] == want).all(), (i, n)
