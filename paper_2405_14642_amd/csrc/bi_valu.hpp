@@ -18,4 +18,11 @@ __device__ __forceinline__ void mac(uint64_t &acc, uint32_t &cnt, uint32_t a, ui
     asm("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(cnt), "=s"(unused) : "s"(cc));
 }
 
+// The same with a per-lane (VGPR) a.
+__device__ __forceinline__ void mac_v(uint64_t &acc, uint32_t &cnt, uint32_t a, uint32_t b) {
+    uint64_t cc, unused;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc), "=s"(cc) : "v"(a), "v"(b));
+    asm("v_addc_co_u32_e64 %0, %1, %0, 0, %2" : "+v"(cnt), "=s"(unused) : "s"(cc));
+}
+
 }  // namespace bi

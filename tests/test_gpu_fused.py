@@ -72,6 +72,20 @@ def test_sizes(B, ctx, orc, name, n):
     assert bad.size == 0, f"{name} n={n}: rows {bad.tolist()} differ"
 
 
+@pytest.mark.parametrize("name", ["poly", "mullow"])
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 17, 31, 32, 33, 64, 65, 96, 128, 130, 200, 255, 256])
+def test_packed_many_instances(B, ctx, orc, name, n):
+    """Instances of up to 256 words run several per wavefront: batches of
+    many wavefronts with a partial last one, every instance checked."""
+    rng = np.random.default_rng(500 + n)
+    batch = 333
+    a, b = operands(rng, batch, n)
+    got = run(B, ctx, PROGRAMS[name], a, b)
+    exp = want(orc, name, a, b)
+    bad = np.nonzero((got != exp).any(axis=1))[0]
+    assert bad.size == 0, f"{name} n={n}: rows {bad[:8].tolist()} differ"
+
+
 @pytest.mark.parametrize("name", list(PROGRAMS))
 def test_u64_limbs(B, ctx, orc, name):
     rng = np.random.default_rng(64)
@@ -82,7 +96,7 @@ def test_u64_limbs(B, ctx, orc, name):
 
 
 @pytest.mark.parametrize("name", list(PROGRAMS))
-@pytest.mark.parametrize("bits", [1 << 12, 1 << 15, 1 << 18])
+@pytest.mark.parametrize("bits", [1 << 10, 1 << 12, 1 << 15, 1 << 18])
 def test_paper_workload_sampled(B, ctx, orc, name, bits):
     """NumBits x NumInsts = 2^32 (the paper's batches, u64 limbs); every
     instance runs, 8 sampled instances are checked against the oracle."""
