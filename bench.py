@@ -88,6 +88,28 @@ def measured_traffic(kernel):
     return None
 
 
+def measured_large_traffic(case):
+    """HBM bytes of one bigadd_large call (all four kernels) from the committed
+    PMC summary, or None when the case is missing or the kernels' source
+    changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "bigadd_large_traffic.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(re.search(r"```json\s*(\{.*?\})\s*```", text, re.S).group(1))
+        src = b"".join(open(os.path.join(ROOT, "paper_2405_14642_amd", "csrc", f), "rb").read()
+                       for f in ("bigadd_large.hip", "bi_common.hpp"))
+    except (OSError, AttributeError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+        return None
+    for r in rec.get("calls", []):
+        if r.get("case") == case:
+            return r["traffic_bytes"]
+    return None
+
+
 def add_kernel_name(n_limbs, limb_bits):
     """Name of the addition kernel the library launches for this shape (16-byte
     chunks; mirrors the size classes of the launcher in csrc/bigadd.hip)."""
@@ -698,9 +720,11 @@ def bench_add_large(args):
     key = str(main_bits) if str(main_bits) in per_size else str(sizes[-1])
     main = per_size[key]["uniform"]
     nb = 12 * (int(key) // 32)
-    roofline = {"bound": "hbm", "kernel": "bigadd_large call (large_add_tile_kernel + scan + fix-up)",
+    case = f"2^{int(key).bit_length() - 1} bits uniform"
+    roofline = {"bound": "hbm", "kernel": "bigadd_large call (large_add_tile_kernel + scan + fix-up + walk)",
                 "achieved": main["GB_per_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(main["GB_per_s"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(main["GB_per_s"] / HBM_PEAK_GBS, 4), "traffic": measured_large_traffic(case),
+                "traffic_source": "profiles/bigadd_large_traffic.md",
                 "avg_launch_us": main["us_per_call"], "algorithmic_bytes_per_launch": nb}
     cpu = None if args.no_cpu else cpu_baseline_add_large(args, W, int(key))
     return {
