@@ -25,7 +25,11 @@
  * are reported as BI_EHIP; asynchronous device faults surface at the caller's
  * next synchronisation.  bi_last_error() gives a message for the last failing
  * call on the calling host thread.  A context is not thread-safe: use one per
- * host thread or serialise calls.
+ * host thread or serialise calls.  bigmul (NTT and large-product MFMA paths),
+ * bigmul_v and bigadd_large use one scratch buffer owned by the context: such
+ * calls on different streams of one context must not overlap in time (order
+ * them with events, or use a context per stream).  When a call needs more
+ * scratch than the context holds, it synchronises the device and reallocates.
  */
 #ifndef BIGINT_MI355X_H
 #define BIGINT_MI355X_H

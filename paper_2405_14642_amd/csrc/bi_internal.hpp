@@ -141,7 +141,7 @@ struct Ctx {
 };
 
 // Returns a device buffer of at least `bytes` owned by the context; growing it
-// synchronises `st` first so no queued kernel still uses the old buffer.
+// synchronises the device first so no queued kernel still uses the old buffer.
 bi_status ctx_scratch(Ctx &c, size_t bytes, hipStream_t st, void **out);
 
 bi_status ctx_init(Ctx &c, int device, const hipDeviceProp_t &prop);

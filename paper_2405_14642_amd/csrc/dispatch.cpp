@@ -67,7 +67,10 @@ bi_status ctx_scratch(Ctx &c, size_t bytes, hipStream_t st, void **out) {
         return BI_OK;
     }
     if (c.scratch.ptr) {
-        hipError_t e = hipStreamSynchronize(st);
+        // Every stream that used the old buffer must be done with it, not
+        // only `st`: growth is rare, so wait for the whole device.
+        (void)st;
+        hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return set_error(BI_EHIP, "scratch resize: %s", hipGetErrorString(e));
         (void)hipFree(c.scratch.ptr);
         c.scratch = Scratch{};
