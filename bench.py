@@ -338,8 +338,38 @@ def bench_mul(args, kind):
         "config": {"workload": "mul_quadratic" if kind == "mulq" else "mul_ntt",
                    "cases": [{"bits": c[0], "pairs": c[1]} for c in cases], "limb_bits": 32,
                    "algorithms": algos, "parallelism": "single-gpu"},
-        "roofline": dom.get("roofline"), "per_size": results, "cpu_baseline": None,
+        "roofline": dom.get("roofline"), "per_size": results,
+        "cpu_baseline": None if args.no_cpu else cpu_baseline_mul(args, kind, cases),
     }
+
+
+def cpu_baseline_mul(args, kind, cases):
+    """The oracle's schoolbook product on the first pairs of each size, one
+    task per pair, each size for an equal share of the time budget; products/s
+    over the sample."""
+    import oracle
+    import workloads as W
+    oracle.build()
+    orc = oracle.get()
+    budget = args.cpu_seconds / len(cases)
+    pairs, secs, threads, samples = 0, 0.0, 0, []
+    for bits, batch in cases:
+        cnt = min(batch, 64)
+        idx = np.arange(cnt, dtype=np.uint64)
+        a, b = W.mul_quad_inputs(bits, pairs=idx) if kind == "mulq" else W.ntt_inputs(bits, batch, pairs=idx)
+        t_size, n_size = 0.0, 0
+        while t_size < budget:
+            t = time.perf_counter()
+            orc.mul(a, b)
+            t_size += time.perf_counter() - t
+            n_size += cnt
+            threads = orc.last_threads
+        pairs += n_size
+        secs += t_size
+        samples.append(f"{cnt} pairs x{n_size // cnt} at 2^{bits.bit_length() - 1}")
+    return {"value": pairs / secs, "unit": "mults/s", "cores": threads, "kind": "oracle",
+            "sample": "first pairs of each size, repeated: " + "; ".join(samples),
+            "cpu_model": cpu_info(), "seconds": round(secs, 2)}
 
 
 def bench_stream(args):
