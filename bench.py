@@ -42,7 +42,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="add", choices=["add", "add_large", "mulq", "ntt", "stream", "copy", "fused"])
+    p.add_argument("--workload", default="add", choices=["add", "add_large", "mul_large", "mulq", "ntt", "stream", "copy", "fused"])
     p.add_argument("--stream-pairs", type=int, default=100000, help="pairs in the mixed-size stream")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU baseline budget")
@@ -768,6 +768,72 @@ def bench_add_large(args):
     }
 
 
+def bench_mul_large(args):
+    """One pair per size, 2^19..2^24 bits (u32 limbs, uniform), multiplied by
+    bigmul_large (k^2 block products of 2^18 bits through the batched
+    kernels, a column-sum fold and the multi-workgroup addition).  The
+    roofline is the butterfly rate of the block products' NTTs."""
+    import torch
+
+    import paper_2405_14642_amd as B
+    import workloads as W
+    from tests import gpu_util as G
+
+    ctx = B.Context(0)
+    B.autotune(ctx)
+    stream = torch.cuda.current_stream()
+    sizes = (1 << 19, 1 << 20, 1 << 22, 1 << 24)
+    if args.sizes:
+        sizes = tuple(int(x) for x in args.sizes.split(","))
+    per_size = {}
+    step_ms = 0.0
+    for bits in sizes:
+        n = bits // 32
+        a, b = W.large_add_inputs(n)
+        A, Bt = G.to_dev(a), G.to_dev(b)
+        out = G.empty_dev(2 * n, np.uint32)
+
+        def timed(algo):
+            for _ in range(args.warmup + 1):
+                B.bigmul_large(ctx, A, Bt, out, algo=algo, stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            evs = []
+            for _ in range(args.steps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                B.bigmul_large(ctx, A, Bt, out, algo=algo, stream=stream.cuda_stream)
+                e1.record(stream)
+                evs.append((e0, e1))
+            torch.cuda.synchronize()
+            return 1e3 * float(np.mean([x.elapsed_time(y) for x, y in evs]))
+
+        us = timed(B.MUL_AUTO)
+        k = (n + 8191) // 8192
+        bfly = 2.0 * 3 * k * k * (1 << 15) / 2 * 15  # two primes, three length-2^15 transforms per block product
+        per_size[str(bits)] = {"us_per_call": round(us, 2), "block_products": k * k, "mults_per_s": 1e6 / us,
+                               "butterflies_per_s": bfly / (us * 1e-6),
+                               "ntt_frac": round(bfly / (us * 1e-6) / NTT_BFLY_PEAK, 4),
+                               "us_per_call_by_block_algorithm": {
+                                   name: round(timed(ALGO_IDS[name]), 2) for name in ("mfma", "ntt")}}
+        step_ms += us / 1e3
+        del A, Bt, out
+    ctx.close()
+    key = str(1 << 20) if str(1 << 20) in per_size else str(sizes[-1])
+    main = per_size[key]
+    return {
+        "metric": f"bigmul_large products/s of one 2^{int(key).bit_length() - 1}-bit pair (u32 limbs)",
+        "value": main["mults_per_s"], "unit": "mults/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic (seeded splitmix64, uniform)",
+        "config": {"workload": "mul_large", "sizes_bits": list(sizes), "limb_bits": 32, "parallelism": "single-gpu"},
+        "roofline": {"bound": "alu", "achieved": round(main["butterflies_per_s"] / 1e12, 3),
+                     "peak": round(NTT_BFLY_PEAK / 1e12, 3), "unit": "T butterflies/s",
+                     "frac": main["ntt_frac"], "traffic": None},
+        "per_size": per_size, "cpu_baseline": None,
+    }
+
+
 def cpu_baseline_add_large(args, W, bits):
     import oracle
     oracle.build()
@@ -822,6 +888,8 @@ def main():
         res = bench_add(args)
     elif args.workload == "add_large":
         res = bench_add_large(args)
+    elif args.workload == "mul_large":
+        res = bench_mul_large(args)
     elif args.workload == "stream":
         res = bench_stream(args)
     elif args.workload == "copy":

@@ -31,7 +31,7 @@ EXPORTS = ("bi_ctx_create", "bi_ctx_destroy", "bi_status_str", "bi_last_error",
            "bigadd", "bigmul", "bigadd_v", "bigmul_v", "bi_ntt_field", "bi_autotune", "bi_tune_get",
            "bi_tune_set", "bi_stream_open", "bi_stream_submit", "bi_stream_poll", "bi_stream_wait",
            "bi_stream_close", "bi_fused", "bi_tune_get_valu",
-           "bi_tune_set_valu", "bigadd_large")
+           "bi_tune_set_valu", "bigadd_large", "bigmul_large")
 NUM_CLASSES = 10
 
 
@@ -71,6 +71,7 @@ def _load():
     L.bigadd.argtypes = [P, P, P, P, P, U32, U32, U64, P]
     L.bigmul.argtypes = [P, P, P, P, U32, U32, U64, I, P]
     L.bigadd_large.argtypes = [P, P, P, P, P, U64, U32, P]
+    L.bigmul_large.argtypes = [P, P, P, P, U64, U32, I, P]
     L.bigadd_v.argtypes = [P, P, P, P, P, P, U64, U32, P]
     L.bigmul_v.argtypes = [P, P, P, P, P, U64, U32, I, P]
     L.bi_ntt_field.argtypes = [U64, P]
@@ -88,7 +89,7 @@ def _load():
     for f in (L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field, L.bi_autotune,
               L.bi_tune_get, L.bi_tune_set, L.bi_stream_open, L.bi_stream_submit, L.bi_stream_poll,
               L.bi_stream_wait, L.bi_stream_close, L.bi_fused, L.bi_tune_get_valu,
-              L.bi_tune_set_valu, L.bigadd_large):
+              L.bi_tune_set_valu, L.bigadd_large, L.bigmul_large):
         f.restype = I
     return L
 
@@ -173,6 +174,15 @@ def bigadd_large(ctx, a, b, out, carry=None, n_limbs=None, limb_bits=None, strea
     lb = _limb_bits(a, limb_bits)
     n = n_limbs if n_limbs is not None else a.numel()
     _check(lib.bigadd_large(_h(ctx), _ptr(a), _ptr(b), _ptr(out), _ptr(carry), n, lb, _stream(stream, a)))
+    return out
+
+
+def bigmul_large(ctx, a, b, out, algo=MUL_AUTO, n_limbs=None, limb_bits=None, stream=None):
+    """out (2n limbs) = a * b for ONE pair of integers beyond 2^18 bits (1-D
+    limb tensors); algo picks the 2^18-bit block products' algorithm."""
+    lb = _limb_bits(a, limb_bits)
+    n = n_limbs if n_limbs is not None else a.numel()
+    _check(lib.bigmul_large(_h(ctx), _ptr(a), _ptr(b), _ptr(out), n, lb, int(algo), _stream(stream, a)))
     return out
 
 

@@ -171,6 +171,37 @@ bi_status bigadd_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
     return BI_OK;
 }
 
+bi_status bigmul_large(bi_ctx *ctx, const void *a, const void *b, void *out, uint64_t n_limbs, uint32_t limb_bits,
+                       int algo, void *stream) {
+    if (limb_bits != 32 && limb_bits != 64) return fail(BI_ELIMB, "limb_bits must be 32 or 64 (got %u)", limb_bits);
+    if (n_limbs == 0) return fail(BI_EINVAL, "n_limbs must be >= 1");
+    if (n_limbs > BI_MAX_LARGE_MUL_BITS / limb_bits)
+        return fail(BI_ESIZE, "n_limbs * limb_bits exceeds %u bits (n_limbs = %llu)", BI_MAX_LARGE_MUL_BITS,
+                    (unsigned long long)n_limbs);
+    if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT_PF64) return fail(BI_EINVAL, "unknown algorithm %d", algo);
+    if (algo != BI_MUL_AUTO && !bi::algo_supports(algo, bi::kMaxLimbs32))
+        return fail(BI_EALGO, "algorithm %d does not run 2^18-bit blocks", algo);
+    bi_status s;
+    if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
+    if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;
+    if ((s = check_ptr(out, limb_bits, "out")) != BI_OK) return s;
+    const uint64_t tot = n_limbs * (limb_bits / 8);
+    if (overlaps(out, 2 * tot, a, tot) || overlaps(out, 2 * tot, b, tot)) return fail(BI_EALIAS, "out overlaps an input");
+    if (!ctx) return fail(BI_EINVAL, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint64_t n32 = n_limbs * (limb_bits / 32);
+    void *scr = nullptr;
+    if ((s = bi::ctx_scratch(ctx->impl, bi::large_mul_scratch_bytes(n32, ctx->impl.num_cus), st, &scr)) != BI_OK)
+        return s;
+    if (algo == BI_MUL_AUTO) algo = bi::large_mul_auto_algo(ctx->impl, n32);
+    hipError_t e = bi::launch_bigmul_large(ctx->impl, static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
+                                           static_cast<uint32_t *>(out), n32, algo, static_cast<uint8_t *>(scr), st);
+    if (e != hipSuccess) return hip_fail(e, "bigmul_large launch");
+    return BI_OK;
+}
+
 bi_status bigmul(bi_ctx *ctx, const void *a, const void *b, void *out, uint32_t n_limbs, uint32_t limb_bits,
                  uint64_t batch, int algo, void *stream) {
     uint64_t ib = 0;

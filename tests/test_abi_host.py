@@ -89,6 +89,30 @@ def test_bigadd_large_validation(B, args, status):
 
 
 @pytest.mark.parametrize("args,status", [
+    (dict(limb_bits=16), -3),
+    (dict(n=0), -1),
+    (dict(n=(1 << 24) // 32 + 1), -2),
+    (dict(n=(1 << 24) // 64 + 1, limb_bits=64), -2),
+    (dict(a=None), -1),
+    (dict(out=None), -1),
+    (dict(a=FAKE + 2), -3),
+    (dict(out=FAKE + 8), -4),                     # out overlaps a
+    (dict(out=FAKE + (1 << 24) - 16), -4),        # out's 2n limbs reach into b
+    (dict(), -1),                                 # all valid, but ctx is NULL
+    (dict(n=(1 << 24) // 32), -1),                # the largest size passes the size check
+    (dict(algo=9), -1),                           # unknown algorithm
+    (dict(algo=-1), -1),
+    (dict(algo=4), -1),                           # every algorithm runs 2^18-bit blocks: fails only on ctx
+])
+def test_bigmul_large_validation(B, args, status):
+    p = dict(a=FAKE, b=FAKE + (1 << 24), out=FAKE + (2 << 24), n=4, limb_bits=32, algo=0)
+    p.update(args)
+    st = B.lib.bigmul_large(None, p["a"], p["b"], p["out"], p["n"], p["limb_bits"], p["algo"], None)
+    assert st == status, B.lib.bi_last_error()
+    assert B.lib.bi_last_error()
+
+
+@pytest.mark.parametrize("args,status", [
     (dict(limb_bits=8), -3),
     (dict(n=0), -1),
     (dict(n=8193), -2),

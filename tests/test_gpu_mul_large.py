@@ -1,0 +1,93 @@
+"""Parity of bigmul_large (one product beyond 2^18 bits, built from block
+products) with the CPU oracle's schoolbook product, bit-exact: sizes around
+the 8192-word block with ragged last blocks, all-ones operands (every column
+sum and carry at its largest), u32 and u64 limbs, and a 2^21-bit product."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+BLOCK = 8192
+
+
+@pytest.fixture(scope="module")
+def B():
+    import paper_2405_14642_amd as B
+    return B
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def run(B, ctx, a, b, algo=0):
+    A, Bt = G.to_dev(a), G.to_dev(b)
+    out = G.empty_dev(2 * a.shape[0], a.dtype)
+    B.bigmul_large(ctx, A, Bt, out, algo=algo)
+    G.sync()
+    return G.from_dev(out, a.dtype)
+
+
+def check(orc, a, b, got):
+    want = orc.mul(a[None, :], b[None, :])[0]
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{bad.size} limbs differ, first at {bad[:8]}"
+
+
+@pytest.mark.parametrize("n", [1, 5, BLOCK - 1, BLOCK, BLOCK + 1, 2 * BLOCK, 3 * BLOCK + 100, 4 * BLOCK - 7])
+def test_sizes_uniform(B, ctx, orc, n):
+    rng = np.random.default_rng(n + 11)
+    a = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    check(orc, a, b, run(B, ctx, a, b))
+
+
+@pytest.mark.parametrize("n", [BLOCK + 1, 3 * BLOCK + 100])
+def test_all_ones(B, ctx, orc, n):
+    a = np.full(n, 0xFFFFFFFF, dtype=np.uint32)
+    check(orc, a, a.copy(), run(B, ctx, a, a.copy()))
+    rng = np.random.default_rng(n)
+    b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    check(orc, a, b, run(B, ctx, a, b))
+
+
+def test_u64_limbs(B, ctx, orc):
+    n = BLOCK // 2 + 3  # 64-bit limbs: 8198 words, two blocks
+    rng = np.random.default_rng(64)
+    a = rng.integers(0, 2**64, n, dtype=np.uint64, endpoint=False)
+    b = rng.integers(0, 2**64, n, dtype=np.uint64, endpoint=False)
+    check(orc, a, b, run(B, ctx, a, b))
+
+
+def test_2_21_bits(B, ctx, orc):
+    n = 1 << 16  # 8 x 8 block products
+    rng = np.random.default_rng(21)
+    a = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    check(orc, a, b, run(B, ctx, a, b))
+
+
+def test_repeat_after_smaller(B, ctx, orc):
+    """Context scratch sized by a larger call serves a smaller one again."""
+    rng = np.random.default_rng(3)
+    for n in (5 * BLOCK + 1, BLOCK + 3):
+        a = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        check(orc, a, b, run(B, ctx, a, b))
+
+
+@pytest.mark.parametrize("algo", [1, 2, 3, 4])
+def test_block_algorithms(B, ctx, orc, algo):
+    """Every algorithm forced for the block products gives the same product."""
+    n = 2 * BLOCK + 3
+    rng = np.random.default_rng(algo)
+    a = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    check(orc, a, b, run(B, ctx, a, b, algo))
