@@ -772,7 +772,8 @@ def bench_mul_large(args):
     """One pair per size, 2^19..2^24 bits (u32 limbs, uniform), multiplied by
     bigmul_large (k^2 block products of 2^18 bits through the batched
     kernels, a column-sum fold and the multi-workgroup addition).  The
-    roofline is the butterfly rate of the block products' NTTs."""
+    roofline is that of the block products' tuned algorithm: int8 MFMA
+    operations (2 per digit product) or NTT butterflies."""
     import torch
 
     import paper_2405_14642_amd as B
@@ -780,7 +781,7 @@ def bench_mul_large(args):
     from tests import gpu_util as G
 
     ctx = B.Context(0)
-    B.autotune(ctx)
+    tuned = B.autotune(ctx)
     stream = torch.cuda.current_stream()
     sizes = (1 << 19, 1 << 20, 1 << 22, 1 << 24)
     if args.sizes:
@@ -793,29 +794,42 @@ def bench_mul_large(args):
         A, Bt = G.to_dev(a), G.to_dev(b)
         out = G.empty_dev(2 * n, np.uint32)
 
-        def timed(algo):
+        def timed(algo, block_bits=0):
             for _ in range(args.warmup + 1):
-                B.bigmul_large(ctx, A, Bt, out, algo=algo, stream=stream.cuda_stream)
+                B.bigmul_large(ctx, A, Bt, out, algo=algo, block_bits=block_bits, stream=stream.cuda_stream)
             torch.cuda.synchronize()
             evs = []
             for _ in range(args.steps):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-                B.bigmul_large(ctx, A, Bt, out, algo=algo, stream=stream.cuda_stream)
+                B.bigmul_large(ctx, A, Bt, out, algo=algo, block_bits=block_bits, stream=stream.cuda_stream)
                 e1.record(stream)
                 evs.append((e0, e1))
             torch.cuda.synchronize()
             return 1e3 * float(np.mean([x.elapsed_time(y) for x, y in evs]))
 
         us = timed(B.MUL_AUTO)
-        k = (n + 8191) // 8192
-        bfly = 2.0 * 3 * k * k * (1 << 15) / 2 * 15  # two primes, three length-2^15 transforms per block product
-        per_size[str(bits)] = {"us_per_call": round(us, 2), "block_products": k * k, "mults_per_s": 1e6 / us,
-                               "butterflies_per_s": bfly / (us * 1e-6),
-                               "ntt_frac": round(bfly / (us * 1e-6) / NTT_BFLY_PEAK, 4),
+        bw = 2048 if n <= (1 << 15) else 8192  # the library's default block size
+        k = (n + bw - 1) // bw
+        cls = (bw - 1).bit_length() - 4  # size class of a bw-word product
+        if tuned[cls] == ALGO_IDS["mfma"]:
+            ops = 2.0 * k * k * (4 * bw) ** 2  # int8 digit products of the block products
+            roof = {"bound": "mfma", "achieved": round(ops / (us * 1e-6) / 1e12, 1),
+                    "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "TOP/s (int8)",
+                    "frac": round(ops / (us * 1e-6) / MFMA_I8_PEAK_OPS, 4)}
+        else:
+            m = 4 * bw
+            bfly = 2.0 * 3 * k * k * m / 2 * (m.bit_length() - 1)  # two primes, three length-4bw transforms
+            roof = {"bound": "alu", "achieved": round(bfly / (us * 1e-6) / 1e12, 3),
+                    "peak": round(NTT_BFLY_PEAK / 1e12, 3), "unit": "T butterflies/s",
+                    "frac": round(bfly / (us * 1e-6) / NTT_BFLY_PEAK, 4)}
+        per_size[str(bits)] = {"us_per_call": round(us, 2), "block_bits": 32 * bw, "block_products": k * k,
+                               "block_algorithm": tuned[cls], "mults_per_s": 1e6 / us, "roofline": roof,
                                "us_per_call_by_block_algorithm": {
-                                   name: round(timed(ALGO_IDS[name]), 2) for name in ("mfma", "ntt")}}
+                                   name: round(timed(ALGO_IDS[name]), 2) for name in ("mfma", "ntt")},
+                               "us_per_call_by_block_bits": {
+                                   str(bb): round(timed(B.MUL_AUTO, bb), 2) for bb in (1 << 16, 1 << 17, 1 << 18)}}
         step_ms += us / 1e3
         del A, Bt, out
     ctx.close()
@@ -827,9 +841,7 @@ def bench_mul_large(args):
         "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic (seeded splitmix64, uniform)",
         "config": {"workload": "mul_large", "sizes_bits": list(sizes), "limb_bits": 32, "parallelism": "single-gpu"},
-        "roofline": {"bound": "alu", "achieved": round(main["butterflies_per_s"] / 1e12, 3),
-                     "peak": round(NTT_BFLY_PEAK / 1e12, 3), "unit": "T butterflies/s",
-                     "frac": main["ntt_frac"], "traffic": None},
+        "roofline": dict(main["roofline"], traffic=None),
         "per_size": per_size, "cpu_baseline": None,
     }
 

@@ -123,17 +123,19 @@ bi_status bigadd_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
  * a, b: n_limbs limbs of limb_bits (32 or 64) bits; 1 <= n_limbs and
  * n_limbs * limb_bits <= BI_MAX_LARGE_MUL_BITS (BI_EINVAL / BI_ESIZE);
  * out must not overlap a or b (BI_EALIAS); pointers limb-aligned (BI_ELIMB).
- * The operands are cut into k blocks of 2^18 bits; the k^2 block products run
- * as one ragged batch through the tuned per-size-class kernels, a column-sum
- * kernel folds them and bigadd_large's kernels add the low and high words.
- * algo: the block products' algorithm, BI_MUL_AUTO or one that runs 8192-limb
- * products (BI_EALGO otherwise; BI_EINVAL for an unknown value).
+ * The operands are cut into k blocks of block_bits bits (2^16, 2^17 or 2^18;
+ * 0 lets the library choose by size, other values BI_EINVAL); the k^2 block
+ * products run as one ragged batch through the tuned per-size-class kernels,
+ * a column-sum kernel folds them and bigadd_large's kernels add the low and
+ * high words.  algo: the block products' algorithm, BI_MUL_AUTO or one that
+ * runs products of that block size (BI_EALGO otherwise; BI_EINVAL for an
+ * unknown value).
  * Uses context scratch (about k^2 * 64 KB of block products plus the batch's
  * transform scratch; BI_ENOMEM if it cannot grow).  Asynchronous like every
  * call.
  */
 bi_status bigmul_large(bi_ctx *ctx, const void *a, const void *b, void *out, uint64_t n_limbs, uint32_t limb_bits,
-                       int algo, void *stream);
+                       int algo, uint32_t block_bits, void *stream);
 
 /*
  * bigmul -- full product, eq. (1) of Section 3.1 without truncation: for each

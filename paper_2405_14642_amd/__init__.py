@@ -71,7 +71,7 @@ def _load():
     L.bigadd.argtypes = [P, P, P, P, P, U32, U32, U64, P]
     L.bigmul.argtypes = [P, P, P, P, U32, U32, U64, I, P]
     L.bigadd_large.argtypes = [P, P, P, P, P, U64, U32, P]
-    L.bigmul_large.argtypes = [P, P, P, P, U64, U32, I, P]
+    L.bigmul_large.argtypes = [P, P, P, P, U64, U32, I, U32, P]
     L.bigadd_v.argtypes = [P, P, P, P, P, P, U64, U32, P]
     L.bigmul_v.argtypes = [P, P, P, P, P, U64, U32, I, P]
     L.bi_ntt_field.argtypes = [U64, P]
@@ -177,12 +177,14 @@ def bigadd_large(ctx, a, b, out, carry=None, n_limbs=None, limb_bits=None, strea
     return out
 
 
-def bigmul_large(ctx, a, b, out, algo=MUL_AUTO, n_limbs=None, limb_bits=None, stream=None):
+def bigmul_large(ctx, a, b, out, algo=MUL_AUTO, block_bits=0, n_limbs=None, limb_bits=None, stream=None):
     """out (2n limbs) = a * b for ONE pair of integers beyond 2^18 bits (1-D
-    limb tensors); algo picks the 2^18-bit block products' algorithm."""
+    limb tensors); algo and block_bits (0 = by size, else 2^16..2^18) pick
+    the block products."""
     lb = _limb_bits(a, limb_bits)
     n = n_limbs if n_limbs is not None else a.numel()
-    _check(lib.bigmul_large(_h(ctx), _ptr(a), _ptr(b), _ptr(out), n, lb, int(algo), _stream(stream, a)))
+    _check(lib.bigmul_large(_h(ctx), _ptr(a), _ptr(b), _ptr(out), n, lb, int(algo), int(block_bits),
+                            _stream(stream, a)))
     return out
 
 

@@ -172,15 +172,19 @@ bi_status bigadd_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
 }
 
 bi_status bigmul_large(bi_ctx *ctx, const void *a, const void *b, void *out, uint64_t n_limbs, uint32_t limb_bits,
-                       int algo, void *stream) {
+                       int algo, uint32_t block_bits, void *stream) {
     if (limb_bits != 32 && limb_bits != 64) return fail(BI_ELIMB, "limb_bits must be 32 or 64 (got %u)", limb_bits);
     if (n_limbs == 0) return fail(BI_EINVAL, "n_limbs must be >= 1");
     if (n_limbs > BI_MAX_LARGE_MUL_BITS / limb_bits)
         return fail(BI_ESIZE, "n_limbs * limb_bits exceeds %u bits (n_limbs = %llu)", BI_MAX_LARGE_MUL_BITS,
                     (unsigned long long)n_limbs);
     if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT_PF64) return fail(BI_EINVAL, "unknown algorithm %d", algo);
-    if (algo != BI_MUL_AUTO && !bi::algo_supports(algo, bi::kMaxLimbs32))
-        return fail(BI_EALGO, "algorithm %d does not run 2^18-bit blocks", algo);
+    if (block_bits != 0 && block_bits != (1u << 16) && block_bits != (1u << 17) && block_bits != (1u << 18))
+        return fail(BI_EINVAL, "block_bits must be 0, 2^16, 2^17 or 2^18 (got %u)", block_bits);
+    const uint64_t n32 = n_limbs * (limb_bits / 32);
+    const uint32_t bw = block_bits ? block_bits / 32 : bi::large_mul_auto_block(n32);
+    if (algo != BI_MUL_AUTO && !bi::algo_supports(algo, bw))
+        return fail(BI_EALGO, "algorithm %d does not run %u-bit blocks", algo, 32 * bw);
     bi_status s;
     if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
     if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;
@@ -191,13 +195,11 @@ bi_status bigmul_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     const hipStream_t st = static_cast<hipStream_t>(stream);
-    const uint64_t n32 = n_limbs * (limb_bits / 32);
     void *scr = nullptr;
-    if ((s = bi::ctx_scratch(ctx->impl, bi::large_mul_scratch_bytes(n32, ctx->impl.num_cus), st, &scr)) != BI_OK)
+    if ((s = bi::ctx_scratch(ctx->impl, bi::large_mul_scratch_bytes(n32, bw, ctx->impl.num_cus), st, &scr)) != BI_OK)
         return s;
-    if (algo == BI_MUL_AUTO) algo = bi::large_mul_auto_algo(ctx->impl, n32);
     hipError_t e = bi::launch_bigmul_large(ctx->impl, static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
-                                           static_cast<uint32_t *>(out), n32, algo, static_cast<uint8_t *>(scr), st);
+                                           static_cast<uint32_t *>(out), n32, bw, algo, static_cast<uint8_t *>(scr), st);
     if (e != hipSuccess) return hip_fail(e, "bigmul_large launch");
     return BI_OK;
 }

@@ -244,14 +244,15 @@ hipError_t launch_bigmul_v_binned(const Ctx &c, const Tune &tune, const void *a,
                                   const bi_desc *desc, const uint32_t *lists, const uint32_t *counts,
                                   const uint32_t *host_counts, uint32_t limb_bits, int algo, void *scratch,
                                   hipStream_t st);
-// Full product of one pair of n32 > 0 words through k^2 block products of
-// 2^18 bits; scratch holds large_mul_scratch_bytes(n32, num_cus) bytes,
-// 256-byte aligned.
-size_t large_mul_scratch_bytes(uint64_t n32, int num_cus);
+// Full product of one pair of n32 > 0 words through k^2 block products of bw
+// words (2048, 4096 or 8192); scratch holds large_mul_scratch_bytes(n32, bw,
+// num_cus) bytes, 256-byte aligned.
+size_t large_mul_scratch_bytes(uint64_t n32, uint32_t bw, int num_cus);
 hipError_t launch_bigmul_large(const Ctx &c, const uint32_t *a, const uint32_t *b, uint32_t *out, uint64_t n32,
-                               int algo, uint8_t *scratch, hipStream_t st);
-// Block-product algorithm bigmul_large uses for k^2 products under BI_MUL_AUTO.
-int large_mul_auto_algo(const Ctx &c, uint64_t n32);
+                               uint32_t bw, int algo, uint8_t *scratch, hipStream_t st);
+// Block size (words) bigmul_large takes for n32-word operands when the caller
+// leaves it to the library.
+uint32_t large_mul_auto_block(uint64_t n32);
 bi_status dispatch_bigmul_v(Ctx &c, const void *a, const void *b, void *out, const bi_desc *desc, uint64_t count,
                             uint32_t limb_bits, int algo, hipStream_t st);
 

@@ -103,11 +103,14 @@ def test_bigadd_large_validation(B, args, status):
     (dict(algo=9), -1),                           # unknown algorithm
     (dict(algo=-1), -1),
     (dict(algo=4), -1),                           # every algorithm runs 2^18-bit blocks: fails only on ctx
+    (dict(block=1 << 15), -1),                    # block sizes other than 2^16..2^18
+    (dict(block=(1 << 16) + 32), -1),
+    (dict(block=1 << 16, algo=3), -1),            # valid block and algorithm: fails only on ctx
 ])
 def test_bigmul_large_validation(B, args, status):
-    p = dict(a=FAKE, b=FAKE + (1 << 24), out=FAKE + (2 << 24), n=4, limb_bits=32, algo=0)
+    p = dict(a=FAKE, b=FAKE + (1 << 24), out=FAKE + (2 << 24), n=4, limb_bits=32, algo=0, block=0)
     p.update(args)
-    st = B.lib.bigmul_large(None, p["a"], p["b"], p["out"], p["n"], p["limb_bits"], p["algo"], None)
+    st = B.lib.bigmul_large(None, p["a"], p["b"], p["out"], p["n"], p["limb_bits"], p["algo"], p["block"], None)
     assert st == status, B.lib.bi_last_error()
     assert B.lib.bi_last_error()
 

@@ -27,10 +27,10 @@ def ctx(B):
     c.close()
 
 
-def run(B, ctx, a, b, algo=0):
+def run(B, ctx, a, b, algo=0, block_bits=0):
     A, Bt = G.to_dev(a), G.to_dev(b)
     out = G.empty_dev(2 * a.shape[0], a.dtype)
-    B.bigmul_large(ctx, A, Bt, out, algo=algo)
+    B.bigmul_large(ctx, A, Bt, out, algo=algo, block_bits=block_bits)
     G.sync()
     return G.from_dev(out, a.dtype)
 
@@ -91,3 +91,15 @@ def test_block_algorithms(B, ctx, orc, algo):
     a = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
     b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
     check(orc, a, b, run(B, ctx, a, b, algo))
+
+
+@pytest.mark.parametrize("block_bits", [1 << 16, 1 << 17, 1 << 18])
+@pytest.mark.parametrize("n", [2047, 2049, 3 * 4096 + 5, 40000])
+def test_block_sizes(B, ctx, orc, block_bits, n):
+    """Every block size gives the same product, around its block boundaries."""
+    rng = np.random.default_rng(n ^ block_bits)
+    a = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    if n == 2049:
+        a[:] = 0xFFFFFFFF
+    check(orc, a, b, run(B, ctx, a, b, block_bits=block_bits))
