@@ -103,3 +103,27 @@ def test_block_sizes(B, ctx, orc, block_bits, n):
     if n == 2049:
         a[:] = 0xFFFFFFFF
     check(orc, a, b, run(B, ctx, a, b, block_bits=block_bits))
+
+
+def _mod(x: np.ndarray, p: int) -> int:
+    """Value of a little-endian u32 limb array mod p (Horner, high limb first)."""
+    r = 0
+    for v in x[::-1].tolist():
+        r = (r * (1 << 32) + v) % p
+    return r
+
+
+def test_max_size_sampled(B, ctx, orc):
+    """2^24-bit operands (the largest size, 4096 block products): the lowest
+    8192 words equal the oracle's product of the operands' lowest 8192 words
+    (they depend on nothing else), and the whole product agrees with a * b
+    modulo three 61-bit primes."""
+    n = (1 << 24) // 32
+    rng = np.random.default_rng(24)
+    a = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    got = run(B, ctx, a, b)
+    low = orc.mul(a[None, :BLOCK], b[None, :BLOCK])[0][:BLOCK]
+    assert (got[:BLOCK] == low).all()
+    for p in ((1 << 61) - 1, (1 << 61) - 31, 2305843009213693921):
+        assert _mod(got, p) == _mod(a, p) * _mod(b, p) % p, p
