@@ -37,6 +37,21 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+class G:
+    """numpy limb arrays <-> device tensors (torch tensors as raw limb buffers)."""
+
+    @staticmethod
+    def to_dev(x):
+        import torch
+        x = np.ascontiguousarray(x)
+        return torch.from_numpy(x.view({4: np.int32, 8: np.int64}[x.dtype.itemsize])).to("cuda")
+
+    @staticmethod
+    def empty_dev(shape, dtype):
+        import torch
+        return torch.empty(shape, dtype=torch.int32 if np.dtype(dtype).itemsize == 4 else torch.int64, device="cuda")
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -130,7 +145,6 @@ def bench_add(args):
 
     import paper_2405_14642_amd as B
     import workloads as W
-    from tests import gpu_util as G
 
     ctx = B.Context(0)
     stream = torch.cuda.current_stream()
@@ -237,7 +251,6 @@ def bench_mul(args, kind):
 
     import paper_2405_14642_amd as B
     import workloads as W
-    from tests import gpu_util as G
 
     ctx = B.Context(0)
     stream = torch.cuda.current_stream()
@@ -390,7 +403,6 @@ def bench_stream(args):
 
     import paper_2405_14642_amd as B
     import workloads as W
-    from tests import gpu_util as G
 
     count = args.stream_pairs
     n, ones = W.stream_sizes(count)
@@ -555,7 +567,6 @@ def bench_fused(args):
 
     import paper_2405_14642_amd as B
     import workloads as W
-    from tests import gpu_util as G
 
     ctx = B.Context(0)
     stream = torch.cuda.current_stream()
@@ -702,7 +713,6 @@ def bench_add_large(args):
 
     import paper_2405_14642_amd as B
     import workloads as W
-    from tests import gpu_util as G
 
     ctx = B.Context(0)
     stream = torch.cuda.current_stream()
@@ -778,7 +788,6 @@ def bench_mul_large(args):
 
     import paper_2405_14642_amd as B
     import workloads as W
-    from tests import gpu_util as G
 
     ctx = B.Context(0)
     tuned = B.autotune(ctx)

@@ -12,6 +12,8 @@ What it computes (plain definitions, Section 2 and eq. (1) of Section 3.1):
   beside the paper's same-length sum.
 * ``mul(a, b)``  -> the full 2n-limb product a * b (schoolbook rows); the
   paper's same-length product is its low n limbs.
+* ``add_ragged`` / ``mul_ragged`` -> the same per pair over a list of pairs
+  of different lengths (one C call, pairs in parallel).
 * ``mul_low(a, b)`` -> the paper's same-length product (Figs. 4-5): the low
   n limbs of ``mul``.
 * ``add6(a, b)`` and ``poly(a, b)`` -> the fused programs of Section 6.1 in
@@ -106,20 +108,47 @@ class Oracle:
                                                 n, batch, threads)
         return out.view(dtype).reshape(batch, -1)
 
-    def mul_ragged(self, pairs, threads: int = 0):
-        """pairs: list of (a, b) uint32 1-D arrays of equal length per pair."""
+    @staticmethod
+    def _ragged_layout(pairs, out_per_limb):
+        """Concatenated operands of a list of pairs: a in pair order, b in
+        reverse pair order, results with one spare limb between pairs (so
+        the three offset arrays all differ)."""
         ns = np.array([len(p[0]) for p in pairs], dtype=np.uint32)
-        off = np.zeros(len(pairs), dtype=np.uint64)
-        if len(pairs) > 1:
-            off[1:] = np.cumsum(ns[:-1].astype(np.uint64))
-        A = np.concatenate([np.asarray(p[0], dtype=np.uint32) for p in pairs]) if pairs else np.zeros(0, np.uint32)
-        B = np.concatenate([np.asarray(p[1], dtype=np.uint32) for p in pairs]) if pairs else np.zeros(0, np.uint32)
-        out = np.empty(int(2 * ns.astype(np.uint64).sum()), dtype=np.uint32)
-        ooff = (2 * off).astype(np.uint64)
+        cnt = len(pairs)
+        n64 = ns.astype(np.uint64)
+        a_off = np.zeros(cnt, dtype=np.uint64)
+        b_off = np.zeros(cnt, dtype=np.uint64)
+        o_off = np.zeros(cnt, dtype=np.uint64)
+        if cnt > 1:
+            a_off[1:] = np.cumsum(n64[:-1])
+            b_off[:-1] = np.cumsum(n64[::-1])[::-1][1:]
+            o_off[1:] = np.cumsum(out_per_limb * n64[:-1] + 1)
+        A = np.zeros(int(n64.sum()), np.uint32)
+        B = np.zeros(int(n64.sum()), np.uint32)
+        for p, (x, y) in enumerate(pairs):
+            A[int(a_off[p]): int(a_off[p]) + int(ns[p])] = np.asarray(x, dtype=np.uint32)
+            B[int(b_off[p]): int(b_off[p]) + int(ns[p])] = np.asarray(y, dtype=np.uint32)
+        total_out = int(o_off[-1]) + out_per_limb * int(ns[-1]) + 1 if cnt else 0
+        return ns, A, B, a_off, b_off, o_off, np.zeros(total_out, np.uint32)
+
+    def mul_ragged(self, pairs, threads: int = 0):
+        """pairs: list of (a, b) uint32 1-D arrays of equal length per pair;
+        returns the list of 2n-limb products."""
+        ns, A, B, ao, bo, oo, out = self._ragged_layout(pairs, 2)
         self.last_threads = self.lib.oracle_mul_ragged(A.ctypes.data, B.ctypes.data, out.ctypes.data,
-                                                       off.ctypes.data, off.ctypes.data, ooff.ctypes.data,
+                                                       ao.ctypes.data, bo.ctypes.data, oo.ctypes.data,
                                                        ns.ctypes.data, len(pairs), threads)
-        return [out[int(o):int(o) + 2 * int(k)] for o, k in zip(ooff, ns)]
+        return [out[int(o):int(o) + 2 * int(k)] for o, k in zip(oo, ns)]
+
+    def add_ragged(self, pairs, threads: int = 0):
+        """pairs: list of (a, b) uint32 1-D arrays of equal length per pair;
+        returns the list of (sum mod 2^(32 n), carry out) per pair."""
+        ns, A, B, ao, bo, oo, out = self._ragged_layout(pairs, 1)
+        carry = np.empty(len(pairs), dtype=np.uint8)
+        self.last_threads = self.lib.oracle_add_ragged(A.ctypes.data, B.ctypes.data, out.ctypes.data,
+                                                       carry.ctypes.data, ao.ctypes.data, bo.ctypes.data,
+                                                       oo.ctypes.data, ns.ctypes.data, len(pairs), threads)
+        return [(out[int(o):int(o) + int(k)], int(c)) for o, k, c in zip(oo, ns, carry)]
 
 
 _default: Oracle | None = None
@@ -144,6 +173,10 @@ def mul(a, b, threads: int = 0):
 
 def mul_ragged(pairs, threads: int = 0):
     return get().mul_ragged(pairs, threads)
+
+
+def add_ragged(pairs, threads: int = 0):
+    return get().add_ragged(pairs, threads)
 
 
 def mul_low(a, b, threads: int = 0):

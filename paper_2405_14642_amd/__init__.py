@@ -119,6 +119,30 @@ def _stream(stream, ref=None):
     return torch.cuda.current_stream(dev).cuda_stream
 
 
+def _require(*args):
+    """Host-side check of the tensor arguments before any library call:
+    each (name, tensor, bytes needed[, element width]) must be contiguous,
+    hold at least that many bytes, have elements of that width when given,
+    and (checked last, for all of them) live on the GPU.  Plain int
+    addresses and None are passed through unchecked."""
+    ts = [x for x in args if x[1] is not None and not isinstance(x[1], int)]
+    for name, t, nbytes, *width in ts:
+        have = t.numel() * t.element_size()
+        if width and width[0] is not None and t.element_size() != width[0]:
+            raise ValueError(f"{name} has {t.element_size()}-byte elements, the other operands {width[0]}-byte ones")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if have < nbytes:
+            raise ValueError(f"{name} holds {have} bytes, the call needs {nbytes}")
+    for name, t, *_ in ts:
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+
+
+def _width(t):
+    return None if t is None or isinstance(t, int) else t.element_size()
+
+
 def _limb_bits(t, limb_bits):
     if limb_bits is not None:
         return limb_bits
@@ -164,6 +188,8 @@ def bigadd(ctx, a, b, out, carry=None, n_limbs=None, limb_bits=None, batch=None,
     lb = _limb_bits(a, limb_bits)
     n = n_limbs if n_limbs is not None else a.shape[-1]
     bt = batch if batch is not None else (a.numel() // n if n else 0)
+    w, nb = _width(a), n * bt * lb // 8
+    _require(("a", a, nb, w), ("b", b, nb, w), ("out", out, nb, w), ("carry", carry, bt))
     _check(lib.bigadd(_h(ctx), _ptr(a), _ptr(b), _ptr(out), _ptr(carry), n, lb, bt, _stream(stream, a)))
     return out
 
@@ -173,6 +199,8 @@ def bigadd_large(ctx, a, b, out, carry=None, n_limbs=None, limb_bits=None, strea
     a one-byte device tensor or None."""
     lb = _limb_bits(a, limb_bits)
     n = n_limbs if n_limbs is not None else a.numel()
+    w, nb = _width(a), n * lb // 8
+    _require(("a", a, nb, w), ("b", b, nb, w), ("out", out, nb, w), ("carry", carry, 1))
     _check(lib.bigadd_large(_h(ctx), _ptr(a), _ptr(b), _ptr(out), _ptr(carry), n, lb, _stream(stream, a)))
     return out
 
@@ -183,6 +211,8 @@ def bigmul_large(ctx, a, b, out, algo=MUL_AUTO, block_bits=0, n_limbs=None, limb
     the block products."""
     lb = _limb_bits(a, limb_bits)
     n = n_limbs if n_limbs is not None else a.numel()
+    w, nb = _width(a), n * lb // 8
+    _require(("a", a, nb, w), ("b", b, nb, w), ("out", out, 2 * nb, w))
     _check(lib.bigmul_large(_h(ctx), _ptr(a), _ptr(b), _ptr(out), n, lb, int(algo), int(block_bits),
                             _stream(stream, a)))
     return out
@@ -193,6 +223,8 @@ def bigmul(ctx, a, b, out, algo=MUL_AUTO, n_limbs=None, limb_bits=None, batch=No
     lb = _limb_bits(a, limb_bits)
     n = n_limbs if n_limbs is not None else a.shape[-1]
     bt = batch if batch is not None else (a.numel() // n if n else 0)
+    w, nb = _width(a), n * bt * lb // 8
+    _require(("a", a, nb, w), ("b", b, nb, w), ("out", out, 2 * nb, w))
     _check(lib.bigmul(_h(ctx), _ptr(a), _ptr(b), _ptr(out), n, lb, bt, int(algo), _stream(stream, a)))
     return out
 
@@ -204,6 +236,8 @@ def fused(ctx, program, a, b, out, n_limbs=None, limb_bits=None, batch=None, str
     lb = _limb_bits(a, limb_bits)
     n = n_limbs if n_limbs is not None else a.shape[-1]
     bt = batch if batch is not None else (a.numel() // n if n else 0)
+    w, nb = _width(a), n * bt * lb // 8
+    _require(("a", a, nb, w), ("b", b, nb, w), ("out", out, nb, w))
     _check(lib.bi_fused(_h(ctx), int(program), _ptr(a), _ptr(b), _ptr(out), n, lb, bt, _stream(stream, a)))
     return out
 
@@ -211,6 +245,7 @@ def fused(ctx, program, a, b, out, n_limbs=None, limb_bits=None, batch=None, str
 def bigadd_v(ctx, a, b, out, carry, desc, count, limb_bits, stream=None):
     """Ragged addition; desc is a device buffer of `count` bi_desc records
     (uint64 a_off, b_off, out_off; uint32 n_limbs, reserved)."""
+    _require(("desc", desc, 32 * count), ("carry", carry, count))
     _check(lib.bigadd_v(_h(ctx), _ptr(a), _ptr(b), _ptr(out), _ptr(carry), _ptr(desc), count, limb_bits,
                         _stream(stream, a)))
     return out
@@ -260,6 +295,8 @@ def ntt_field(p: int) -> NttFieldInfo:
 
 
 def bigmul_v(ctx, a, b, out, desc, count, limb_bits, algo=MUL_AUTO, stream=None):
+    """Ragged multiplication; desc as for bigadd_v (results of 2 n_limbs limbs)."""
+    _require(("desc", desc, 32 * count))
     _check(lib.bigmul_v(_h(ctx), _ptr(a), _ptr(b), _ptr(out), _ptr(desc), count, limb_bits, int(algo),
                         _stream(stream, a)))
     return out

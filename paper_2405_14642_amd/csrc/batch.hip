@@ -28,13 +28,31 @@ __global__ void zero_words_kernel(uint32_t *p, uint32_t n) {
 __global__ void bin_kernel(const bi_desc *__restrict__ desc, uint64_t count, const uint64_t *count_ptr,
                            uint32_t words_per_limb, uint32_t *counts, uint32_t *lists, uint64_t stride) {
     if (count_ptr) count = min(*count_ptr, stride);
-    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
-         i += uint64_t(gridDim.x) * blockDim.x) {
-        const uint32_t n32 = desc[i].n_limbs * words_per_limb;
-        if (n32 == 0 || n32 > kMaxLimbs32) continue;
-        const uint32_t c = size_class(n32);
-        const uint32_t slot = atomicAdd(&counts[c], 1u);
-        lists[uint64_t(c) * stride + slot] = uint32_t(i);
+    const uint32_t lane = lane_id();
+    const uint64_t below = (uint64_t(1) << lane) - 1;  // lanes under this one
+    const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
+    // whole wavefronts walk the descriptors together, so the ballots below
+    // see every lane of the wave
+    for (uint64_t i0 = uint64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63u); i0 < count; i0 += step) {
+        const uint64_t i = i0 + lane;
+        uint32_t c = kNumClasses;  // no class: past the end, or a skipped descriptor
+        if (i < count) {
+            const uint32_t n32 = desc[i].n_limbs * words_per_limb;
+            if (n32 != 0 && n32 <= kMaxLimbs32) c = size_class(n32);
+        }
+        // one atomic per class present in the wave: the lowest lane of the
+        // class reserves the slots, each lane takes its rank among them
+        uint64_t todo = __ballot(c < kNumClasses);
+        while (todo) {
+            const uint32_t leader = uint32_t(__ffsll(static_cast<unsigned long long>(todo)) - 1);
+            const uint32_t cl = __shfl(c, int(leader));
+            const uint64_t same = __ballot(c == cl);
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&counts[cl], uint32_t(__popcll(same)));
+            base = __shfl(base, int(leader));
+            if (c == cl) lists[uint64_t(cl) * stride + base + uint32_t(__popcll(same & below))] = uint32_t(i);
+            todo &= ~same;
+        }
     }
 }
 

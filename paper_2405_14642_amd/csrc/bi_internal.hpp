@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "../../include/bigint.h"
 
 namespace bi {
@@ -192,7 +194,7 @@ hipError_t launch_bigmul_ntt_list(const NttConst &K, const ListInst &src, uint32
                                   uint32_t *scratch, hipStream_t st, int num_cus);
 // Ragged NTT classes run in rounds of at most kNttListChunk instances of the
 // longest transform (more at shorter lengths); scratch for `count` instances.
-constexpr uint64_t kNttListChunk = 4096;
+constexpr uint64_t kNttListChunk = 1024;
 size_t ntt_list_scratch_bytes(uint64_t count);
 
 // PrimeField64 NTT multiplication: four half-length transforms per pair (2
@@ -257,6 +259,12 @@ bi_status dispatch_bigmul_v(Ctx &c, const void *a, const void *b, void *out, con
                             uint32_t limb_bits, int algo, hipStream_t st);
 
 bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out);
+
+// Raises kernel `fn`'s dynamic-LDS limit to a whole CU (160 KiB) on the
+// current device, once per device: `done` holds one bit per device id (ids
+// of 64 and above set the attribute on every call).  Thread-safe: a racing
+// second caller repeats the idempotent attribute set.
+hipError_t lds_limit_once(const void *fn, std::atomic<uint64_t> &done);
 
 // Sets the calling thread's bi_last_error() message and returns s.
 bi_status set_error(bi_status s, const char *fmt, ...);

@@ -116,21 +116,6 @@ __device__ __forceinline__ uint32_t add_instance_streamed(const uint32_t *__rest
     return cin_row;
 }
 
-template <int W, int U, bool NT>
-__global__ __launch_bounds__(256) void bigadd_stream_kernel(const uint32_t *__restrict__ a,
-                                                            const uint32_t *__restrict__ b,
-                                                            uint32_t *out, uint8_t *carry,
-                                                            uint32_t m, uint64_t batch) {
-    const uint32_t lane = lane_id();
-    const uint64_t wave = wave_global();
-    const uint64_t nwaves = (uint64_t(gridDim.x) * blockDim.x) >> 6;
-    for (uint64_t inst = wave; inst < batch; inst += nwaves) {
-        const uint64_t off = inst * m * W;
-        const uint32_t c = add_instance_streamed<W, U, NT>(a + off, b + off, out + off, m, lane);
-        if (carry && lane == 0) carry[inst] = uint8_t(c);
-    }
-}
-
 // Ragged batch: one wavefront per descriptor, chunks of one limb (W words).
 template <int W, int U>
 __global__ __launch_bounds__(256) void bigadd_ragged_kernel(const uint32_t *__restrict__ a,

@@ -302,11 +302,11 @@ static hipError_t launch_nw(const Src &src, uint32_t nmax, uint64_t count, hipSt
     const MfmaLayout lo = mfma_layout((nmax + 7) & ~7u);
     const void *fn = reinterpret_cast<const void *>(&bigmul_mfma_kernel<NW, OCC, Src>);
     // (LDS bytes << 32 | resident workgroups per CU) of the last launch shape
-    static std::atomic<uint64_t> occ{0};
+    static std::atomic<uint64_t> occ{0}, lds_set{0};
+    hipError_t e = lds_limit_once(fn, lds_set);
+    if (e != hipSuccess) return e;
     uint64_t o = occ.load(std::memory_order_relaxed);
     if ((o >> 32) != lo.total) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
         int nblk = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, fn, 64 * NW, lo.total);
         if (e != hipSuccess) return e;

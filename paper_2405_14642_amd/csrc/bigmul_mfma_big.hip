@@ -250,11 +250,12 @@ template <class Src>
 static hipError_t launch_big(const Src &src, uint32_t nmax, uint64_t count_max, uint64_t chunk, uint8_t *scr,
                              hipStream_t st, int num_cus) {
     static std::atomic<int> occ{0};
+    static std::atomic<uint64_t> lds_set{0};
     int nblk = occ.load(std::memory_order_relaxed);
     const void *fn = reinterpret_cast<const void *>(&mfma_big_kernel<Src>);
+    hipError_t e = lds_limit_once(fn, lds_set);
+    if (e != hipSuccess) return e;
     if (nblk == 0) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, fn, 256, kLdsTotal);
         if (e != hipSuccess) return e;
         if (nblk < 1) nblk = 1;

@@ -579,13 +579,9 @@ static hipError_t launch_crt_nw(const Coef &coef, const Src &src, uint64_t base,
                                 uint32_t nmax, hipStream_t st) {
     const uint32_t ngroups = (2 * nmax + 3) / 4;
     const size_t lds = sizeof(uint32_t) * (4 * ngroups + 2 * ngroups + NW);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_crt_carry_kernel<NW, Src, Coef>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    static std::atomic<uint64_t> lds_set{0};
+    hipError_t e = lds_limit_once(reinterpret_cast<const void *>(&ntt_crt_carry_kernel<NW, Src, Coef>), lds_set);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((ntt_crt_carry_kernel<NW, Src, Coef>), dim3(uint32_t(grid)), dim3(64 * NW), lds, st, coef, src,
                        base, chunk);
     return hipGetLastError();
@@ -620,15 +616,12 @@ template <int M, class Src>
 static hipError_t launch_ntt_m(const NttConst &K, const Src &src, uint32_t nmax, uint64_t count_max, uint64_t chunk,
                                uint64_t cap, uint32_t *tr, hipStream_t st) {
     const size_t lds = sizeof(uint32_t) * ((1u << M) + (1u << M) / 32);
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_fwd_kernel<M, Src>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&ntt_inv_kernel<M, Src>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    static std::atomic<uint64_t> lds_set[2];
+    for (int i = 0; i < 2; ++i) {
+        const void *fn = i ? reinterpret_cast<const void *>(&ntt_inv_kernel<M, Src>)
+                           : reinterpret_cast<const void *>(&ntt_fwd_kernel<M, Src>);
+        const hipError_t e = lds_limit_once(fn, lds_set[i]);
         if (e != hipSuccess) return e;
-        attr = true;
     }
     const uint32_t T = (1u << M) / E;
     const uint32_t L = 1u << M;
@@ -707,13 +700,10 @@ static hipError_t launch_ntt64_m(const NttConst64 &K, const Src &src, uint32_t n
     const size_t lds = sizeof(uint64_t) * ((1u << M) + (1u << M) / 32);
     const void *fns[2] = {reinterpret_cast<const void *>(&ntt64_fwd_kernel<M, Src>),
                           reinterpret_cast<const void *>(&ntt64_inv_kernel<M, Src>)};
-    static bool attr = false;
-    if (!attr) {
-        for (const void *fn : fns) {
-            const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            if (e != hipSuccess) return e;
-        }
-        attr = true;
+    static std::atomic<uint64_t> lds_set[2];
+    for (int i = 0; i < 2; ++i) {
+        const hipError_t e = lds_limit_once(fns[i], lds_set[i]);
+        if (e != hipSuccess) return e;
     }
     const uint32_t T = (1u << M) / E;
     const Half64Coef coef{tr, 1u << M};

@@ -183,13 +183,9 @@ size_t valu_lds_bytes(uint32_t n, int Q, int NW) {
 
 template <int Q, int NW, class Src>
 static hipError_t launch_q(const Src &src, size_t lds, uint32_t grid, hipStream_t st) {
-    static bool attr_set = false;  // allow up to the whole 160 KiB LDS of a CU
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&bigmul_valu_kernel<Q, NW, Src>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<uint64_t> lds_set{0};  // allow up to the whole 160 KiB LDS of a CU
+    hipError_t e = lds_limit_once(reinterpret_cast<const void *>(&bigmul_valu_kernel<Q, NW, Src>), lds_set);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((bigmul_valu_kernel<Q, NW, Src>), dim3(grid), dim3(64 * NW), lds, st, src);
     return hipGetLastError();
 }

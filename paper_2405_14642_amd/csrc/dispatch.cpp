@@ -8,6 +8,17 @@
 
 namespace bi {
 
+hipError_t lds_limit_once(const void *fn, std::atomic<uint64_t> &done) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = dev >= 0 && dev < 64 ? uint64_t(1) << dev : 0;
+    if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_release);
+    return e;
+}
+
 bool algo_supports(int algo, uint32_t n32) {
     switch (algo) {
         case BI_MUL_SCHOOL_VALU: return n32 >= 1 && n32 <= kMaxLimbs32;

@@ -592,14 +592,14 @@ hipError_t launch_persistent(uint32_t threads, size_t lds, const uint32_t *a, co
     const void *fn = reinterpret_cast<const void *>(kernel);
     // ((LDS bytes + 1) << 32 | resident workgroups per CU) of the last launch
     // of this kernel (0: none yet)
-    static std::atomic<uint64_t> occ{0};
+    static std::atomic<uint64_t> occ{0}, lds_set{0};
+    hipError_t e = hipSuccess;
+    if (lds > 0) {  // kernels with dynamic LDS may use all of a CU's
+        e = lds_limit_once(fn, lds_set);
+        if (e != hipSuccess) return e;
+    }
     uint64_t o = occ.load(std::memory_order_relaxed);
     if ((o >> 32) != lds + 1) {
-        hipError_t e = hipSuccess;
-        if (lds > 0) {  // kernels with dynamic LDS may use all of a CU's
-            e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            if (e != hipSuccess) return e;
-        }
         int nblk = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, fn, int(threads), lds);
         if (e != hipSuccess) return e;

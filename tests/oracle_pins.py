@@ -201,6 +201,16 @@ def check_ragged(orc):
     outs = orc.mul_ragged(pairs)
     for (x, y), o in zip(pairs, outs):
         assert O.to_int(o) == O.to_int(x) * O.to_int(y)
+    # ragged sums, with an all-ones + 1 pair (the carry crosses every limb)
+    # and an all-ones + all-ones pair among them
+    pairs.append((np.full(7, 0xFFFFFFFF, np.uint32), np.array([1, 0, 0, 0, 0, 0, 0], np.uint32)))
+    pairs.append((np.full(3, 0xFFFFFFFF, np.uint32), np.full(3, 0xFFFFFFFF, np.uint32)))
+    sums = orc.add_ragged(pairs)
+    for (x, y), (o, c) in zip(pairs, sums):
+        n = len(x)
+        s = O.to_int(x) + O.to_int(y)
+        assert len(o) == n and O.to_int(o) == s % (1 << (32 * n)) and c == s >> (32 * n)
+    assert sums[-2][1] == 1 and not sums[-2][0].any()
 
 
 ALL_FAST = (check_add_bruteforce, check_mul_bruteforce, check_closed_forms, check_invariants,

@@ -202,3 +202,36 @@ def test_stream_validation_host(B):
     assert B.lib.bi_stream_poll(None, 0, ctypes.byref(done)) == -1
     assert B.lib.bi_stream_wait(None, 0) == -1
     assert B.lib.bi_stream_close(None) == 0
+
+
+def test_binding_checks_tensor_arguments(B):
+    """The binding rejects tensors too short for the call, limb-width
+    mismatches, non-contiguous views and host tensors with ValueError before
+    any library call (so a bad tensor can never reach a kernel)."""
+    import torch
+    a = torch.zeros((4, 8), dtype=torch.int32)
+    short = torch.zeros((4, 7), dtype=torch.int32)
+    prod = torch.zeros((4, 16), dtype=torch.int32)
+    with pytest.raises(ValueError, match="b holds"):
+        B.bigmul(None, a, short, prod)
+    with pytest.raises(ValueError, match="out holds"):
+        B.bigmul(None, a, a, a)                              # the product needs 2n limbs
+    with pytest.raises(ValueError, match="out holds"):
+        B.bigadd(None, a, a, short)
+    with pytest.raises(ValueError, match="carry holds"):
+        B.bigadd(None, a, a, a, torch.zeros(3, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="byte elements"):
+        B.bigadd(None, a, a.to(torch.int64), a)
+    with pytest.raises(ValueError, match="contiguous"):
+        B.bigadd(None, a, prod[:, :8], a)
+    with pytest.raises(ValueError, match="out holds"):
+        B.fused(None, B.PROG_POLY, a, a, short)
+    x = torch.zeros(100, dtype=torch.int32)
+    with pytest.raises(ValueError, match="out holds"):
+        B.bigmul_large(None, x, x, torch.zeros(199, dtype=torch.int32))
+    with pytest.raises(ValueError, match="b holds"):
+        B.bigadd_large(None, x, x[:99], x)
+    with pytest.raises(ValueError, match="desc holds"):
+        B.bigmul_v(None, x, x, x, torch.zeros(63, dtype=torch.uint8), 2, 32)
+    with pytest.raises(ValueError, match="device tensor"):
+        B.bigmul(None, a, a, prod)                           # right sizes, host memory

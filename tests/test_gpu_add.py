@@ -1,6 +1,8 @@
 """Parity of the HIP addition kernels with the CPU oracle (bit-exact)."""
 from __future__ import annotations
 
+import zlib
+
 import numpy as np
 import pytest
 
@@ -145,13 +147,13 @@ def test_ragged(B, ctx, orc):
         G.sync()
         got = G.from_dev(dev_out, dt)
         cg = carry.cpu().numpy()
+        pairs = [(A[int(a_off[i]): int(a_off[i]) + n].view(np.uint32), Bv[int(bpos[i]): int(bpos[i]) + n].view(np.uint32))
+                 for i, n in enumerate(ns.tolist())]
+        want = orc.add_ragged(pairs)
         for i, n in enumerate(ns.tolist()):
-            ao, bo, oo = int(a_off[i]), int(bpos[i]), int(out_off[i])
-            x = A[ao: ao + n][None]
-            y = Bv[bo: bo + n][None]
-            want, wc = orc.add(x, y)
-            assert (got[oo: oo + n] == want[0]).all(), i
-            assert cg[i] == wc[0], i
+            oo = int(out_off[i])
+            assert (got[oo: oo + n].view(np.uint32) == want[i][0]).all(), i
+            assert cg[i] == want[i][1], i
 
 
 @pytest.mark.parametrize("bits", W.ADD_SWEEP_BITS)
@@ -171,7 +173,7 @@ def test_tuning_variants(B, orc, tune, monkeypatch):
     monkeypatch.setenv("BI_ADD_TUNE", tune)
     c = B.Context(0)
     try:
-        rng = np.random.default_rng(hash(tune) & 0xFFFF)
+        rng = np.random.default_rng(zlib.crc32(tune.encode()))
         for n, dt in ((1, np.uint32), (100, np.uint32), (128, np.uint64), (255, np.uint64), (256, np.uint64),
                       (300, np.uint64), (512, np.uint64), (1000, np.uint32), (2048, np.uint64), (4096, np.uint64)):
             a, b = rand(rng, 37, n, dt), rand(rng, 37, n, dt)

@@ -125,48 +125,42 @@ def test_all_ones_closed_form(B, ctx, algo):
         assert (got == exp).all()
 
 
-def residues(x: np.ndarray, p: int) -> np.ndarray:
-    """Residue mod p (< 2^20) of every row of little-endian u32 limbs (Horner)."""
-    x = x.astype(np.uint64)
-    r = np.zeros(x.shape[0], dtype=np.uint64)
-    base, P = np.uint64((1 << 32) % p), np.uint64(p)
-    for k in range(x.shape[1] - 1, -1, -1):
-        r = (r * base + x[:, k] % P) % P
-    return r
+def full_size_check(B, ctx, orc, a, b):
+    """Every algorithm that runs this size, in the benchmark's launch
+    configuration (one uniform bigmul over the whole batch), against the
+    oracle's products of every pair (computed once per size)."""
+    n = a.shape[1]
+    want = orc.mul(a, b)
+    A, Bt = G.to_dev(a), G.to_dev(b)
+    out = G.empty_dev((a.shape[0], 2 * n), a.dtype)
+    ran = []
+    for name, algo in ALGOS.items():
+        if not available(B, ctx, algo, n):
+            continue
+        out.fill_(-1)
+        B.bigmul(ctx, A, Bt, out, algo=algo)
+        G.sync()
+        got = G.from_dev(out, a.dtype)
+        bad = np.nonzero((got != want).any(axis=1))[0]
+        assert bad.size == 0, f"{name}: {bad.size} of {a.shape[0]} products differ, first {bad[:8]}"
+        ran.append(name)
+    assert ran
 
 
-@pytest.mark.parametrize("algo", list(ALGOS))
 @pytest.mark.parametrize("bits", W.MULQ_BITS)
-def test_full_size_quadratic(B, ctx, orc, algo, bits):
-    """The quadratic-multiplication workload at full size, in the benchmark's
-    launch configuration: 64 sampled products against the oracle, and every
-    product checked modulo two primes against residues of its operands."""
-    n = bits // 32
-    if not available(B, ctx, ALGOS[algo], n):
-        pytest.skip("unavailable")
+def test_full_size_quadratic(B, ctx, orc, bits):
+    """The quadratic-multiplication workload at full size (2^25 / n pairs):
+    every product of every algorithm compared with the oracle."""
     a, b = W.mul_quad_inputs(bits)
-    got = run_mul(B, ctx, a, b, ALGOS[algo])
-    rng = np.random.default_rng(bits)
-    idx = np.unique(np.concatenate([[0, a.shape[0] - 1], rng.integers(0, a.shape[0], 62)]))
-    check(orc, a[idx], b[idx], got[idx])
-    for p in (1000003, 999983):
-        P = np.uint64(p)
-        assert (residues(got, p) == (residues(a, p) * residues(b, p)) % P).all()
+    full_size_check(B, ctx, orc, a, b)
 
 
-@pytest.mark.parametrize("algo", list(ALGOS))
 @pytest.mark.parametrize("bits,batch", W.NTT_CASES)
-def test_full_size_ntt_workload(B, ctx, orc, algo, bits, batch):
-    n = bits // 32
-    if not available(B, ctx, ALGOS[algo], n):
-        pytest.skip("unavailable")
+def test_full_size_ntt_workload(B, ctx, orc, bits, batch):
+    """The NTT-multiplication workload at full size: every product of every
+    algorithm compared with the oracle."""
     a, b = W.ntt_inputs(bits, batch)
-    got = run_mul(B, ctx, a, b, ALGOS[algo])
-    idx = [0, batch // 2, batch - 1]
-    check(orc, a[idx], b[idx], got[idx])
-    for p in (1000003, 999983):
-        P = np.uint64(p)
-        assert (residues(got, p) == (residues(a, p) * residues(b, p)) % P).all()
+    full_size_check(B, ctx, orc, a, b)
 
 
 @pytest.mark.parametrize("algo", ["auto"] + list(ALGOS))

@@ -162,3 +162,45 @@ def test_stream_u64_limbs(B, ctx, orc, use_graph):
         n, ao, oo = int(ns[i]), int(off[i]), int(out_off[i])
         want = orc.mul(A[ao: ao + n][None], Bv[ao: ao + n][None])[0]
         assert (got[oo: oo + 2 * n] == want).all(), (i, n)
+
+
+@pytest.fixture(scope="module")
+def stream_workload(orc):
+    """The mixed-size stream at full size (10^5 pairs, 2^10..2^18 bits, 10 %
+    all-ones, in its log-uniform bursts) and the oracle's product of every
+    pair, laid out as the queue writes them (pair i at 2 off[i])."""
+    import workloads as W
+    count = 100000
+    n, ones = W.stream_sizes(count)
+    bursts = W.stream_bursts(count)
+    a, b, off = W.stream_inputs(np.arange(count), n, ones)
+    nn = n.astype(np.int64)
+    prods = orc.mul_ragged([(a[int(o): int(o) + k], b[int(o): int(o) + k]) for o, k in zip(off, nn)])
+    want = np.concatenate(prods)
+    return a, b, off, nn, bursts, want
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_stream_full_workload(B, ctx, stream_workload, use_graph):
+    """Every one of the 10^5 products of the stream workload, submitted burst
+    by burst through the queue (graph replay with device binning, or host
+    binning), equals the oracle's."""
+    a, b, off, nn, bursts, want = stream_workload
+    count = len(nn)
+    d = np.zeros(count, dtype=G.DESC_DTYPE)
+    d["a_off"], d["b_off"], d["out_off"], d["n_limbs"] = off, off, 2 * off, nn
+    dA, dB = G.to_dev(a), G.to_dev(b)
+    out = G.empty_dev((2 * int(nn.sum()),), np.uint32)
+    out.fill_(-1)
+    start = 0
+    with B.StreamQueue(ctx, dA, dB, out, 32, max_descs=int(bursts.max()), algo=0, use_graph=use_graph) as q:
+        for bs in bursts.tolist():
+            q.submit(d[start: start + bs])
+            start += bs
+        assert start == count
+    got = G.from_dev(out, np.uint32)
+    bad = np.nonzero(got != want)[0]
+    if bad.size:
+        pair = np.searchsorted(2 * off.astype(np.int64), bad[:8], side="right") - 1
+        raise AssertionError(f"{bad.size} words differ, first in pairs {sorted(set(pair.tolist()))}")

@@ -76,6 +76,9 @@ MUTATIONS = {
     "mul_transposed_index": ("(uint64_t)out[i + j] + carry;\n            out[i + j]", "(uint64_t)out[i + j] + carry;\n            out[j]"),
     "mul_dropped_carry_term": ("(uint64_t)out[i + j] + carry;", "(uint64_t)out[i + j];"),
     "mul_top_limb_offset": ("out[i + n] = (uint32_t)carry;", "out[i + n - 1] += (uint32_t)carry;"),
+    "add_ragged_b_offset": ("add_one(a + a_off[p], b + b_off[p]", "add_one(a + a_off[p], b + a_off[p]"),
+    "add_ragged_out_offset": ("b + b_off[p], out + out_off[p], n[p]);\n        if", "b + b_off[p], out + a_off[p], n[p]);\n        if"),
+    "mul_ragged_b_offset": ("mul_one(a + a_off[p], b + b_off[p]", "mul_one(a + a_off[p], b + a_off[p]"),
     "mul_truncated_row": ("for (size_t j = 0; j < n; ++j) {\n            uint64_t t", "for (size_t j = 0; j + 1 < n; ++j) {\n            uint64_t t"),
 }
 
