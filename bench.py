@@ -1,24 +1,34 @@
 """Benchmark of the batched big-integer hot path on one MI355X.
 
-Default workload: the addition bandwidth sweep.  One step adds, at each of
-2^10, 2^12, 2^14, 2^16 and 2^18 bits (u64 limbs), a batch of 2^32/N pairs
-(1 GiB of operands, 0.5 GiB of sums per size), i.e. five bigadd launches.
-Inputs are generated on the host (seeded, 75 % uniform, 25 % carry-heavy),
-copied to HBM once, and stay resident; the timed region contains only the
-kernels.  Every launch is timed with HIP events on the stream it runs on.
+Default workload (all): one JSON line carrying
+  * the addition bandwidth sweep (the headline value).  One step adds, at
+    each of 2^10, 2^12, 2^14, 2^16 and 2^18 bits (u64 limbs), a batch of
+    2^32/N pairs (1 GiB of operands, 0.5 GiB of sums per size), i.e. five
+    bigadd launches; inputs are seeded (75 % uniform, 25 % carry-heavy);
+  * mul_quadratic: 2^12..2^15 bits, 2^25/n pairs, every algorithm, best per
+    size, each with its integer-op roofline;
+  * mul_ntt: (2^15, 4096), (2^16, 1024), (2^17, 256), (2^18, 64) pairs, the
+    same;
+  * stream: 10^5 products of mixed sizes in bursts (the stream queue against
+    per-class padded launches, saturated throughput and burst latency at 0.8x
+    load);
+  each with the CPU oracle timed beside it (all cores and one core).
+Inputs are generated on the host, copied to HBM once and stay resident; the
+timed regions contain only the kernels.  Every launch is timed with HIP
+events on the stream it runs on.
 
-Other workloads (--workload): mulq (quadratic multiplication sizes),
-ntt (NTT-multiplication sizes), stream (10^5 products of mixed sizes in
-bursts: the stream queue against per-class padded launches, saturated
-throughput and burst latency at 0.8x load), copy (a plain 1 GiB device copy,
-the known-size kernel that scales the HBM byte counters), fused (the
-paper's fused programs 6-Add and Poly, Section 6.1, over the addition sweep's
-batches, with 1-Add beside them); each prints its own JSON line.
+Other workloads (--workload) print their own line: add, mulq, ntt, stream
+(the parts above alone), copy (a plain 1 GiB device copy, the known-size
+kernel that scales the HBM byte counters), fused (the paper's fused programs
+6-Add and Poly, Section 6.1, over the addition sweep's batches, with 1-Add
+beside them), add_large / mul_large (one integer beyond a workgroup), peaks
+(register-resident issue rates of the instructions the rooflines count).
 
-Prints one JSON line (rank 0, one GPU):
+Top-level fields (rank 0, one GPU):
   value   whole-job additions per second over the step (all five sizes);
-  roofline   for the dominant kernel: algorithmic bytes per launch (3 N/8 per
-             pair = 1.5 GiB) over its average launch time, against 8 TB/s;
+  roofline   for the dominant addition kernel: algorithmic bytes per launch
+             (3 N/8 per pair = 1.5 GiB) over its average launch time,
+             against 8 TB/s;
   cpu_baseline   the CPU oracle on this host's cores over the same sweep.
 """
 from __future__ import annotations
@@ -57,12 +67,13 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="add", choices=["add", "add_large", "mul_large", "mulq", "ntt", "stream", "copy", "fused"])
+    p.add_argument("--workload", default="all",
+                   choices=["all", "add", "add_large", "mul_large", "mulq", "ntt", "stream", "copy", "fused", "peaks"])
     p.add_argument("--stream-pairs", type=int, default=100000, help="pairs in the mixed-size stream")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU baseline budget")
     p.add_argument("--sizes", default="", help="comma-separated subset of sizes in bits (profiling runs)")
-    p.add_argument("--algos", default="valu,mfma,ntt", help="multiplication algorithms to time")
+    p.add_argument("--algos", default="valu,mfma,ntt,ntt64", help="multiplication algorithms to time")
     return p.parse_args()
 
 
@@ -380,9 +391,21 @@ def cpu_baseline_mul(args, kind, cases):
         pairs += n_size
         secs += t_size
         samples.append(f"{cnt} pairs x{n_size // cnt} at 2^{bits.bit_length() - 1}")
+    # one core: the first 8 pairs of each size, once
+    pairs1, secs1, macs1 = 0, 0.0, 0.0
+    for bits, batch in cases:
+        idx = np.arange(min(batch, 8), dtype=np.uint64)
+        a, b = W.mul_quad_inputs(bits, pairs=idx) if kind == "mulq" else W.ntt_inputs(bits, batch, pairs=idx)
+        t = time.perf_counter()
+        orc.mul(a, b, threads=1)
+        secs1 += time.perf_counter() - t
+        pairs1 += len(idx)
+        macs1 += float(len(idx)) * a.shape[1] ** 2
     return {"value": pairs / secs, "unit": "mults/s", "cores": threads, "kind": "oracle",
             "sample": "first pairs of each size, repeated: " + "; ".join(samples),
-            "cpu_model": cpu_info(), "seconds": round(secs, 2)}
+            "cpu_model": cpu_info(), "seconds": round(secs, 2),
+            "one_core": {"value": pairs1 / secs1, "unit": "mults/s", "cores": 1, "seconds": round(secs1, 2),
+                         "u32_macs_per_s": macs1 / secs1, "sample": "first 8 pairs of each size, once"}}
 
 
 def bench_stream(args):
@@ -551,9 +574,17 @@ def cpu_baseline_stream(args, a, b, off, nn):
         pairs += len(items)
         macs += float(sum(len(x) ** 2 for x, _ in items))
         i += chunk
-    return {"value": pairs / secs, "unit": "mults/s", "cores": orc.last_threads, "kind": "oracle",
+    threads = orc.last_threads
+    items = [(a[int(off[k]): int(off[k]) + int(nn[k])], b[int(off[k]): int(off[k]) + int(nn[k])]) for k in range(64)]
+    t = time.perf_counter()
+    orc.mul_ragged(items, threads=1)
+    secs1 = time.perf_counter() - t
+    macs1 = float(sum(len(x) ** 2 for x, _ in items))
+    return {"value": pairs / secs, "unit": "mults/s", "cores": threads, "kind": "oracle",
             "sample": f"first {pairs} pairs of the stream", "u32_macs_per_s": macs / secs,
-            "cpu_model": cpu_info(), "seconds": round(secs, 2)}
+            "cpu_model": cpu_info(), "seconds": round(secs, 2),
+            "one_core": {"value": 64 / secs1, "unit": "mults/s", "cores": 1, "seconds": round(secs1, 2),
+                         "u32_macs_per_s": macs1 / secs1, "sample": "first 64 pairs of the stream, once"}}
 
 
 def bench_fused(args):
@@ -778,19 +809,48 @@ def bench_add_large(args):
     }
 
 
+def large_ntt_block_words(n32):
+    """Block size (words) bigmul_large's NTT path picks by default: the
+    smallest power of two >= 512 that keeps the operands within 64 blocks
+    (the rule of large_ntt_auto_block in the library)."""
+    bw = 512
+    while bw < 8192 and -(-n32 // bw) > 64:
+        bw *= 2
+    return bw
+
+
+def large_ntt_butterflies(n32, bw):
+    """Radix-2 butterflies of one bigmul_large product on the NTT path, both
+    primes: per block 2 forward row transforms, 2k - 1 inverse rows, and per
+    row position the column transforms (4 forward and 2 inverse halves of H
+    points)."""
+    k = -(-n32 // bw)
+    m = 11
+    while (1 << m) < 4 * bw:
+        m += 1
+    L = 1 << m
+    r = 0
+    while (2 << r) < 2 * k - 1:
+        r += 1
+    H = 1 << r
+    rows = (2 * k + 2 * k - 1) * (L // 2) * m
+    cols = L * 6 * (H // 2) * r
+    return 2.0 * (rows + cols), k, L, H
+
+
 def bench_mul_large(args):
     """One pair per size, 2^19..2^24 bits (u32 limbs, uniform), multiplied by
-    bigmul_large (k^2 block products of 2^18 bits through the batched
-    kernels, a column-sum fold and the multi-workgroup addition).  The
-    roofline is that of the block products' tuned algorithm: int8 MFMA
-    operations (2 per digit product) or NTT butterflies."""
+    bigmul_large: the default NTT path is a two-dimensional convolution (row
+    transforms per block, column transforms across blocks, CRT, a fold and
+    the multi-workgroup addition); its roofline counts the butterflies of
+    those transforms against the butterfly peak.  Beside it: other block
+    sizes, and the k^2 block products forced to the int8-MFMA schoolbook."""
     import torch
 
     import paper_2405_14642_amd as B
     import workloads as W
 
     ctx = B.Context(0)
-    tuned = B.autotune(ctx)
     stream = torch.cuda.current_stream()
     sizes = (1 << 19, 1 << 20, 1 << 22, 1 << 24)
     if args.sizes:
@@ -819,30 +879,26 @@ def bench_mul_large(args):
             return 1e3 * float(np.mean([x.elapsed_time(y) for x, y in evs]))
 
         us = timed(B.MUL_AUTO)
-        bw = 2048 if n <= (1 << 15) else 8192  # the library's default block size
-        k = (n + bw - 1) // bw
-        cls = (bw - 1).bit_length() - 4  # size class of a bw-word product
-        if tuned[cls] == ALGO_IDS["mfma"]:
-            ops = 2.0 * k * k * (4 * bw) ** 2  # int8 digit products of the block products
-            roof = {"bound": "mfma", "achieved": round(ops / (us * 1e-6) / 1e12, 1),
-                    "peak": MFMA_I8_PEAK_OPS / 1e12, "unit": "TOP/s (int8)",
-                    "frac": round(ops / (us * 1e-6) / MFMA_I8_PEAK_OPS, 4)}
-        else:
-            m = 4 * bw
-            bfly = 2.0 * 3 * k * k * m / 2 * (m.bit_length() - 1)  # two primes, three length-4bw transforms
-            roof = {"bound": "alu", "achieved": round(bfly / (us * 1e-6) / 1e12, 3),
-                    "peak": round(NTT_BFLY_PEAK / 1e12, 3), "unit": "T butterflies/s",
-                    "frac": round(bfly / (us * 1e-6) / NTT_BFLY_PEAK, 4)}
-        per_size[str(bits)] = {"us_per_call": round(us, 2), "block_bits": 32 * bw, "block_products": k * k,
-                               "block_algorithm": tuned[cls], "mults_per_s": 1e6 / us, "roofline": roof,
-                               "us_per_call_by_block_algorithm": {
-                                   name: round(timed(ALGO_IDS[name]), 2) for name in ("mfma", "ntt")},
-                               "us_per_call_by_block_bits": {
-                                   str(bb): round(timed(B.MUL_AUTO, bb), 2) for bb in (1 << 16, 1 << 17, 1 << 18)}}
+        bw = large_ntt_block_words(n)
+        bfly, k, L, H = large_ntt_butterflies(n, bw)
+        roof = {"bound": "alu", "achieved": round(bfly / (us * 1e-6) / 1e12, 3),
+                "peak": round(NTT_BFLY_PEAK / 1e12, 3), "unit": "T butterflies/s",
+                "frac": round(bfly / (us * 1e-6) / NTT_BFLY_PEAK, 4), "butterflies_per_call": bfly}
+        by_block = {}
+        for bb in (1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18):
+            if -(-n // (bb // 32)) <= 64:
+                by_block[str(bb)] = round(timed(B.MUL_AUTO, bb), 2)
+        mfma_blocks = None
+        if bits <= (1 << 22):  # k^2 block products grow quadratically
+            mfma_blocks = round(timed(B.MUL_SCHOOL_MFMA), 2)
+        per_size[str(bits)] = {"us_per_call": round(us, 2), "block_bits": 32 * bw, "blocks": k,
+                               "row_length": L, "column_half_length": H, "mults_per_s": 1e6 / us, "roofline": roof,
+                               "us_per_call_by_block_bits": by_block,
+                               "us_per_call_mfma_block_products": mfma_blocks}
         step_ms += us / 1e3
         del A, Bt, out
     ctx.close()
-    key = str(1 << 20) if str(1 << 20) in per_size else str(sizes[-1])
+    key = str(1 << 24) if str(1 << 24) in per_size else str(sizes[-1])
     main = per_size[key]
     return {
         "metric": f"bigmul_large products/s of one 2^{int(key).bit_length() - 1}-bit pair (u32 limbs)",
@@ -894,9 +950,99 @@ def cpu_baseline_add(args, W):
         adds += n_size
         secs += t_size
         samples.append(f"{cnt} pairs x{n_size // cnt} at 2^{bits.bit_length() - 1}")
+    # one core: the first 1/16 of each size's sample, once
+    adds1, secs1 = 0, 0.0
+    for bits in W.ADD_SWEEP_BITS:
+        cnt = max(1, W.add_sweep_pairs(bits) // 64)
+        a, b = W.add_sweep_inputs(bits, pairs=np.arange(cnt, dtype=np.uint64))
+        t = time.perf_counter()
+        orc.add(a, b, threads=1)
+        secs1 += time.perf_counter() - t
+        adds1 += cnt
     return {"value": adds / secs, "unit": "adds/s", "cores": threads, "kind": "oracle",
             "sample": "first quarter of each size's batch, repeated: " + "; ".join(samples),
-            "cpu_model": cpu_info(), "seconds": round(secs, 2)}
+            "cpu_model": cpu_info(), "seconds": round(secs, 2),
+            "one_core": {"value": adds1 / secs1, "unit": "adds/s", "cores": 1, "seconds": round(secs1, 2),
+                         "sample": "first 1/64 of each size's batch, once"}}
+
+
+# Issue-rate probe kinds (libbiprobe.so): instruction measured and what one
+# "op" is.
+PROBE_KINDS = (
+    (0, "v_add_u32", "lane-op"),
+    (1, "v_addc_co_u32 (VOP3, carry in SGPR pair)", "lane-op"),
+    (2, "v_mad_u64_u32", "lane-op"),
+    (3, "v_mul_lo_u32", "lane-op"),
+    (4, "v_mul_hi_u32", "lane-op"),
+    (5, "v_mfma_i32_32x32x32_i8", "int8 MAC"),
+    (6, "schoolbook term: v_mad_u64_u32 + v_addc_co_u32", "term"),
+)
+SIMDS = 256 * 4          # 256 CUs x 4 SIMDs
+CLOCK_PEAK_HZ = 2.4e9    # MI355X peak engine clock
+
+
+def bench_peaks(args):
+    """Register-resident issue rates of the instructions the integer-op
+    rooflines count, with the shader clock each loop ran at (s_memtime
+    against the 100 MHz s_memrealtime); per kind the best of 1, 2, 4 and 8
+    waves per SIMD.  ops/clk/SIMD = rate / (1024 SIMDs x measured clock)."""
+    import ctypes
+    import torch
+    torch.cuda.init()
+    torch.zeros(1, device="cuda")
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2405_14642_amd", "libbiprobe.so"))
+    D = ctypes.c_double
+    lib.bi_probe_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(D), ctypes.POINTER(D),
+                                  ctypes.POINTER(D)]
+    lib.bi_probe_rate.restype = ctypes.c_int
+    rates = {}
+    for kind, name, unit in PROBE_KINDS:
+        best = None
+        for waves in (1, 2, 4, 8):
+            ops, clk, sec = D(), D(), D()
+            iters = 4000 if kind == 5 else 20000
+            st = lib.bi_probe_rate(kind, iters, waves, ctypes.byref(ops), ctypes.byref(clk), ctypes.byref(sec))
+            if st != 0:
+                raise RuntimeError(f"probe {name} failed with HIP error {st}")
+            if best is None or ops.value > best[0]:
+                best = (ops.value, clk.value, sec.value, waves)
+        ops, clk, sec, waves = best
+        per_clk = ops / (SIMDS * clk) if clk else None
+        rates[name] = {"unit": unit + "/s", "rate": ops, "clock_hz": round(clk), "seconds": round(sec, 6),
+                       "waves_per_simd": waves, "per_clk_per_simd": round(per_clk, 3) if per_clk else None,
+                       "at_2p4GHz": per_clk * SIMDS * CLOCK_PEAK_HZ if per_clk else None}
+    return {"metric": "register-resident issue rates (ops/s) of the instructions the integer-op rooflines count",
+            "value": rates["v_mad_u64_u32"]["rate"], "unit": "v_mad_u64_u32 lane-ops/s", "n_gpus": 1,
+            "steps": 1, "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic (register-resident loops)",
+            "config": {"workload": "peaks", "parallelism": "single-gpu"}, "rates": rates,
+            "roofline": None, "cpu_baseline": None}
+
+
+SUB_KEYS = ("metric", "value", "unit", "ms_per_step", "dtype", "config", "roofline", "per_size", "cpu_baseline")
+
+
+def bench_all(args):
+    """The default run: the addition sweep (the headline value: additions/s,
+    HBM roofline), then the quadratic and NTT multiplication sizes (every
+    algorithm, best per size, integer-op rooflines) and the mixed-size
+    stream, each carried in the one JSON line with its own roofline and CPU
+    baseline."""
+    import torch
+    res = bench_add(args)
+    torch.cuda.empty_cache()
+    for key, kind in (("mul_quadratic", "mulq"), ("mul_ntt", "ntt")):
+        sub = bench_mul(args, kind)
+        res[key] = {k: sub[k] for k in SUB_KEYS}
+        torch.cuda.empty_cache()
+    sub = bench_stream(args)
+    res["stream"] = {k: v for k, v in sub.items() if k not in ("n_gpus", "steps", "warmup", "higher_is_better",
+                                                                  "scaling", "vs_baseline", "data")}
+    torch.cuda.empty_cache()
+    res["metric"] = ("integer adds/s and mults/s per size (2^10..2^18 bits) with % of the HBM / integer-op "
+                     "roofline; value: additions/s over the 2^10..2^18-bit sweep (u64 limbs, 1 GiB of operands "
+                     "per size)")
+    return res
 
 
 def main():
@@ -905,7 +1051,9 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; the batch shards by instance "
                           "across GPUs with no exchange, so --gpus N > 1 is not supported"}))
         sys.exit(2)
-    if args.workload == "add":
+    if args.workload == "all":
+        res = bench_all(args)
+    elif args.workload == "add":
         res = bench_add(args)
     elif args.workload == "add_large":
         res = bench_add_large(args)
@@ -913,6 +1061,8 @@ def main():
         res = bench_mul_large(args)
     elif args.workload == "stream":
         res = bench_stream(args)
+    elif args.workload == "peaks":
+        res = bench_peaks(args)
     elif args.workload == "copy":
         res = bench_copy(args)
     elif args.workload == "fused":

@@ -223,15 +223,26 @@ bi_status bigmul_v(bi_ctx *ctx, const void *a, const void *b, void *out,
  * per-class choice to algo_out[0 .. n_out) if not NULL.  It allocates and frees 64 MiB of device memory and synchronises
  * `stream`.  bi_tune_get / bi_tune_set read or replace the per-class choice
  * (BI_EALGO if an algorithm cannot run a class's sizes; nothing is changed
- * then).  Until tuned, a context uses a built-in table.
+ * then).  Until tuned, a context uses a built-in table (the choices
+ * bi_autotune made on an MI355X).
+ *
+ * bi_tune_save writes the context's tables (algorithm and VALU schedule per
+ * class, the addition schedules) to the text file `path`, keyed by the
+ * device's architecture name and the HIP runtime version; bi_tune_load reads
+ * such a file into the context.  A file written for another architecture or
+ * runtime version, a malformed one, or one naming an algorithm or schedule a
+ * class cannot run is refused (BI_EINVAL, nothing changed).  Host file I/O
+ * only, no HIP call; BI_EINVAL if the file cannot be opened.
  */
 #define BI_NUM_CLASSES 10
 
 bi_status bi_autotune(bi_ctx *ctx, void *stream, int *algo_out, uint32_t n_out);
 bi_status bi_tune_get(const bi_ctx *ctx, int *algo_out, uint32_t n_out);
 bi_status bi_tune_set(bi_ctx *ctx, const int *algo_in, uint32_t n_in);
-/* The VALU schoolbook schedule per class: q_out[k], waves_out[k] (0, 0 until
- * tuned: the built-in size rule applies).  Either array may be NULL.
+bi_status bi_tune_save(const bi_ctx *ctx, const char *path);
+bi_status bi_tune_load(bi_ctx *ctx, const char *path);
+/* The VALU schoolbook schedule per class: q_out[k], waves_out[k] ((0, 0):
+ * the built-in size rule applies).  Either array may be NULL.
  * bi_tune_set_valu replaces entries 0 .. n_in-1: (0, 0) restores the size
  * rule; otherwise q must be 2 or 4, waves 1, 2, 4, 8 or 16, and the schedule's
  * LDS must fit one CU for the class's largest size (BI_EINVAL otherwise;

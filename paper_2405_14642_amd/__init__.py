@@ -31,7 +31,8 @@ EXPORTS = ("bi_ctx_create", "bi_ctx_destroy", "bi_status_str", "bi_last_error",
            "bigadd", "bigmul", "bigadd_v", "bigmul_v", "bi_ntt_field", "bi_autotune", "bi_tune_get",
            "bi_tune_set", "bi_stream_open", "bi_stream_submit", "bi_stream_poll", "bi_stream_wait",
            "bi_stream_close", "bi_fused", "bi_tune_get_valu",
-           "bi_tune_set_valu", "bigadd_large", "bigmul_large")
+           "bi_tune_set_valu", "bigadd_large", "bigmul_large", "bi_tune_save",
+           "bi_tune_load")
 NUM_CLASSES = 10
 
 
@@ -78,6 +79,8 @@ def _load():
     L.bi_autotune.argtypes = [P, P, P, U32]
     L.bi_tune_get.argtypes = [P, P, U32]
     L.bi_tune_set.argtypes = [P, P, U32]
+    L.bi_tune_save.argtypes = [P, ctypes.c_char_p]
+    L.bi_tune_load.argtypes = [P, ctypes.c_char_p]
     L.bi_stream_open.argtypes = [P, P, U64, P, U64, P, U64, U32, U64, I, I, P, ctypes.POINTER(P)]
     L.bi_stream_submit.argtypes = [P, P, U64, ctypes.POINTER(U64)]
     L.bi_stream_poll.argtypes = [P, U64, ctypes.POINTER(I)]
@@ -89,7 +92,7 @@ def _load():
     for f in (L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field, L.bi_autotune,
               L.bi_tune_get, L.bi_tune_set, L.bi_stream_open, L.bi_stream_submit, L.bi_stream_poll,
               L.bi_stream_wait, L.bi_stream_close, L.bi_fused, L.bi_tune_get_valu,
-              L.bi_tune_set_valu, L.bigadd_large, L.bigmul_large):
+              L.bi_tune_set_valu, L.bigadd_large, L.bigmul_large, L.bi_tune_save, L.bi_tune_load):
         f.restype = I
     return L
 
@@ -268,6 +271,18 @@ def tune_get(ctx):
 def tune_set(ctx, algos):
     arr = (ctypes.c_int * len(algos))(*algos)
     _check(lib.bi_tune_set(_h(ctx), arr, len(algos)))
+
+
+def tune_save(ctx, path):
+    """Write the context's tuning tables to `path` (keyed by architecture
+    and HIP runtime version)."""
+    _check(lib.bi_tune_save(_h(ctx), os.fsencode(path)))
+
+
+def tune_load(ctx, path):
+    """Load tuning tables written by tune_save for this architecture and
+    runtime version (BigIntError otherwise; nothing changed)."""
+    _check(lib.bi_tune_load(_h(ctx), os.fsencode(path)))
 
 
 def tune_get_valu(ctx):

@@ -10,6 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbigint.so")
+PROBE_LIB = os.path.join(HERE, "libbiprobe.so")  # issue-rate probe of the benchmark
 OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -36,18 +37,25 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 8) -> str:
-    """Compile every HIP/C++ source under csrc/ and link libbigint.so."""
-    os.makedirs(OBJ, exist_ok=True)
-    srcs = sources()
-    with cf.ThreadPoolExecutor(max_workers=min(jobs, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+def _link(objs, lib):
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(jobs: int = 8) -> str:
+    """Compile every HIP/C++ source under csrc/ and link libbigint.so; the
+    issue-rate probe under csrc/probe/ becomes libbiprobe.so."""
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = sources()
+    probes = sorted(glob.glob(os.path.join(CSRC, "probe", "*.hip")))
+    with cf.ThreadPoolExecutor(max_workers=min(jobs, len(srcs) + len(probes))) as ex:
+        objs = list(ex.map(_compile, srcs + probes))
+    _link(objs[:len(srcs)], LIB)
+    _link(objs[len(srcs):], PROBE_LIB)
     return LIB
 
 

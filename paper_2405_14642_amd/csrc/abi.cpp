@@ -179,12 +179,24 @@ bi_status bigmul_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
         return fail(BI_ESIZE, "n_limbs * limb_bits exceeds %u bits (n_limbs = %llu)", BI_MAX_LARGE_MUL_BITS,
                     (unsigned long long)n_limbs);
     if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT_PF64) return fail(BI_EINVAL, "unknown algorithm %d", algo);
-    if (block_bits != 0 && block_bits != (1u << 16) && block_bits != (1u << 17) && block_bits != (1u << 18))
-        return fail(BI_EINVAL, "block_bits must be 0, 2^16, 2^17 or 2^18 (got %u)", block_bits);
     const uint64_t n32 = n_limbs * (limb_bits / 32);
-    const uint32_t bw = block_bits ? block_bits / 32 : bi::large_mul_auto_block(n32);
-    if (algo != BI_MUL_AUTO && !bi::algo_supports(algo, bw))
-        return fail(BI_EALGO, "algorithm %d does not run %u-bit blocks", algo, 32 * bw);
+    // AUTO and NTT: the two-dimensional NTT convolution (n log n); a forced
+    // VALU, MFMA or PrimeField64 algorithm: k^2 block products of that algorithm.
+    const bool two_dim = algo == BI_MUL_AUTO || algo == BI_MUL_NTT;
+    uint32_t bw = 0;
+    if (two_dim) {
+        if (block_bits != 0 && (block_bits < (1u << 14) || block_bits > (1u << 18) || (block_bits & (block_bits - 1))))
+            return fail(BI_EINVAL, "block_bits must be 0 or a power of two in [2^14, 2^18] (got %u)", block_bits);
+        bw = block_bits ? block_bits / 32 : bi::large_ntt_auto_block(n32);
+        if ((n32 + bw - 1) / bw > bi::kLargeNttMaxBlocks)
+            return fail(BI_EINVAL, "%u-bit blocks give more than %u blocks at %llu words", 32 * bw,
+                        bi::kLargeNttMaxBlocks, (unsigned long long)n32);
+    } else {
+        if (block_bits != 0 && block_bits != (1u << 16) && block_bits != (1u << 17) && block_bits != (1u << 18))
+            return fail(BI_EINVAL, "block_bits must be 0, 2^16, 2^17 or 2^18 for block products (got %u)", block_bits);
+        bw = block_bits ? block_bits / 32 : bi::large_mul_auto_block(n32);
+        if (!bi::algo_supports(algo, bw)) return fail(BI_EALGO, "algorithm %d does not run %u-bit blocks", algo, 32 * bw);
+    }
     bi_status s;
     if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
     if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;
@@ -196,10 +208,15 @@ bi_status bigmul_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     const hipStream_t st = static_cast<hipStream_t>(stream);
     void *scr = nullptr;
-    if ((s = bi::ctx_scratch(ctx->impl, bi::large_mul_scratch_bytes(n32, bw, ctx->impl.num_cus), st, &scr)) != BI_OK)
-        return s;
-    hipError_t e = bi::launch_bigmul_large(ctx->impl, static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
-                                           static_cast<uint32_t *>(out), n32, bw, algo, static_cast<uint8_t *>(scr), st);
+    const size_t need =
+        two_dim ? bi::large_ntt_scratch_bytes(n32, bw) : bi::large_mul_scratch_bytes(n32, bw, ctx->impl.num_cus);
+    if ((s = bi::ctx_scratch(ctx->impl, need, st, &scr)) != BI_OK) return s;
+    auto A = static_cast<const uint32_t *>(a);
+    auto B = static_cast<const uint32_t *>(b);
+    auto C = static_cast<uint32_t *>(out);
+    auto S = static_cast<uint8_t *>(scr);
+    const hipError_t e = two_dim ? bi::launch_bigmul_large_ntt(ctx->impl, A, B, C, n32, bw, S, st)
+                                 : bi::launch_bigmul_large(ctx->impl, A, B, C, n32, bw, algo, S, st);
     if (e != hipSuccess) return hip_fail(e, "bigmul_large launch");
     return BI_OK;
 }
@@ -294,6 +311,16 @@ bi_status bi_tune_get(const bi_ctx *ctx, int *algo_out, uint32_t n_out) {
     if (!ctx || !algo_out) return fail(BI_EINVAL, "NULL argument");
     for (uint32_t k = 0; k < n_out && k < bi::kNumClasses; ++k) algo_out[k] = ctx->impl.tune.mul_algo[k];
     return BI_OK;
+}
+
+bi_status bi_tune_save(const bi_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(BI_EINVAL, "NULL argument");
+    return bi::tune_save(ctx->impl, path);
+}
+
+bi_status bi_tune_load(bi_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(BI_EINVAL, "NULL argument");
+    return bi::tune_load(ctx->impl, path);
 }
 
 bi_status bi_tune_set(bi_ctx *ctx, const int *algo_in, uint32_t n_in) {

@@ -8,6 +8,8 @@
 // kernel families and their schedules.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstring>
 #include <vector>
 
 #include "bi_internal.hpp"
@@ -128,6 +130,66 @@ bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out) {
     if (s != BI_OK) return s;
     if (algo_out)
         for (uint32_t k = 0; k < n_out && k < kNumClasses; ++k) algo_out[k] = c.tune.mul_algo[k];
+    return BI_OK;
+}
+
+// File format (text, one record per line):
+//   bigint-tune 1
+//   arch <gcnArchName>
+//   hip <runtime version>
+//   mul_algo <10 algorithm ids>
+//   valu_q <10 values>    valu_nw <10 values>
+//   add_multi <multi2> <multi4> <multi8>
+bi_status tune_save(const Ctx &c, const char *path) {
+    std::FILE *f = std::fopen(path, "w");
+    if (!f) return set_error(BI_EINVAL, "cannot open %s for writing", path);
+    std::fprintf(f, "bigint-tune 1\narch %s\nhip %d\nmul_algo", c.arch, c.hip_version);
+    for (uint32_t k = 0; k < kNumClasses; ++k) std::fprintf(f, " %d", c.tune.mul_algo[k]);
+    std::fprintf(f, "\nvalu_q");
+    for (uint32_t k = 0; k < kNumClasses; ++k) std::fprintf(f, " %d", int(c.tune.valu_q[k]));
+    std::fprintf(f, "\nvalu_nw");
+    for (uint32_t k = 0; k < kNumClasses; ++k) std::fprintf(f, " %d", int(c.tune.valu_nw[k]));
+    std::fprintf(f, "\nadd_multi %d %d %d\n", int(c.add.multi2), int(c.add.multi4), int(c.add.multi8));
+    const bool ok = std::fclose(f) == 0;
+    return ok ? BI_OK : set_error(BI_EINVAL, "writing %s failed", path);
+}
+
+bi_status tune_load(Ctx &c, const char *path) {
+    std::FILE *f = std::fopen(path, "r");
+    if (!f) return set_error(BI_EINVAL, "cannot open %s", path);
+    char arch[64] = {}, key[32] = {};
+    int version = -1, hip = 0;
+    int algo[kNumClasses], q[kNumClasses], nw[kNumClasses], m[3];
+    // each record opens with its key, compared as a whole token
+    auto expect = [&](const char *k) { return std::fscanf(f, "%31s", key) == 1 && std::strcmp(key, k) == 0; };
+    auto ints = [&](int *v, uint32_t cnt) {
+        for (uint32_t i = 0; i < cnt; ++i)
+            if (std::fscanf(f, "%d", &v[i]) != 1) return false;
+        return true;
+    };
+    bool ok = expect("bigint-tune") && ints(&version, 1) && version == 1 && expect("arch") &&
+              std::fscanf(f, "%63s", arch) == 1 && expect("hip") && ints(&hip, 1) && expect("mul_algo") &&
+              ints(algo, kNumClasses) && expect("valu_q") && ints(q, kNumClasses) && expect("valu_nw") &&
+              ints(nw, kNumClasses) && expect("add_multi") && ints(m, 3);
+    std::fclose(f);
+    if (!ok) return set_error(BI_EINVAL, "%s is not a tuning file", path);
+    if (std::strcmp(arch, c.arch) != 0 || hip != c.hip_version)
+        return set_error(BI_EINVAL, "%s was tuned for %s with HIP %d, this context is %s with HIP %d", path, arch, hip,
+                         c.arch, c.hip_version);
+    for (uint32_t k = 0; k < kNumClasses; ++k) {
+        if (!algo_supports(algo[k], class_nmax(k)))
+            return set_error(BI_EINVAL, "%s: algorithm %d cannot run size class %u", path, algo[k], k);
+        if (!(q[k] == 0 && nw[k] == 0) && !valu_plan_fits(class_nmax(k), q[k], nw[k], nullptr))
+            return set_error(BI_EINVAL, "%s: VALU schedule (%d, %d) does not fit size class %u", path, q[k], nw[k], k);
+    }
+    for (uint32_t k = 0; k < kNumClasses; ++k) {
+        c.tune.mul_algo[k] = algo[k];
+        c.tune.valu_q[k] = uint8_t(q[k]);
+        c.tune.valu_nw[k] = uint8_t(nw[k]);
+    }
+    c.add.multi2 = m[0] != 0;
+    c.add.multi4 = m[1] != 0;
+    c.add.multi8 = m[2] != 0;
     return BI_OK;
 }
 

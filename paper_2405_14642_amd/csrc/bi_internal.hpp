@@ -47,10 +47,16 @@ __host__ __device__ constexpr uint32_t ntt_t0_offset(uint32_t m) {
 }
 constexpr uint32_t kNttTableWords = ntt_t0_offset(kNttLogLmax + 1);
 
+// Output scales 2^-l 2^32 are kept up to l = kNttScaleMax: a row transform of
+// up to 2^15 points times a column transform of up to 2^7 (products beyond
+// 2^18 bits, as a two-dimensional convolution).
+constexpr int kNttScaleMax = kNttLogLmax + 7;
+
 struct NttConst {
     uint32_t p[kNttPrimes], pneg[kNttPrimes];     // modulus, -p^-1 mod 2^32
-    uint32_t scale[kNttPrimes][kNttLogLmax + 1];  // 2^-l * 2^32 mod p
-    uint32_t scale_sh[kNttPrimes][kNttLogLmax + 1];
+    uint32_t one_sh[kNttPrimes];                  // Shoup companion of 1: floor(2^32 / p)
+    uint32_t scale[kNttPrimes][kNttScaleMax + 1];  // 2^-l * 2^32 mod p
+    uint32_t scale_sh[kNttPrimes][kNttScaleMax + 1];
     uint32_t crt, crt_sh;                         // p1^-1 mod p2 and its Shoup companion
     const uint2 *fwd[kNttPrimes];                 // twiddle blocks (w^e, Shoup), w of order Lmax
     const uint2 *inv[kNttPrimes];                 // the same for w^-1
@@ -117,6 +123,19 @@ struct UniformInst {
     }
 };
 
+// Block q < k of ONE long operand pair cut into blocks of bw words: words
+// [q bw, min((q + 1) bw, n32)) of a and b (the last block may be shorter).
+struct BlockInst {
+    const uint32_t *a, *b;
+    uint64_t n32;
+    uint32_t bw, k;
+    __device__ __forceinline__ uint64_t count() const { return k; }
+    __device__ __forceinline__ InstRef get(uint64_t q) const {
+        const uint64_t off = q * bw, rem = n32 - off;
+        return InstRef{a + off, b + off, nullptr, uint32_t(rem < bw ? rem : bw)};
+    }
+};
+
 struct ListInst {
     const uint32_t *a, *b;
     uint32_t *c;
@@ -140,7 +159,10 @@ struct Ctx {
     Tune tune{};
     NttTables ntt;
     Scratch scratch;
+    char arch[64] = {};               // gcnArchName of the device
+    int hip_version = 0;              // hipRuntimeGetVersion
 };
+
 
 // Returns a device buffer of at least `bytes` owned by the context; growing it
 // synchronises the device first so no queued kernel still uses the old buffer.
@@ -180,8 +202,10 @@ hipError_t launch_bigmul_valu(const uint32_t *a, const uint32_t *b, uint32_t *c,
 // (ntt_scratch_bytes), then CRT and carry produce the product.
 uint32_t ntt_log_len(uint32_t n32);  // log2 of the transform length, 0 if too large
 size_t ntt_scratch_bytes(uint32_t n32, uint64_t batch);
+// `round` bounds the products whose transforms are in tr at once (the batch
+// runs in rounds of that many).
 hipError_t launch_bigmul_ntt(const NttConst &k, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32,
-                             uint64_t batch, uint32_t *tr, hipStream_t st);
+                             uint64_t batch, uint32_t *tr, hipStream_t st, uint64_t round, int num_cus);
 
 // Ragged (descriptor-list) launches of one size class; nmax bounds the
 // class's limb counts, count_max bounds the class size (the true size is read
@@ -203,7 +227,7 @@ size_t ntt_list_scratch_bytes(uint64_t count);
 uint32_t ntt64_log_len(uint32_t n32);  // log2 H, 0 if too large
 size_t ntt64_scratch_bytes(uint32_t n32, uint64_t batch);
 hipError_t launch_bigmul_ntt64(const NttConst64 &k, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32,
-                               uint64_t batch, uint64_t *tr, hipStream_t st);
+                               uint64_t batch, uint64_t *tr, hipStream_t st, uint64_t round);
 hipError_t launch_bigmul_ntt64_list(const NttConst64 &K, const ListInst &src, uint32_t nmax, uint64_t count_max,
                                     uint64_t *scratch, hipStream_t st, int num_cus);
 size_t ntt64_list_scratch_bytes(uint64_t count);
@@ -214,7 +238,7 @@ size_t ntt64_list_scratch_bytes(uint64_t count);
 uint32_t mfma_max_limbs();
 size_t mfma_big_slot_bytes(uint32_t nmax);
 hipError_t launch_bigmul_mfma_big(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
-                                  uint8_t *scr, hipStream_t st, int num_cus);
+                                  uint8_t *scr, hipStream_t st, int num_cus, uint64_t round);
 hipError_t launch_bigmul_mfma_big_list(const ListInst &src, uint32_t nmax, uint64_t count_max, uint8_t *scr,
                                        size_t scr_bytes, hipStream_t st, int num_cus);
 hipError_t launch_bigmul_mfma(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
@@ -225,8 +249,12 @@ size_t fused_lds_bytes(int program, uint32_t n32);
 hipError_t launch_fused(int program, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
                         hipStream_t st, int num_cus);
 
+// Full products of a uniform batch.  Scratch-using algorithms take the
+// context's growable buffer, or with `fixed` set that buffer of fixed_bytes
+// (never grown: the batch runs in rounds that fit it; BI_ESIZE if one product
+// does not).
 bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint32_t n32, uint64_t batch, int algo,
-                          hipStream_t st);
+                          hipStream_t st, void *fixed = nullptr, size_t fixed_bytes = 0);
 bi_status dispatch_bigadd_v(Ctx &c, const void *a, const void *b, void *out, uint8_t *carry, const bi_desc *desc,
                             uint64_t count, uint32_t limb_bits, hipStream_t st);
 // Ragged multiplication core: binning plus one list launch per size class.
@@ -252,13 +280,28 @@ hipError_t launch_bigmul_v_binned(const Ctx &c, const Tune &tune, const void *a,
 size_t large_mul_scratch_bytes(uint64_t n32, uint32_t bw, int num_cus);
 hipError_t launch_bigmul_large(const Ctx &c, const uint32_t *a, const uint32_t *b, uint32_t *out, uint64_t n32,
                                uint32_t bw, int algo, uint8_t *scratch, hipStream_t st);
-// Block size (words) bigmul_large takes for n32-word operands when the caller
-// leaves it to the library.
+// Block size (words) of bigmul_large's block products for n32-word operands
+// when the caller leaves it to the library.
 uint32_t large_mul_auto_block(uint64_t n32);
+
+// The same product as a two-dimensional NTT convolution (rows: the k <= 64
+// blocks of bw words, 512 <= bw <= 8192, transformed along each block;
+// columns: transformed across blocks), then CRT, a fold into words and the
+// multi-workgroup addition.  scratch holds large_ntt_scratch_bytes(n32, bw)
+// bytes, 256-byte aligned.
+constexpr uint32_t kLargeNttMaxBlocks = 64;
+uint32_t large_ntt_auto_block(uint64_t n32);
+size_t large_ntt_scratch_bytes(uint64_t n32, uint32_t bw);
+hipError_t launch_bigmul_large_ntt(const Ctx &c, const uint32_t *a, const uint32_t *b, uint32_t *out, uint64_t n32,
+                                   uint32_t bw, uint8_t *scratch, hipStream_t st);
 bi_status dispatch_bigmul_v(Ctx &c, const void *a, const void *b, void *out, const bi_desc *desc, uint64_t count,
                             uint32_t limb_bits, int algo, hipStream_t st);
 
 bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out);
+// The context's tuning tables to / from a text file keyed by the device
+// architecture and the HIP runtime version.
+bi_status tune_save(const Ctx &c, const char *path);
+bi_status tune_load(Ctx &c, const char *path);
 
 // Raises kernel `fn`'s dynamic-LDS limit to a whole CU (160 KiB) on the
 // current device, once per device: `done` holds one bit per device id (ids

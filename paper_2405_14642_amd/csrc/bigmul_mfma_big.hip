@@ -290,9 +290,10 @@ static hipError_t launch_big(const Src &src, uint32_t nmax, uint64_t count_max, 
 }
 
 hipError_t launch_bigmul_mfma_big(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
-                                  uint8_t *scr, hipStream_t st, int num_cus) {
+                                  uint8_t *scr, hipStream_t st, int num_cus, uint64_t round) {
     if (batch == 0) return hipSuccess;
-    return launch_big(UniformInst{a, b, c, n32, batch}, n32, batch, batch, scr, st, num_cus);
+    if (round == 0) return hipErrorInvalidValue;
+    return launch_big(UniformInst{a, b, c, n32, batch}, n32, batch, std::min(batch, round), scr, st, num_cus);
 }
 
 hipError_t launch_bigmul_mfma_big_list(const ListInst &src, uint32_t nmax, uint64_t count_max, uint8_t *scr,

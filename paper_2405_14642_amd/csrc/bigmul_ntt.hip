@@ -390,6 +390,46 @@ __global__ __launch_bounds__((1 << M) / E) void ntt_inv_kernel(NttConst K, Src s
     }
 }
 
+// The inverse split in two halves, one workgroup per (instance, prime, half)
+// with half the threads of ntt_inv_kernel: the forward transform's positions
+// [h L/2, (h+1) L/2) hold the even (h = 0) or odd (h = 1) frequencies in
+// bit-reversed order, so each half's pointwise product and inverse of length
+// L/2 gives z_h; the coefficients are c_j = z_0[j] + w_L^-j z_1[j] and
+// c_{j+L/2} = z_0[j] - w_L^-j z_1[j] (CrtCoefSplit).  Used when the
+// full-length inverses are too few to fill the GPU.  z_h overwrites the
+// first operand's transform at [h L/2, (h+1) L/2).
+template <int M, class Src>
+__global__ __launch_bounds__((1 << M) / (2 * E)) void ntt_inv_half_kernel(NttConst K, Src src, uint64_t base,
+                                                                          uint64_t chunk, uint32_t *__restrict__ tr) {
+    extern __shared__ __align__(16) uint32_t sh[];
+    constexpr uint32_t L = 1u << M;
+    if constexpr (M > kNttLogLmin) {  // halves need transforms of at least 2^kNttLogLmin points
+    const uint64_t cnt = chunk_count(src, base, chunk);
+    for (uint64_t work = blockIdx.x; work < 4 * cnt; work += gridDim.x) {
+        const uint64_t q2 = work >> 2;
+        const int pr = int(work & 1), h = int((work >> 1) & 1);
+        const uint32_t p = K.p[pr], pneg = K.pneg[pr];
+        uint32_t *ta = tr + (4 * q2 + pr) * L + h * (L / 2);  // operand a, prime pr, this half
+        const uint32_t *tb = ta + 2 * L;                      // operand b, prime pr, this half
+        uint32_t x[E];
+        const uint4 *va = reinterpret_cast<const uint4 *>(ta + E * threadIdx.x);
+        const uint4 *vb = reinterpret_cast<const uint4 *>(tb + E * threadIdx.x);
+#pragma unroll
+        for (int q = 0; q < E / 4; ++q) {
+            const uint4 u = va[q], v = vb[q];
+            x[4 * q] = mul_mont(u.x, v.x, p, pneg);
+            x[4 * q + 1] = mul_mont(u.y, v.y, p, pneg);
+            x[4 * q + 2] = mul_mont(u.z, v.z, p, pneg);
+            x[4 * q + 3] = mul_mont(u.w, v.w, p, pneg);
+        }
+        __syncthreads();  // every thread has read its part of ta before results overwrite it
+        // scale by the full length's L^-1 2^32: z_h then combine without a factor 1/2
+        ntt_inverse<M - 1>(x, ta, L / 2, sh, K.inv[pr], Fp32{p}, make_uint2(K.scale[pr][M], K.scale_sh[pr][M]));
+        __syncthreads();
+    }
+    }
+}
+
 // Product coefficient k (16-bit position) of chunk slot q from the two
 // residues (Garner): residues of prime i at tr + (4 q + i) L.
 struct CrtCoef {
@@ -399,6 +439,27 @@ struct CrtCoef {
         const uint32_t a1 = tr[4 * q * L + k], a2 = tr[(4 * q + 1) * L + k];
         const uint32_t tq = mul_shoup(sub_mod(a2, a1, p2), crt, crt_sh, p2);
         return uint64_t(p1) * tq + a1;  // < p1 p2; equals the coefficient (< 2^46)
+    }
+};
+
+// The same from the two inverse halves of ntt_inv_half_kernel: residue of
+// prime i at position k is z_0[j] +- w_L^-j z_1[j] (j = k mod L/2, minus for
+// k >= L/2), with z_h at tr + (4 q + i) L + h L/2.
+struct CrtCoefSplit {
+    const uint32_t *tr;
+    const uint2 *inv[kNttPrimes];  // w^-e tables, w of order 2^kNttLogLmax
+    uint32_t L, shift, p1, p2, crt, crt_sh;  // shift = kNttLogLmax - log2 L
+    __device__ __forceinline__ uint32_t residue(uint64_t q, int i, uint32_t k, uint32_t p) const {
+        const uint32_t half = L / 2, j = k & (half - 1);
+        const uint32_t *z = tr + (4 * q + i) * L;
+        const uint2 w = inv[i][j << shift];
+        const uint32_t t = mul_shoup(z[half + j], w.x, w.y, p);
+        return k < half ? add_mod(z[j], t, p) : sub_mod(z[j], t, p);
+    }
+    __device__ __forceinline__ uint64_t operator()(uint64_t q, uint32_t k) const {
+        const uint32_t a1 = residue(q, 0, k, p1), a2 = residue(q, 1, k, p2);
+        const uint32_t tq = mul_shoup(sub_mod(a2, a1, p2), crt, crt_sh, p2);
+        return uint64_t(p1) * tq + a1;
     }
 };
 
@@ -614,30 +675,47 @@ static hipError_t launch_crt(const Coef &coef, const Src &src, uint64_t base, ui
 // capped at `cap` workgroups per kernel (the kernels loop over their work).
 template <int M, class Src>
 static hipError_t launch_ntt_m(const NttConst &K, const Src &src, uint32_t nmax, uint64_t count_max, uint64_t chunk,
-                               uint64_t cap, uint32_t *tr, hipStream_t st) {
+                               uint64_t cap, uint32_t *tr, hipStream_t st, int num_cus) {
     const size_t lds = sizeof(uint32_t) * ((1u << M) + (1u << M) / 32);
-    static std::atomic<uint64_t> lds_set[2];
-    for (int i = 0; i < 2; ++i) {
-        const void *fn = i ? reinterpret_cast<const void *>(&ntt_inv_kernel<M, Src>)
-                           : reinterpret_cast<const void *>(&ntt_fwd_kernel<M, Src>);
-        const hipError_t e = lds_limit_once(fn, lds_set[i]);
+    const size_t lds_half = sizeof(uint32_t) * ((1u << (M - 1)) + (1u << (M - 1)) / 32);
+    static std::atomic<uint64_t> lds_set[3];
+    const void *fns[3] = {reinterpret_cast<const void *>(&ntt_fwd_kernel<M, Src>),
+                          reinterpret_cast<const void *>(&ntt_inv_kernel<M, Src>),
+                          reinterpret_cast<const void *>(&ntt_inv_half_kernel<M, Src>)};
+    for (int i = 0; i < 3; ++i) {
+        const hipError_t e = lds_limit_once(fns[i], lds_set[i]);
         if (e != hipSuccess) return e;
     }
     const uint32_t T = (1u << M) / E;
     const uint32_t L = 1u << M;
-    const CrtCoef coef{tr, L, K.p[0], K.p[1], K.crt, K.crt_sh};
+    // workgroups of length 2^M that fit one CU's LDS at once
+    const uint64_t per_cu = (160 * 1024) / lds;
     for (uint64_t base = 0; base < count_max; base += chunk) {
         const uint64_t c = std::min(chunk, count_max - base);
         hipLaunchKernelGGL((ntt_fwd_kernel<M, Src>), dim3(uint32_t(std::min(4 * c, cap))), dim3(T), lds, st, K, src, base,
                            chunk, tr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((ntt_inv_kernel<M, Src>), dim3(uint32_t(std::min(2 * c, cap))), dim3(T), lds, st, K, src, base,
-                           chunk, tr);
+        // 2c full-length inverses that leave CUs idle: run them as 4c halves
+        const bool split = M > kNttLogLmin && 2 * c < per_cu * uint64_t(num_cus > 0 ? num_cus : 1);
+        if (split) {
+            hipLaunchKernelGGL((ntt_inv_half_kernel<M, Src>), dim3(uint32_t(std::min(4 * c, cap))), dim3(T / 2),
+                               lds_half, st, K, src, base, chunk, tr);
+        } else {
+            hipLaunchKernelGGL((ntt_inv_kernel<M, Src>), dim3(uint32_t(std::min(2 * c, cap))), dim3(T), lds, st, K, src,
+                               base, chunk, tr);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         // words go to the second operand's transforms (slots 4 q + 2, 4 q + 3)
-        e = launch_crt(coef, src, base, chunk, std::min(c, cap), nmax, tr + 2 * L, 4 * uint64_t(L), st);
+        if (split) {
+            const CrtCoefSplit coef{tr, {K.inv[0], K.inv[1]}, L, uint32_t(kNttLogLmax - M), K.p[0], K.p[1], K.crt,
+                                    K.crt_sh};
+            e = launch_crt(coef, src, base, chunk, std::min(c, cap), nmax, tr + 2 * L, 4 * uint64_t(L), st);
+        } else {
+            const CrtCoef coef{tr, L, K.p[0], K.p[1], K.crt, K.crt_sh};
+            e = launch_crt(coef, src, base, chunk, std::min(c, cap), nmax, tr + 2 * L, 4 * uint64_t(L), st);
+        }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -645,13 +723,13 @@ static hipError_t launch_ntt_m(const NttConst &K, const Src &src, uint32_t nmax,
 
 template <class Src>
 static hipError_t launch_ntt(const NttConst &K, const Src &src, uint32_t nmax, uint64_t count_max, uint64_t chunk,
-                             uint64_t cap, uint32_t *tr, hipStream_t st) {
+                             uint64_t cap, uint32_t *tr, hipStream_t st, int num_cus) {
     switch (ntt_log_len(nmax)) {
-        case 11: return launch_ntt_m<11>(K, src, nmax, count_max, chunk, cap, tr, st);
-        case 12: return launch_ntt_m<12>(K, src, nmax, count_max, chunk, cap, tr, st);
-        case 13: return launch_ntt_m<13>(K, src, nmax, count_max, chunk, cap, tr, st);
-        case 14: return launch_ntt_m<14>(K, src, nmax, count_max, chunk, cap, tr, st);
-        case 15: return launch_ntt_m<15>(K, src, nmax, count_max, chunk, cap, tr, st);
+        case 11: return launch_ntt_m<11>(K, src, nmax, count_max, chunk, cap, tr, st, num_cus);
+        case 12: return launch_ntt_m<12>(K, src, nmax, count_max, chunk, cap, tr, st, num_cus);
+        case 13: return launch_ntt_m<13>(K, src, nmax, count_max, chunk, cap, tr, st, num_cus);
+        case 14: return launch_ntt_m<14>(K, src, nmax, count_max, chunk, cap, tr, st, num_cus);
+        case 15: return launch_ntt_m<15>(K, src, nmax, count_max, chunk, cap, tr, st, num_cus);
         default: return hipErrorInvalidValue;
     }
 }
@@ -672,7 +750,7 @@ hipError_t launch_bigmul_ntt_list(const NttConst &K, const ListInst &src, uint32
     const uint64_t chunk = cmax << (kNttLogLmax - m);
     // about two resident workgroups per CU (2^(15-M) fit at length 2^M)
     const uint64_t cap = uint64_t(num_cus) << (16 - m);
-    return launch_ntt(K, src, nmax, count_max, chunk, cap, scratch, st);
+    return launch_ntt(K, src, nmax, count_max, chunk, cap, scratch, st, num_cus);
 }
 
 uint32_t ntt_log_len(uint32_t n32) {
@@ -687,9 +765,11 @@ size_t ntt_scratch_bytes(uint32_t n32, uint64_t batch) {
 }
 
 hipError_t launch_bigmul_ntt(const NttConst &K, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32,
-                             uint64_t batch, uint32_t *tr, hipStream_t st) {
+                             uint64_t batch, uint32_t *tr, hipStream_t st, uint64_t round, int num_cus) {
     if (batch == 0) return hipSuccess;
-    return launch_ntt(K, UniformInst{a, b, c, n32, batch}, n32, batch, batch, 65536, tr, st);
+    if (round == 0) return hipErrorInvalidValue;
+    return launch_ntt(K, UniformInst{a, b, c, n32, batch}, n32, batch, std::min(batch, round), 65536, tr, st,
+                      num_cus);
 }
 
 // The three PrimeField64 kernels over instances [0, count_max) of src in rounds
@@ -754,9 +834,10 @@ size_t ntt64_list_scratch_bytes(uint64_t count) {
 }
 
 hipError_t launch_bigmul_ntt64(const NttConst64 &K, const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32,
-                               uint64_t batch, uint64_t *tr, hipStream_t st) {
+                               uint64_t batch, uint64_t *tr, hipStream_t st, uint64_t round) {
     if (batch == 0) return hipSuccess;
-    return launch_ntt64(K, UniformInst{a, b, c, n32, batch}, n32, batch, batch, 65536, tr, st);
+    if (round == 0) return hipErrorInvalidValue;
+    return launch_ntt64(K, UniformInst{a, b, c, n32, batch}, n32, batch, std::min(batch, round), 65536, tr, st);
 }
 
 hipError_t launch_bigmul_ntt64_list(const NttConst64 &K, const ListInst &src, uint32_t nmax, uint64_t count_max,
@@ -770,6 +851,271 @@ hipError_t launch_bigmul_ntt64_list(const NttConst64 &K, const ListInst &src, ui
     // about two resident workgroups per CU (2^(14-M) fit at length 2^M)
     const uint64_t cap = uint64_t(num_cus) << (15 - m);
     return launch_ntt64(K, src, nmax, count_max, chunk, cap, scratch, st);
+}
+
+// ---------------------------------------------------------------------------
+// One product beyond 2^18 bits as a two-dimensional convolution.  With the
+// operands cut into k blocks of bw words (2 bw 16-bit coefficients each),
+//     A(x, y) = sum_q sum_j a_{q,j} x^j y^q   (and B alike),
+// the integer product is C(x, y) = A B evaluated at x = 2^16, y = 2^(32 bw).
+// Zero-padding x to L >= 4 bw points and y to K = 2H >= 2k - 1 points makes
+// both cyclic convolutions exact, so C is the inverse of the pointwise product
+// of the two-dimensional transforms: rows (length L, per block, the transform
+// kernels above) and columns (length K, across blocks, per row position).
+// Each entry c(v, u) is below k 2 bw (2^16 - 1)^2 <= 2^52 < p1 p2, so CRT
+// recovers it exactly, and coefficient P of the product is
+// c(P div 2bw, P mod 2bw) + c(P div 2bw - 1, P mod 2bw + 2bw).
+//
+// Transform slots (L words each) in the scratch: forward rows of block q at
+// 4 q + 2 operand + prime (as the batched forward kernel writes them); the
+// column kernel overwrites them in place with the product rows, row v of
+// prime pr at slot 2 v + pr (a thread owns one column of one prime and reads
+// all of its entries before writing any).
+// ---------------------------------------------------------------------------
+
+// One thread per (column x, prime): the K-point column transforms of a and b
+// as their even (cyclic, H points) and odd (negacyclic: inputs times psi^i,
+// psi of order K) halves, pointwise Montgomery products, H-point inverses,
+// recombination c_j = (E_j + psi^-j O_j) / K, c_{j+H} = (E_j - psi^-j O_j) / K,
+// and the scale that undoes the Montgomery factor and the row transform's L.
+template <int R>
+__global__ __launch_bounds__(64) void ntt_col_kernel(NttConst K, uint32_t *__restrict__ tr, uint32_t L, uint32_t M,
+                                                     uint32_t k) {
+    constexpr int H = 1 << R;
+    __shared__ uint32_t esh[H * 64];  // E_j of lane l at esh[64 j + l]
+    const uint32_t wgs_per_prime = L / 64;
+    const int pr = int(blockIdx.x / wgs_per_prime);  // uniform: twiddles come through scalar loads
+    const uint32_t lane = threadIdx.x;
+    const uint32_t x = (blockIdx.x - uint32_t(pr) * wgs_per_prime) * 64 + lane;
+    const uint32_t p = K.p[pr], pneg = K.pneg[pr];
+    const Fp32 f{p};
+    const uint2 *fw = K.fwd[pr], *iw = K.inv[pr];
+    const uint32_t *col = tr + x;
+    auto ld = [&](uint32_t slot) { return col[uint64_t(slot) * L]; };
+    uint32_t ya[H], yb[H];
+    // even half: DFT_H of the zero-padded block columns
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        ya[i] = uint32_t(i) < k ? ld(4 * i + pr) : 0u;
+        yb[i] = uint32_t(i) < k ? ld(4 * i + 2 + pr) : 0u;
+    }
+    small_dif<R>(ya, fw, f);
+    small_dif<R>(yb, fw, f);
+#pragma unroll
+    for (int i = 0; i < H; ++i) ya[i] = mul_mont(ya[i], yb[i], p, pneg);
+    small_dit_inv<R>(ya, iw, f);
+#pragma unroll
+    for (int i = 0; i < H; ++i) esh[64 * i + lane] = ya[i];
+    // odd half: the same on inputs twisted by psi^i (psi = w^(2^(14 - R)))
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const uint2 ps = fw[uint32_t(i) << (14 - R)];
+        ya[i] = uint32_t(i) < k ? f.mulw(ld(4 * i + pr), ps) : 0u;
+        yb[i] = uint32_t(i) < k ? f.mulw(ld(4 * i + 2 + pr), ps) : 0u;
+    }
+    small_dif<R>(ya, fw, f);
+    small_dif<R>(yb, fw, f);
+#pragma unroll
+    for (int i = 0; i < H; ++i) ya[i] = mul_mont(ya[i], yb[i], p, pneg);
+    small_dit_inv<R>(ya, iw, f);
+    // recombine and scale by 2^-(R + 1 + M) 2^32; rows v < 2k - 1
+    const uint2 sc = make_uint2(K.scale[pr][R + 1 + M], K.scale_sh[pr][R + 1 + M]);
+    const uint32_t nrows = 2 * k - 1;
+    uint32_t *out = tr + x;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        const uint32_t e = esh[64 * j + lane];
+        const uint32_t o = f.mulw(ya[j], iw[uint32_t(j) << (14 - R)]);
+        if (uint32_t(j) < nrows) out[uint64_t(2 * j + pr) * L] = f.mulw(f.add(e, o), sc);
+        if (uint32_t(j + H) < nrows) out[uint64_t(2 * (j + H) + pr) * L] = f.mulw(f.sub(e, o), sc);
+    }
+}
+
+// One workgroup per product row (slot 2 v + prime): the inverse row
+// transform, in place, natural order out (the column kernel applied every
+// scale factor).
+template <int M>
+__global__ __launch_bounds__((1 << M) / E) void ntt_rowinv_kernel(NttConst K, uint32_t *__restrict__ tr,
+                                                                  uint32_t nslots) {
+    extern __shared__ __align__(16) uint32_t sh[];
+    constexpr uint32_t L = 1u << M;
+    for (uint32_t slot = blockIdx.x; slot < nslots; slot += gridDim.x) {
+        const int pr = int(slot & 1u);
+        uint32_t *row = tr + uint64_t(slot) * L;
+        uint32_t x[E];
+        const uint4 *v = reinterpret_cast<const uint4 *>(row + E * threadIdx.x);
+#pragma unroll
+        for (int q = 0; q < E / 4; ++q) {
+            const uint4 u = v[q];
+            x[4 * q] = u.x;
+            x[4 * q + 1] = u.y;
+            x[4 * q + 2] = u.z;
+            x[4 * q + 3] = u.w;
+        }
+        __syncthreads();  // every thread has read its part of the row before results overwrite it
+        ntt_inverse<M>(x, row, L, sh, K.inv[pr], Fp32{K.p[pr]}, make_uint2(1u, K.one_sh[pr]));
+        __syncthreads();
+    }
+}
+
+// Coefficient P (16-bit position) of the long product from the product rows.
+struct LargeCoef {
+    const uint32_t *tr;
+    uint32_t L, bw2, nrows;  // bw2 = 2 bw coefficients per block; nrows = 2k - 1
+    uint32_t p1, p2, crt, crt_sh;
+    __device__ __forceinline__ uint64_t entry(uint32_t v, uint32_t u) const {
+        const uint32_t r1 = tr[uint64_t(2 * v) * L + u], r2 = tr[uint64_t(2 * v + 1) * L + u];
+        const uint32_t tq = mul_shoup(sub_mod(r2, r1, p2), crt, crt_sh, p2);
+        return uint64_t(p1) * tq + r1;  // < p1 p2; equals c(v, u) (< 2^52)
+    }
+    __device__ __forceinline__ uint64_t operator()(uint64_t P) const {
+        const uint32_t v = uint32_t(P / bw2), u = uint32_t(P - uint64_t(v) * bw2);
+        uint64_t c = v < nrows ? entry(v, u) : 0;
+        if (v >= 1 && v - 1 < nrows) c += entry(v - 1, u + bw2);
+        return c;  // < 2^53
+    }
+};
+
+// Coefficients to words: word w of the product is W_w = c(2w) + c(2w+1) 2^16
+// < 2^70, written lo_w + m_w 2^32 (m_w < 2^38).  Then
+//     product = sum_w S_w 2^(32 w),  S_w = lo_w + (m_{w-1} mod 2^32) + floor(m_{w-2} / 2^32) < 2^34,
+// stored as the low words Lw[w] = S_w mod 2^32 and high words Hw[w + 1] =
+// floor(S_w / 2^32) for the final addition.  One thread per 8 words (it
+// recomputes the two words below its group).
+__global__ __launch_bounds__(256) void large_ntt_fold_kernel(LargeCoef coef, uint64_t nwords, uint32_t *__restrict__ Lw,
+                                                             uint32_t *__restrict__ Hw) {
+    const uint64_t ngroups = (nwords + 7) / 8;
+    for (uint64_t g = uint64_t(blockIdx.x) * 256 + threadIdx.x; g < ngroups; g += uint64_t(gridDim.x) * 256) {
+        const uint64_t w0 = 8 * g;
+        uint32_t lo[10];
+        uint64_t m[10];
+#pragma unroll
+        for (int i = 0; i < 10; ++i) {
+            const uint64_t w = w0 + uint64_t(i) - 2;  // wraps for w0 = 0, i < 2: then >= nwords
+            if (w >= nwords) {
+                lo[i] = 0;
+                m[i] = 0;
+                continue;
+            }
+            const uint64_t c0 = coef(2 * w), c1 = coef(2 * w + 1);
+            const uint64_t t = c0 + ((c1 & 0xFFFFu) << 16);  // < 2^53 + 2^32
+            lo[i] = uint32_t(t);
+            m[i] = (t >> 32) + (c1 >> 16);
+        }
+#pragma unroll
+        for (int i = 2; i < 10; ++i) {
+            const uint64_t w = w0 + uint64_t(i) - 2;
+            if (w >= nwords) break;
+            const uint64_t sw = uint64_t(lo[i]) + uint32_t(m[i - 1]) + (m[i - 2] >> 32);
+            Lw[w] = uint32_t(sw);
+            if (w + 1 < nwords) Hw[w + 1] = uint32_t(sw >> 32);
+        }
+        if (g == 0) Hw[0] = 0;
+    }
+}
+
+namespace {
+
+struct LargeNttLayout {
+    uint32_t k, M, R;
+    size_t tr, lw, hw, ascr, total;
+};
+
+LargeNttLayout large_ntt_layout(uint64_t n32, uint32_t bw) {
+    LargeNttLayout s;
+    s.k = uint32_t((n32 + bw - 1) / bw);
+    s.M = ntt_log_len(bw);
+    s.R = 0;
+    while ((2u << s.R) < 2 * s.k - 1) ++s.R;  // K = 2^(R+1) >= 2k - 1
+    const uint64_t nwords = 2 * n32;
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    s.tr = 0;
+    s.lw = al(s.tr + size_t(4) * s.k * (size_t(1) << s.M) * sizeof(uint32_t));
+    s.hw = al(s.lw + nwords * sizeof(uint32_t));
+    s.ascr = al(s.hw + (nwords + 1) * sizeof(uint32_t));
+    // the addition's chunk width follows out's alignment: size for the narrowest
+    s.total = al(s.ascr + large_add_scratch_bytes(large_add_tiles(nwords, 1)));
+    return s;
+}
+
+template <int M>
+hipError_t launch_large_rows(const NttConst &K, const BlockInst &src, uint32_t *tr, uint32_t nslots_inv, bool fwd,
+                             hipStream_t st) {
+    const size_t lds = sizeof(uint32_t) * ((1u << M) + (1u << M) / 32);
+    static std::atomic<uint64_t> lds_set[2];
+    const void *fn = fwd ? reinterpret_cast<const void *>(&ntt_fwd_kernel<M, BlockInst>)
+                         : reinterpret_cast<const void *>(&ntt_rowinv_kernel<M>);
+    hipError_t e = lds_limit_once(fn, lds_set[fwd ? 0 : 1]);
+    if (e != hipSuccess) return e;
+    const uint32_t T = (1u << M) / E;
+    if (fwd)
+        hipLaunchKernelGGL((ntt_fwd_kernel<M, BlockInst>), dim3(4 * src.k), dim3(T), lds, st, K, src, 0, src.k, tr);
+    else
+        hipLaunchKernelGGL((ntt_rowinv_kernel<M>), dim3(nslots_inv), dim3(T), lds, st, K, tr, nslots_inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows(uint32_t M, const NttConst &K, const BlockInst &src, uint32_t *tr, uint32_t nslots_inv, bool fwd,
+                       hipStream_t st) {
+    switch (M) {
+        case 11: return launch_large_rows<11>(K, src, tr, nslots_inv, fwd, st);
+        case 12: return launch_large_rows<12>(K, src, tr, nslots_inv, fwd, st);
+        case 13: return launch_large_rows<13>(K, src, tr, nslots_inv, fwd, st);
+        case 14: return launch_large_rows<14>(K, src, tr, nslots_inv, fwd, st);
+        case 15: return launch_large_rows<15>(K, src, tr, nslots_inv, fwd, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_cols(uint32_t R, const NttConst &K, uint32_t *tr, uint32_t M, uint32_t k, hipStream_t st) {
+    const uint32_t L = 1u << M;
+    const dim3 grid(2 * L / 64), blk(64);
+    switch (R) {
+        case 0: hipLaunchKernelGGL((ntt_col_kernel<0>), grid, blk, 0, st, K, tr, L, M, k); break;
+        case 1: hipLaunchKernelGGL((ntt_col_kernel<1>), grid, blk, 0, st, K, tr, L, M, k); break;
+        case 2: hipLaunchKernelGGL((ntt_col_kernel<2>), grid, blk, 0, st, K, tr, L, M, k); break;
+        case 3: hipLaunchKernelGGL((ntt_col_kernel<3>), grid, blk, 0, st, K, tr, L, M, k); break;
+        case 4: hipLaunchKernelGGL((ntt_col_kernel<4>), grid, blk, 0, st, K, tr, L, M, k); break;
+        case 5: hipLaunchKernelGGL((ntt_col_kernel<5>), grid, blk, 0, st, K, tr, L, M, k); break;
+        case 6: hipLaunchKernelGGL((ntt_col_kernel<6>), grid, blk, 0, st, K, tr, L, M, k); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Blocks of 2^(9..13) words: as many as the column transform takes (64), so
+// the row transforms fill the GPU, on blocks of at least 512 words.
+uint32_t large_ntt_auto_block(uint64_t n32) {
+    uint32_t bw = 512;
+    while (bw < kMaxLimbs32 && (n32 + bw - 1) / bw > kLargeNttMaxBlocks) bw *= 2;
+    return bw;
+}
+
+size_t large_ntt_scratch_bytes(uint64_t n32, uint32_t bw) { return large_ntt_layout(n32, bw).total; }
+
+hipError_t launch_bigmul_large_ntt(const Ctx &c, const uint32_t *a, const uint32_t *b, uint32_t *out, uint64_t n32,
+                                   uint32_t bw, uint8_t *scratch, hipStream_t st) {
+    const LargeNttLayout s = large_ntt_layout(n32, bw);
+    if (s.M == 0 || s.k == 0 || s.k > kLargeNttMaxBlocks) return hipErrorInvalidValue;
+    const NttConst &K = c.ntt.c;
+    auto *tr = reinterpret_cast<uint32_t *>(scratch + s.tr);
+    auto *Lw = reinterpret_cast<uint32_t *>(scratch + s.lw);
+    auto *Hw = reinterpret_cast<uint32_t *>(scratch + s.hw);
+    const BlockInst src{a, b, n32, bw, s.k};
+    const uint32_t nrows = 2 * s.k - 1;
+    hipError_t e = launch_rows(s.M, K, src, tr, 0, true, st);
+    if (e == hipSuccess) e = launch_cols(s.R, K, tr, s.M, s.k, st);
+    if (e == hipSuccess) e = launch_rows(s.M, K, src, tr, 2 * nrows, false, st);
+    if (e != hipSuccess) return e;
+    const uint64_t nwords = 2 * n32, groups = (nwords + 7) / 8;
+    const LargeCoef coef{tr, 1u << s.M, 2 * bw, nrows, K.p[0], K.p[1], K.crt, K.crt_sh};
+    hipLaunchKernelGGL(large_ntt_fold_kernel, dim3(uint32_t(std::min<uint64_t>((groups + 255) / 256, 65536))),
+                       dim3(256), 0, st, coef, nwords, Lw, Hw);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_bigadd_large(Lw, Hw, out, nullptr, nwords, scratch + s.ascr, st, c.num_cus);
 }
 
 }  // namespace bi

@@ -29,17 +29,30 @@ bool algo_supports(int algo, uint32_t n32) {
     }
 }
 
-// Default algorithm per size class (replaced by bi_autotune measurements).
+// Built-in per-class table, as bi_autotune measured it on MI355X (one GPU, a
+// fresh context, each class timed at its largest size): the VALU schoolbook
+// up to 64 limbs (2^11 bits), the int8-MFMA schoolbook up to 4096 limbs
+// (2^17 bits), the two-prime NTT at 8192 limbs; and the VALU schedule
+// (Q output words per lane, waves per workgroup) it picked per class.
+// bi_autotune re-measures and replaces it on the device at hand.
 static void default_tune(Tune &t) {
+    static const int algo[kNumClasses] = {BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_VALU,
+                                          BI_MUL_SCHOOL_MFMA, BI_MUL_SCHOOL_MFMA, BI_MUL_SCHOOL_MFMA,
+                                          BI_MUL_SCHOOL_MFMA, BI_MUL_SCHOOL_MFMA, BI_MUL_SCHOOL_MFMA,
+                                          BI_MUL_NTT};
+    static const uint8_t q[kNumClasses] = {2, 2, 2, 4, 2, 2, 4, 4, 4, 4};
+    static const uint8_t nw[kNumClasses] = {1, 1, 1, 1, 2, 4, 4, 8, 16, 16};
     for (uint32_t k = 0; k < kNumClasses; ++k) {
-        const uint32_t n = class_nmax(k);
-        t.mul_algo[k] = n <= 1024 ? BI_MUL_SCHOOL_VALU : BI_MUL_NTT;
-        t.valu_q[k] = t.valu_nw[k] = 0;  // the size rule of valu_plan
+        t.mul_algo[k] = algo[k];
+        t.valu_q[k] = q[k];
+        t.valu_nw[k] = nw[k];
     }
 }
 
 bi_status ctx_init(Ctx &c, int device, const hipDeviceProp_t &prop) {
     c.device = device;
+    std::snprintf(c.arch, sizeof(c.arch), "%s", prop.gcnArchName);
+    if (hipRuntimeGetVersion(&c.hip_version) != hipSuccess) c.hip_version = 0;
     default_tune(c.tune);
     c.num_cus = prop.multiProcessorCount;
     // Defaults from a sweep on MI355X (u64 limbs, 1 GiB of operands): a large
@@ -108,51 +121,62 @@ uint32_t size_class_host(uint32_t n32) {
     return k;
 }
 
+// Scratch for `per_inst` bytes per product of a batch: the fixed buffer when
+// given (rounds of as many products as it holds), else the context's buffer
+// grown to the whole batch.
+static bi_status bigmul_scratch(Ctx &c, size_t per_inst, uint64_t batch, hipStream_t st, void *fixed,
+                                size_t fixed_bytes, void **scr, uint64_t *round) {
+    if (fixed) {
+        if (per_inst > fixed_bytes)
+            return set_error(BI_ESIZE, "one product needs %zu bytes of scratch, the fixed array holds %zu", per_inst,
+                             fixed_bytes);
+        *scr = fixed;
+        *round = fixed_bytes / per_inst;
+        return BI_OK;
+    }
+    *round = batch;
+    return ctx_scratch(c, per_inst * size_t(batch), st, scr);
+}
+
 bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint32_t n32, uint64_t batch, int algo,
-                          hipStream_t st) {
+                          hipStream_t st, void *fixed, size_t fixed_bytes) {
     if (algo == BI_MUL_AUTO) {
         algo = c.tune.mul_algo[size_class_host(n32)];
         if (!algo_supports(algo, n32)) algo = BI_MUL_SCHOOL_VALU;
     }
+    auto A = static_cast<const uint32_t *>(a);
+    auto B = static_cast<const uint32_t *>(b);
+    auto C = static_cast<uint32_t *>(out);
     hipError_t e = hipSuccess;
+    void *scr = nullptr;
+    uint64_t round = 0;
+    bi_status s = BI_OK;
     switch (algo) {
         case BI_MUL_SCHOOL_VALU:
-            e = launch_bigmul_valu(static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
-                                   static_cast<uint32_t *>(out), n32, batch, valu_plan_tuned(n32, c.tune), st,
-                                   c.num_cus);
+            e = launch_bigmul_valu(A, B, C, n32, batch, valu_plan_tuned(n32, c.tune), st, c.num_cus);
             break;
         case BI_MUL_SCHOOL_MFMA:
             if (n32 <= mfma_max_limbs()) {
-                e = launch_bigmul_mfma(static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
-                                       static_cast<uint32_t *>(out), n32, batch, st, c.num_cus);
+                e = launch_bigmul_mfma(A, B, C, n32, batch, st, c.num_cus);
             } else {
-                void *scr = nullptr;
-                bi_status s = ctx_scratch(c, size_t(batch) * mfma_big_slot_bytes(n32), st, &scr);
+                s = bigmul_scratch(c, mfma_big_slot_bytes(n32), batch, st, fixed, fixed_bytes, &scr, &round);
                 if (s != BI_OK) return s;
-                e = launch_bigmul_mfma_big(static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
-                                           static_cast<uint32_t *>(out), n32, batch, static_cast<uint8_t *>(scr), st,
-                                           c.num_cus);
+                e = launch_bigmul_mfma_big(A, B, C, n32, batch, static_cast<uint8_t *>(scr), st, c.num_cus, round);
             }
             break;
-        case BI_MUL_NTT: {
+        case BI_MUL_NTT:
             if (ntt_log_len(n32) == 0) return set_error(BI_EALGO, "NTT supports up to %u limbs", kNttLmax / 4);
-            void *resid = nullptr;
-            const size_t bytes = ntt_scratch_bytes(n32, batch);
-            bi_status s = ctx_scratch(c, bytes, st, &resid);
+            s = bigmul_scratch(c, ntt_scratch_bytes(n32, 1), batch, st, fixed, fixed_bytes, &scr, &round);
             if (s != BI_OK) return s;
-            e = launch_bigmul_ntt(c.ntt.c, static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
-                                  static_cast<uint32_t *>(out), n32, batch, static_cast<uint32_t *>(resid), st);
+            e = launch_bigmul_ntt(c.ntt.c, A, B, C, n32, batch, static_cast<uint32_t *>(scr), st, round, c.num_cus);
             break;
-        }
-        case BI_MUL_NTT_PF64: {
-            if (ntt64_log_len(n32) == 0) return set_error(BI_EALGO, "NTT (PrimeField64) supports up to %u limbs", kP64Hmax / 2);
-            void *resid = nullptr;
-            bi_status s = ctx_scratch(c, ntt64_scratch_bytes(n32, batch), st, &resid);
+        case BI_MUL_NTT_PF64:
+            if (ntt64_log_len(n32) == 0)
+                return set_error(BI_EALGO, "NTT (PrimeField64) supports up to %u limbs", kP64Hmax / 2);
+            s = bigmul_scratch(c, ntt64_scratch_bytes(n32, 1), batch, st, fixed, fixed_bytes, &scr, &round);
             if (s != BI_OK) return s;
-            e = launch_bigmul_ntt64(c.ntt.c64, static_cast<const uint32_t *>(a), static_cast<const uint32_t *>(b),
-                                    static_cast<uint32_t *>(out), n32, batch, static_cast<uint64_t *>(resid), st);
+            e = launch_bigmul_ntt64(c.ntt.c64, A, B, C, n32, batch, static_cast<uint64_t *>(scr), st, round);
             break;
-        }
         default:
             return set_error(BI_EALGO, "multiplication algorithm %d is not available", algo);
     }

@@ -109,6 +109,7 @@ bi_status ntt_setup(NttTables &t) {
         const uint64_t wi = powmod(w, p - 2, p);
         t.c.p[i] = p;
         t.c.pneg[i] = neg_inv32(p);
+        t.c.one_sh[i] = shoup(1u, p);
         uint64_t f = 1, g = 1;
         uint2 *fw = host.data() + size_t(2 * i) * kNttTableWords;
         uint2 *iw = fw + kNttTableWords;
@@ -137,8 +138,8 @@ bi_status ntt_setup(NttTables &t) {
         // Output scale for transform length 2^l: L^-1 * R mod p (R = 2^32 undoes
         // the R^-1 left by the Montgomery pointwise product).
         const uint64_t R = (uint64_t(1) << 32) % p;
-        for (uint32_t l = 0; l <= kNttLogLmax; ++l) {
-            const uint64_t linv = powmod(uint64_t(1) << l, p - 2, p);
+        for (uint32_t l = 0; l <= uint32_t(kNttScaleMax); ++l) {
+            const uint64_t linv = powmod(powmod(2, l, p), p - 2, p);
             const uint32_t s = uint32_t(mulmod(linv, R, p));
             t.c.scale[i][l] = s;
             t.c.scale_sh[i][l] = shoup(s, p);

@@ -103,7 +103,6 @@ def test_bigadd_large_validation(B, args, status):
     (dict(algo=9), -1),                           # unknown algorithm
     (dict(algo=-1), -1),
     (dict(algo=4), -1),                           # every algorithm runs 2^18-bit blocks: fails only on ctx
-    (dict(block=1 << 15), -1),                    # block sizes other than 2^16..2^18
     (dict(block=(1 << 16) + 32), -1),
     (dict(block=1 << 16, algo=3), -1),            # valid block and algorithm: fails only on ctx
 ])
@@ -113,6 +112,30 @@ def test_bigmul_large_validation(B, args, status):
     st = B.lib.bigmul_large(None, p["a"], p["b"], p["out"], p["n"], p["limb_bits"], p["algo"], p["block"], None)
     assert st == status, B.lib.bi_last_error()
     assert B.lib.bi_last_error()
+
+
+@pytest.mark.parametrize("args,valid", [
+    (dict(block=1 << 14), True),                  # the NTT path (AUTO, NTT) takes blocks of 2^14..2^18 bits
+    (dict(block=1 << 15, algo=3), True),
+    (dict(block=1 << 13), False),
+    (dict(block=1 << 19), False),
+    (dict(block=3 << 14), False),
+    (dict(n=(1 << 24) // 32, block=1 << 17), False),  # 128 blocks: the column transform takes at most 64
+    (dict(n=(1 << 24) // 32, block=1 << 18), True),
+    (dict(n=64 * 512 + 1, block=1 << 14), False),
+    (dict(n=64 * 512, block=1 << 14), True),
+    (dict(block=1 << 15, algo=2), False),         # block products take 2^16..2^18-bit blocks
+    (dict(block=1 << 16, algo=2), True),
+])
+def test_bigmul_large_block_sizes(B, args, valid):
+    """Block sizes each path accepts: an invalid one fails on its own
+    (BI_EINVAL naming the blocks), a valid one only on the NULL context."""
+    p = dict(a=FAKE, b=FAKE + (1 << 24), out=FAKE + (2 << 24), n=4, limb_bits=32, algo=0, block=0)
+    p.update(args)
+    st = B.lib.bigmul_large(None, p["a"], p["b"], p["out"], p["n"], p["limb_bits"], p["algo"], p["block"], None)
+    assert st == -1
+    msg = B.lib.bi_last_error().decode()
+    assert (msg == "ctx is NULL") == valid, msg
 
 
 @pytest.mark.parametrize("args,status", [
@@ -187,6 +210,8 @@ def test_tuning_validation(B):
     assert B.lib.bi_autotune(None, None, arr, 10) == -1
     assert B.lib.bi_tune_get(None, arr, 10) == -1
     assert B.lib.bi_tune_set(None, arr, 10) == -1
+    assert B.lib.bi_tune_save(None, b"/tmp/x") == -1
+    assert B.lib.bi_tune_load(None, b"/tmp/x") == -1
 
 
 def test_stream_validation_host(B):

@@ -227,6 +227,44 @@ def test_autotune_and_auto_dispatch(B, orc):
         c.close()
 
 
+def test_tune_save_load(B, orc, tmp_path):
+    """Autotuned tables persist: saved, loaded into a fresh context (the same
+    tables, products bit-exact), and a file for another architecture or a
+    malformed one is refused with the context unchanged."""
+    c = B.Context(0)
+    try:
+        algos = B.autotune(c)
+        valu = B.tune_get_valu(c)
+        path = str(tmp_path / "tune.txt")
+        B.tune_save(c, path)
+    finally:
+        c.close()
+    d = B.Context(0)
+    try:
+        B.tune_set(d, [1] * B.NUM_CLASSES)
+        B.tune_load(d, path)
+        assert B.tune_get(d) == algos and B.tune_get_valu(d) == valu
+        rng = np.random.default_rng(7)
+        for n in (40, 700, 5000):
+            a, b = patterned(rng, 3, n)
+            check(orc, a, b, run_mul(B, d, a, b, 0))
+        text = open(path).read()
+        other = str(tmp_path / "other.txt")
+        arch = [l for l in text.splitlines() if l.startswith("arch ")][0]
+        open(other, "w").write(text.replace(arch, "arch gfx942"))
+        B.tune_set(d, [2] * B.NUM_CLASSES)
+        with pytest.raises(B.BigIntError):
+            B.tune_load(d, other)
+        open(other, "w").write(text.replace("mul_algo", "mul_alg"))
+        with pytest.raises(B.BigIntError):
+            B.tune_load(d, other)
+        with pytest.raises(B.BigIntError):
+            B.tune_load(d, str(tmp_path / "missing.txt"))
+        assert B.tune_get(d) == [2] * B.NUM_CLASSES
+    finally:
+        d.close()
+
+
 def test_valu_schedules(B, orc):
     """Every VALU schoolbook schedule (Q = 2 or 4 output words per lane, 1..16
     waves) that fits a class's sizes is bit-exact, for the class's largest

@@ -1,7 +1,11 @@
-"""Parity of bigmul_large (one product beyond 2^18 bits, built from block
-products) with the CPU oracle's schoolbook product, bit-exact: sizes around
-the 8192-word block with ragged last blocks, all-ones operands (every column
-sum and carry at its largest), u32 and u64 limbs, and a 2^21-bit product."""
+"""Parity of bigmul_large (one product beyond 2^18 bits) with the CPU
+oracle's schoolbook product, bit-exact.  The default path (AUTO, NTT) is a
+two-dimensional NTT convolution over blocks of 2^14..2^18 bits; a forced
+VALU, MFMA or PrimeField64 algorithm runs k^2 block products instead.  Sizes
+around the block boundaries with ragged last blocks and around the 64-block
+limit of the column transform, all-ones operands (every coefficient and carry
+at its largest), u32 and u64 limbs, products of 2^21 and 2^22 bits in full,
+and the 2^24-bit maximum (low words and residues)."""
 from __future__ import annotations
 
 import numpy as np
@@ -85,7 +89,8 @@ def test_repeat_after_smaller(B, ctx, orc):
 
 @pytest.mark.parametrize("algo", [1, 2, 3, 4])
 def test_block_algorithms(B, ctx, orc, algo):
-    """Every algorithm forced for the block products gives the same product."""
+    """Every algorithm (3: the NTT path; others: block products of that
+    algorithm) gives the same product."""
     n = 2 * BLOCK + 3
     rng = np.random.default_rng(algo)
     a = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
@@ -93,16 +98,60 @@ def test_block_algorithms(B, ctx, orc, algo):
     check(orc, a, b, run(B, ctx, a, b, algo))
 
 
-@pytest.mark.parametrize("block_bits", [1 << 16, 1 << 17, 1 << 18])
-@pytest.mark.parametrize("n", [2047, 2049, 3 * 4096 + 5, 40000])
-def test_block_sizes(B, ctx, orc, block_bits, n):
-    """Every block size gives the same product, around its block boundaries."""
-    rng = np.random.default_rng(n ^ block_bits)
+@pytest.mark.parametrize("algo", [0, 2])
+@pytest.mark.parametrize("block_bits", [1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18])
+@pytest.mark.parametrize("n", [1, 511, 513, 2047, 2049, 3 * 4096 + 5, 32768, 40000])
+def test_block_sizes(B, ctx, orc, algo, block_bits, n):
+    """Every block size of either path gives the same product, around its
+    block boundaries (the NTT path takes at most 64 blocks, block products
+    2^16..2^18-bit blocks)."""
+    bw = block_bits // 32
+    if (algo == 0 and -(-n // bw) > 64) or (algo == 2 and block_bits < (1 << 16)):
+        pytest.skip("block size not taken by this path at this size")
+    if n not in _ORACLE_CACHE:  # one oracle product per size, shared by every block size and path
+        rng = np.random.default_rng(n)
+        a = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        if n in (513, 2049):
+            a[:] = 0xFFFFFFFF
+            b[:] = 0xFFFFFFFF
+        _ORACLE_CACHE[n] = (a, b, orc.mul(a[None, :], b[None, :])[0])
+    a, b, want = _ORACLE_CACHE[n]
+    got = run(B, ctx, a, b, algo, block_bits)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, f"{bad.size} limbs differ, first at {bad[:8]}"
+
+
+_ORACLE_CACHE = {}
+
+
+@pytest.mark.parametrize("n", [64 * 512 - 1, 64 * 512, 64 * 512 + 1, 64 * 1024 + 1, 5 * 8192 + 17])
+def test_ntt_block_count_edges(B, ctx, orc, n):
+    """Automatic blocks around the column transform's 64-block limit (the
+    block size doubles past it) and at several column lengths."""
+    rng = np.random.default_rng(n)
     a = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
     b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
-    if n == 2049:
-        a[:] = 0xFFFFFFFF
-    check(orc, a, b, run(B, ctx, a, b, block_bits=block_bits))
+    a[-1] = b[-1] = 0xFFFFFFFF
+    check(orc, a, b, run(B, ctx, a, b))
+
+
+def test_2_22_bits_all_ones(B, ctx, orc):
+    """A 2^22-bit product of all-ones operands: (2^N - 1)^2, every entry of
+    the two-dimensional convolution at its bound, checked in full."""
+    n = 1 << 17
+    a = np.full(n, 0xFFFFFFFF, dtype=np.uint32)
+    got = run(B, ctx, a, a.copy())
+    exp = np.concatenate([[1], np.zeros(n - 1), [0xFFFFFFFE], np.full(n - 1, 0xFFFFFFFF)]).astype(np.uint32)
+    assert (got == exp).all()
+
+
+def test_2_22_bits(B, ctx, orc):
+    n = 1 << 17
+    rng = np.random.default_rng(22)
+    a = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    check(orc, a, b, run(B, ctx, a, b))
 
 
 def _mod(x: np.ndarray, p: int) -> int:
@@ -114,7 +163,7 @@ def _mod(x: np.ndarray, p: int) -> int:
 
 
 def test_max_size_sampled(B, ctx, orc):
-    """2^24-bit operands (the largest size, 4096 block products): the lowest
+    """2^24-bit operands (the largest size, 64 blocks of 2^18 bits): the lowest
     8192 words equal the oracle's product of the operands' lowest 8192 words
     (they depend on nothing else), and the whole product agrees with a * b
     modulo three 61-bit primes."""
