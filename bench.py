@@ -73,7 +73,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU baseline budget")
     p.add_argument("--sizes", default="", help="comma-separated subset of sizes in bits (profiling runs)")
-    p.add_argument("--algos", default="valu,mfma,ntt,ntt64", help="multiplication algorithms to time")
+    p.add_argument("--algos", default="valu,mfma,ntt,ntt64,kara", help="multiplication algorithms to time")
     return p.parse_args()
 
 
@@ -254,7 +254,35 @@ MFMA_I8_PEAK_OPS = 5.0e15                        # dense int8, ops (2 per MAC)
 # compare-select and shifts).
 NTT64_BFLY_PEAK = 1024 * 2.4e9 / (7 / 16 + 16 / 32)  # 2.62e12 butterflies/s
 
-ALGO_IDS = {"valu": 1, "mfma": 2, "ntt": 3, "ntt64": 4}
+ALGO_IDS = {"valu": 1, "mfma": 2, "ntt": 3, "ntt64": 4, "kara": 5}
+
+
+def mul_roofline(name, n, batch, us):
+    """Roofline of `batch` products of n-word operands by algorithm `name`
+    that took `us` microseconds."""
+    macs = float(batch) * n * n
+    if name == "valu":
+        return {"bound": "alu", "achieved": round(macs / (us * 1e-6) / 1e12, 3),
+                "peak": round(VALU_MAC_PEAK / 1e12, 3), "unit": "T u32-MAC/s",
+                "frac": round(macs / (us * 1e-6) / VALU_MAC_PEAK, 4)}
+    if name in ("ntt", "ntt64"):
+        m = 11
+        while (1 << m) < (4 if name == "ntt" else 2) * n:
+            m += 1
+        bfly = 2.0 * 3 * batch * (1 << m) / 2 * m
+        peak = NTT_BFLY_PEAK if name == "ntt" else NTT64_BFLY_PEAK
+        return {"bound": "alu", "achieved": round(bfly / (us * 1e-6) / 1e12, 3),
+                "peak": round(peak / 1e12, 3),
+                "unit": "T butterflies/s" + ("" if name == "ntt" else " (PF64)"),
+                "frac": round(bfly / (us * 1e-6) / peak, 4), "butterflies": bfly}
+    # mfma: min(int8 peak, arithmetic intensity x HBM); the operands and the
+    # product (16 n bytes per pair) bound the small sizes
+    ops = 2.0 * batch * (4 * n) ** 2
+    hbm_roof = ops / (16.0 * n * batch) * HBM_PEAK_GBS * 1e9
+    peak = min(MFMA_I8_PEAK_OPS, hbm_roof)
+    return {"bound": "mfma" if peak == MFMA_I8_PEAK_OPS else "hbm",
+            "achieved": round(ops / (us * 1e-6) / 1e12, 1), "peak": round(peak / 1e12, 1),
+            "unit": "TOP/s (int8)", "frac": round(ops / (us * 1e-6) / peak, 4)}
 
 
 def bench_mul(args, kind):
@@ -297,51 +325,34 @@ def bench_mul(args, kind):
             for _ in range(args.warmup):
                 B.bigmul(ctx, A, Bt, out, algo=algo, stream=stream.cuda_stream)
             torch.cuda.synchronize()
-            evs = []
+            # the calls back to back, timed as one region: the average call
+            # of a stream of them (throughput), host enqueue overlapped
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
             for _ in range(args.steps):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
                 B.bigmul(ctx, A, Bt, out, algo=algo, stream=stream.cuda_stream)
-                e1.record(stream)
-                evs.append((e0, e1))
+            e1.record(stream)
             torch.cuda.synchronize()
-            us = 1e3 * float(np.mean([x.elapsed_time(y) for x, y in evs]))
+            us = 1e3 * e0.elapsed_time(e1) / args.steps
             macs = float(batch) * n * n
             r = {"us_per_launch": round(us, 2), "mults_per_s": batch / (us * 1e-6),
                  "u32_macs_per_s": macs / (us * 1e-6)}
-            if name == "valu":
-                r["roofline"] = {"bound": "alu", "achieved": round(macs / (us * 1e-6) / 1e12, 3),
-                                 "peak": round(VALU_MAC_PEAK / 1e12, 3), "unit": "T u32-MAC/s",
-                                 "frac": round(macs / (us * 1e-6) / VALU_MAC_PEAK, 4)}
-            elif name == "ntt":
-                m = 11
-                while (1 << m) < 4 * n:
-                    m += 1
-                bfly = 2.0 * 3 * batch * (1 << m) / 2 * m
-                r["butterflies_per_launch"] = bfly
-                r["roofline"] = {"bound": "alu", "achieved": round(bfly / (us * 1e-6) / 1e12, 3),
-                                 "peak": round(NTT_BFLY_PEAK / 1e12, 3), "unit": "T butterflies/s",
-                                 "frac": round(bfly / (us * 1e-6) / NTT_BFLY_PEAK, 4)}
-            elif name == "ntt64":
-                m = 11
-                while (1 << m) < 2 * n:
-                    m += 1
-                bfly = 2.0 * 3 * batch * (1 << m) / 2 * m
-                r["butterflies_per_launch"] = bfly
-                r["roofline"] = {"bound": "alu", "achieved": round(bfly / (us * 1e-6) / 1e12, 3),
-                                 "peak": round(NTT64_BFLY_PEAK / 1e12, 3), "unit": "T butterflies/s (PF64)",
-                                 "frac": round(bfly / (us * 1e-6) / NTT64_BFLY_PEAK, 4)}
-            elif name == "mfma":
-                # min(int8 peak, arithmetic intensity x HBM): the operands and
-                # the product (16 n bytes per pair) bound the small sizes
-                ops = 2.0 * batch * (4 * n) ** 2
-                hbm_roof = ops / (16.0 * n * batch) * HBM_PEAK_GBS * 1e9
-                peak = min(MFMA_I8_PEAK_OPS, hbm_roof)
-                r["roofline"] = {"bound": "mfma" if peak == MFMA_I8_PEAK_OPS else "hbm",
-                                 "achieved": round(ops / (us * 1e-6) / 1e12, 1),
-                                 "peak": round(peak / 1e12, 1), "unit": "TOP/s (int8)",
-                                 "frac": round(ops / (us * 1e-6) / peak, 4)}
+            if name == "kara":
+                # the work actually done: 3^levels base products per pair with
+                # the base algorithm, against that algorithm's roofline
+                plan = B.mul_plan(ctx, n, 32, algo)
+                nb = batch * 3 ** plan["kara_levels"]
+                base_name = {v: k for k, v in ALGO_IDS.items()}[plan["base_algo"]]
+                r["plan"] = dict(plan, base_products_per_launch=nb)
+                r["roofline"] = mul_roofline(base_name, plan["base_limbs"], nb, us)
+                # context: the same products as one full-size int8-MFMA schoolbook
+                sb_ops = 2.0 * batch * (4 * n) ** 2
+                r["schoolbook_mfma_equiv_frac"] = round(sb_ops / (us * 1e-6) / MFMA_I8_PEAK_OPS, 4)
+            else:
+                r["roofline"] = mul_roofline(name, n, batch, us)
+                if "butterflies" in r["roofline"]:
+                    r["butterflies_per_launch"] = r["roofline"].pop("butterflies")
             results.setdefault(str(bits), {})[name] = r
             if best is None or us < best[1]:
                 best = (name, us)

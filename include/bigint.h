@@ -61,7 +61,9 @@ typedef enum bi_mul_algo {
     BI_MUL_SCHOOL_VALU = 1,  /* load-balanced schoolbook on the VALU (Section 3)     */
     BI_MUL_SCHOOL_MFMA = 2,  /* schoolbook on int8 MFMA, signed 8-bit digits         */
     BI_MUL_NTT = 3,          /* NTT over two word-size primes + CRT (Section 4)       */
-    BI_MUL_NTT_PF64 = 4      /* NTT over the one 64-bit prime PrimeField64 (Section 4.1) */
+    BI_MUL_NTT_PF64 = 4,     /* NTT over the one 64-bit prime PrimeField64 (Section 4.1) */
+    BI_MUL_KARATSUBA = 5     /* Karatsuba levels over a batched base product (sizes by  */
+                             /* choice of algorithm, left open in Section 1)           */
 } bi_mul_algo;
 
 typedef struct bi_ctx bi_ctx;
@@ -123,16 +125,24 @@ bi_status bigadd_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
  * a, b: n_limbs limbs of limb_bits (32 or 64) bits; 1 <= n_limbs and
  * n_limbs * limb_bits <= BI_MAX_LARGE_MUL_BITS (BI_EINVAL / BI_ESIZE);
  * out must not overlap a or b (BI_EALIAS); pointers limb-aligned (BI_ELIMB).
- * The operands are cut into k blocks of block_bits bits (2^16, 2^17 or 2^18;
- * 0 lets the library choose by size, other values BI_EINVAL); the k^2 block
- * products run as one ragged batch through the tuned per-size-class kernels,
- * a column-sum kernel folds them and bigadd_large's kernels add the low and
- * high words.  algo: the block products' algorithm, BI_MUL_AUTO or one that
- * runs products of that block size (BI_EALGO otherwise; BI_EINVAL for an
- * unknown value).
- * Uses context scratch (about k^2 * 64 KB of block products plus the batch's
- * transform scratch; BI_ENOMEM if it cannot grow).  Asynchronous like every
- * call.
+ * algo BI_MUL_AUTO or BI_MUL_NTT: a two-dimensional NTT convolution (n log n
+ * work): the operands are cut into k <= 64 blocks of block_bits bits (a
+ * power of two in [2^14, 2^18]; 0 lets the library choose the smallest of at
+ * least 2^14 bits that gives at most 64 blocks), each block's 16-bit
+ * coefficients are transformed along the block (length 4 * block words)
+ * and the results across the blocks (length 2k rounded up to a power of
+ * two), modulo the two primes of BI_MUL_NTT; pointwise products, both
+ * inverses, CRT, a fold into words and bigadd_large's kernels give the
+ * product.  Scratch: 16 k (4 block words) bytes of transforms plus 17 n
+ * bytes of fold and addition buffers (n = 32-bit words of an operand).
+ * algo BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_MFMA, BI_MUL_NTT_PF64 or
+ * BI_MUL_KARATSUBA: k^2 block products of that algorithm (block_bits 2^16,
+ * 2^17 or 2^18, 0: 2^16 up to 2^20-bit operands, 2^18 above) as one ragged
+ * batch, a column-sum kernel and bigadd_large's kernels; scratch about
+ * 8 k^2 (block words) bytes of block products plus the batch's own.
+ * BI_EALGO if the algorithm cannot run the block size; BI_EINVAL for an
+ * unknown algorithm or block size.  BI_ENOMEM if the context's scratch
+ * cannot grow.  Asynchronous like every call.
  */
 bi_status bigmul_large(bi_ctx *ctx, const void *a, const void *b, void *out, uint64_t n_limbs, uint32_t limb_bits,
                        int algo, uint32_t block_bits, void *stream);
@@ -157,11 +167,35 @@ bi_status bigmul_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
  *                        Montgomery arithmetic; the product is taken as its
  *                        cyclic and negacyclic halves (transforms of half the
  *                        padded length), recombined, then a carry scan.
- *   BI_MUL_AUTO          the fastest of the above for (n_limbs, batch).
+ *   BI_MUL_KARATSUBA     levels of the subtractive Karatsuba split (a0 b0,
+ *                        a1 b1 and |a0 - a1| |b0 - b1| for halves a0, a1,
+ *                        b0, b1) until the operands have at most 1024 words
+ *                        (2^15 bits), whose products run as one batch with
+ *                        the tuned algorithm of that size; 3^levels base
+ *                        products per pair instead of 4^levels.
+ *   BI_MUL_AUTO          the tuned choice of the above for the size class.
  * Results are exact (bit-identical across algorithms).
  */
 bi_status bigmul(bi_ctx *ctx, const void *a, const void *b, void *out,
                  uint32_t n_limbs, uint32_t limb_bits, uint64_t batch, int algo, void *stream);
+
+/*
+ * bi_mul_plan -- what bigmul runs for n_limbs-limb operands with `algo` on
+ * this context (host only, no HIP call): the algorithm (BI_MUL_AUTO resolved
+ * through the tuning table), and for BI_MUL_KARATSUBA the number of levels,
+ * the words of each base product and the base products' algorithm (without
+ * Karatsuba: 0 levels, n_limbs * limb_bits / 32 words, the algorithm itself).
+ * Errors as bigmul's argument checks (BI_ELIMB, BI_EINVAL, BI_ESIZE), and
+ * BI_EALGO if the algorithm cannot run that size.
+ */
+typedef struct bi_mul_plan_info {
+    int algo;
+    int kara_levels;
+    uint32_t base_limbs; /* 32-bit words */
+    int base_algo;
+} bi_mul_plan_info;
+
+bi_status bi_mul_plan(const bi_ctx *ctx, uint32_t n_limbs, uint32_t limb_bits, int algo, bi_mul_plan_info *out);
 
 /*
  * bi_fused -- the paper's fused programs (Section 6.1): several same-length

@@ -15,13 +15,13 @@ import os
 
 __all__ = ["Context", "BigIntError", "bigadd", "bigmul", "bigadd_v", "bigmul_v", "fused", "ntt_field", "StreamQueue",
            "DESC_DTYPE", "lib", "library_path",
-           "MUL_AUTO", "MUL_SCHOOL_VALU", "MUL_SCHOOL_MFMA", "MUL_NTT", "MUL_NTT_PF64", "PROG_ADD6", "PROG_POLY", "PROG_MUL_LOW", "MAX_BITS",
+           "MUL_AUTO", "MUL_SCHOOL_VALU", "MUL_SCHOOL_MFMA", "MUL_NTT", "MUL_NTT_PF64", "MUL_KARATSUBA", "PROG_ADD6", "PROG_POLY", "PROG_MUL_LOW", "MAX_BITS",
            "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libbigint.so")
 
-MUL_AUTO, MUL_SCHOOL_VALU, MUL_SCHOOL_MFMA, MUL_NTT, MUL_NTT_PF64 = 0, 1, 2, 3, 4
+MUL_AUTO, MUL_SCHOOL_VALU, MUL_SCHOOL_MFMA, MUL_NTT, MUL_NTT_PF64, MUL_KARATSUBA = 0, 1, 2, 3, 4, 5
 PROG_ADD6, PROG_POLY, PROG_MUL_LOW = 1, 2, 3
 MAX_BITS = 1 << 18
 STATUS = {0: "BI_OK", -1: "BI_EINVAL", -2: "BI_ESIZE", -3: "BI_ELIMB", -4: "BI_EALIAS", -5: "BI_EHIP",
@@ -32,7 +32,7 @@ EXPORTS = ("bi_ctx_create", "bi_ctx_destroy", "bi_status_str", "bi_last_error",
            "bi_tune_set", "bi_stream_open", "bi_stream_submit", "bi_stream_poll", "bi_stream_wait",
            "bi_stream_close", "bi_fused", "bi_tune_get_valu",
            "bi_tune_set_valu", "bigadd_large", "bigmul_large", "bi_tune_save",
-           "bi_tune_load")
+           "bi_tune_load", "bi_mul_plan")
 NUM_CLASSES = 10
 
 
@@ -41,6 +41,13 @@ class NttFieldInfo(ctypes.Structure):
     2^two_adicity-th root of unity (Section 4.1)."""
     _fields_ = [("p", ctypes.c_uint64), ("k", ctypes.c_uint64), ("two_adicity", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32), ("a", ctypes.c_uint64), ("g", ctypes.c_uint64)]
+
+
+class MulPlanInfo(ctypes.Structure):
+    """bi_mul_plan_info: the algorithm bigmul runs, and for Karatsuba its
+    levels, base product size (32-bit words) and base algorithm."""
+    _fields_ = [("algo", ctypes.c_int), ("kara_levels", ctypes.c_int), ("base_limbs", ctypes.c_uint32),
+                ("base_algo", ctypes.c_int)]
 
 
 class BigIntError(RuntimeError):
@@ -89,7 +96,8 @@ def _load():
     L.bi_fused.argtypes = [P, I, P, P, P, U32, U32, U64, P]
     L.bi_tune_get_valu.argtypes = [P, P, P, U32]
     L.bi_tune_set_valu.argtypes = [P, P, P, U32]
-    for f in (L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field, L.bi_autotune,
+    L.bi_mul_plan.argtypes = [P, U32, U32, I, P]
+    for f in (L.bi_mul_plan, L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field, L.bi_autotune,
               L.bi_tune_get, L.bi_tune_set, L.bi_stream_open, L.bi_stream_submit, L.bi_stream_poll,
               L.bi_stream_wait, L.bi_stream_close, L.bi_fused, L.bi_tune_get_valu,
               L.bi_tune_set_valu, L.bigadd_large, L.bigmul_large, L.bi_tune_save, L.bi_tune_load):
@@ -266,6 +274,14 @@ def tune_get(ctx):
     out = (ctypes.c_int * NUM_CLASSES)()
     _check(lib.bi_tune_get(_h(ctx), out, NUM_CLASSES))
     return list(out)
+
+
+def mul_plan(ctx, n_limbs, limb_bits=32, algo=MUL_AUTO):
+    """What bigmul runs for n_limbs-limb operands: dict(algo, kara_levels,
+    base_limbs, base_algo)."""
+    info = MulPlanInfo()
+    _check(lib.bi_mul_plan(_h(ctx), n_limbs, limb_bits, algo, ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in MulPlanInfo._fields_}
 
 
 def tune_set(ctx, algos):

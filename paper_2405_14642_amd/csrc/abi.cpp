@@ -178,7 +178,7 @@ bi_status bigmul_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
     if (n_limbs > BI_MAX_LARGE_MUL_BITS / limb_bits)
         return fail(BI_ESIZE, "n_limbs * limb_bits exceeds %u bits (n_limbs = %llu)", BI_MAX_LARGE_MUL_BITS,
                     (unsigned long long)n_limbs);
-    if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT_PF64) return fail(BI_EINVAL, "unknown algorithm %d", algo);
+    if (algo < BI_MUL_AUTO || algo > BI_MUL_KARATSUBA) return fail(BI_EINVAL, "unknown algorithm %d", algo);
     const uint64_t n32 = n_limbs * (limb_bits / 32);
     // AUTO and NTT: the two-dimensional NTT convolution (n log n); a forced
     // VALU, MFMA or PrimeField64 algorithm: k^2 block products of that algorithm.
@@ -226,7 +226,7 @@ bi_status bigmul(bi_ctx *ctx, const void *a, const void *b, void *out, uint32_t 
     uint64_t ib = 0;
     bi_status s = check_shape(n_limbs, limb_bits, batch, &ib);
     if (s != BI_OK) return s;
-    if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT_PF64) return fail(BI_EINVAL, "unknown algorithm %d", algo);
+    if (algo < BI_MUL_AUTO || algo > BI_MUL_KARATSUBA) return fail(BI_EINVAL, "unknown algorithm %d", algo);
     if (batch == 0) return ctx ? BI_OK : fail(BI_EINVAL, "ctx is NULL");
     if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
     if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;
@@ -286,7 +286,7 @@ bi_status bigadd_v(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t
 bi_status bigmul_v(bi_ctx *ctx, const void *a, const void *b, void *out, const bi_desc *desc, uint64_t count,
                    uint32_t limb_bits, int algo, void *stream) {
     if (limb_bits != 32 && limb_bits != 64) return fail(BI_ELIMB, "limb_bits must be 32 or 64 (got %u)", limb_bits);
-    if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT_PF64) return fail(BI_EINVAL, "unknown algorithm %d", algo);
+    if (algo < BI_MUL_AUTO || algo > BI_MUL_KARATSUBA) return fail(BI_EINVAL, "unknown algorithm %d", algo);
     if (count == 0) return ctx ? BI_OK : fail(BI_EINVAL, "ctx is NULL");
     if (!desc) return fail(BI_EINVAL, "desc is NULL");
     bi_status s;
@@ -310,6 +310,29 @@ bi_status bi_autotune(bi_ctx *ctx, void *stream, int *algo_out, uint32_t n_out) 
 bi_status bi_tune_get(const bi_ctx *ctx, int *algo_out, uint32_t n_out) {
     if (!ctx || !algo_out) return fail(BI_EINVAL, "NULL argument");
     for (uint32_t k = 0; k < n_out && k < bi::kNumClasses; ++k) algo_out[k] = ctx->impl.tune.mul_algo[k];
+    return BI_OK;
+}
+
+bi_status bi_mul_plan(const bi_ctx *ctx, uint32_t n_limbs, uint32_t limb_bits, int algo, bi_mul_plan_info *out) {
+    uint64_t ib = 0;
+    bi_status s = check_shape(n_limbs, limb_bits, 1, &ib);
+    if (s != BI_OK) return s;
+    if (algo < BI_MUL_AUTO || algo > BI_MUL_KARATSUBA) return fail(BI_EINVAL, "unknown algorithm %d", algo);
+    if (!ctx || !out) return fail(BI_EINVAL, "NULL argument");
+    const uint32_t n32 = n_limbs * (limb_bits / 32);
+    const int alg = bi::resolve_algo(ctx->impl.tune, n32, algo);
+    if (!bi::algo_supports(alg, n32)) return fail(BI_EALGO, "algorithm %d does not run %u-word products", alg, n32);
+    bi_mul_plan_info r{};
+    r.algo = alg;
+    r.base_limbs = n32;
+    r.base_algo = alg;
+    if (alg == BI_MUL_KARATSUBA) {
+        const bi::KaraPlan kp = bi::kara_plan(n32, bi::kKaraBase);
+        r.kara_levels = kp.levels;
+        r.base_limbs = kp.h[kp.levels];
+        r.base_algo = bi::kara_base_algo(ctx->impl.tune, r.base_limbs);
+    }
+    *out = r;
     return BI_OK;
 }
 

@@ -63,7 +63,7 @@ bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out) {
     hipLaunchKernelGGL(fill_hash_kernel, dim3(1024), dim3(256), 0, st, a, 2 * limbs, 0x2405u);
     Timer tm;
     bi_status s = BI_OK;
-    const int algos[4] = {BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_MFMA, BI_MUL_NTT, BI_MUL_NTT_PF64};
+    const int algos[5] = {BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_MFMA, BI_MUL_NTT, BI_MUL_NTT_PF64, BI_MUL_KARATSUBA};
     for (uint32_t k = 0; k < kNumClasses && s == BI_OK; ++k) {
         const uint32_t n = class_nmax(k);
         uint64_t batch = limbs / n;

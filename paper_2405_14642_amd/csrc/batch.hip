@@ -61,30 +61,53 @@ static size_t lists_bytes(uint64_t count) {
     return (size_t(kNumClasses) * count * sizeof(uint32_t) + 255) & ~size_t(255);
 }
 
+// Scratch a class launch may use for `count` instances: the largest of the
+// NTT transforms and the Karatsuba levels (whatever the class's algorithm).
+static size_t class_scratch_bytes(uint64_t count) {
+    return std::max({ntt_list_scratch_bytes(count), ntt64_list_scratch_bytes(count), kara_list_scratch_bound(count)});
+}
+
 size_t batch_scratch_bytes(uint64_t count, int num_cus) {
     (void)num_cus;
-    return 256 + lists_bytes(count) + std::max(ntt_list_scratch_bytes(count), ntt64_list_scratch_bytes(count));
+    return 256 + lists_bytes(count) + class_scratch_bytes(count);
+}
+
+size_t list_algo_scratch_bytes(int alg, uint32_t nmax, uint64_t count) {
+    switch (alg) {
+        case BI_MUL_SCHOOL_MFMA: return nmax <= mfma_max_limbs() ? 0 : ntt_list_scratch_bytes(count);
+        case BI_MUL_NTT: return ntt_list_scratch_bytes(count);
+        case BI_MUL_NTT_PF64: return ntt64_list_scratch_bytes(count);
+        default: return 0;
+    }
+}
+
+hipError_t launch_bigmul_list_algo(const Ctx &c, const Tune &tune, const ListInst &src, uint32_t nmax,
+                                   uint64_t count_max, int alg, void *scr, size_t scr_bytes, hipStream_t st) {
+    switch (alg) {
+        case BI_MUL_SCHOOL_MFMA:
+            return nmax <= mfma_max_limbs() ? launch_bigmul_mfma_list(src, nmax, count_max, st, c.num_cus)
+                                            : launch_bigmul_mfma_big_list(src, nmax, count_max,
+                                                                          static_cast<uint8_t *>(scr), scr_bytes, st,
+                                                                          c.num_cus);
+        case BI_MUL_NTT:
+            return launch_bigmul_ntt_list(c.ntt.c, src, nmax, count_max, static_cast<uint32_t *>(scr), st, c.num_cus);
+        case BI_MUL_NTT_PF64:
+            return launch_bigmul_ntt64_list(c.ntt.c64, src, nmax, count_max, static_cast<uint64_t *>(scr), st,
+                                            c.num_cus);
+        case BI_MUL_KARATSUBA:
+            return launch_bigmul_kara_list(c, tune, src, nmax, count_max, static_cast<uint8_t *>(scr), scr_bytes, st);
+        default: return launch_bigmul_valu_list(src, nmax, count_max, valu_plan_tuned(nmax, tune), st, c.num_cus);
+    }
 }
 
 // The list kernel of size class k's algorithm (the tuned one, or `algo` when
 // it is forced and supports the class) over at most count_max instances.
 static hipError_t launch_class(const Ctx &c, const Tune &tune, const ListInst &src, uint32_t k, uint64_t count_max,
-                               int algo, uint32_t *ntt_scr, hipStream_t st) {
+                               int algo, void *scr, hipStream_t st) {
     const uint32_t nmax = class_nmax(k);
     int alg = tune.mul_algo[k];
     if (algo != BI_MUL_AUTO && algo_supports(algo, nmax)) alg = algo;
-    switch (alg) {
-        case BI_MUL_SCHOOL_MFMA:
-            return nmax <= mfma_max_limbs()
-                       ? launch_bigmul_mfma_list(src, nmax, count_max, st, c.num_cus)
-                       : launch_bigmul_mfma_big_list(src, nmax, count_max, reinterpret_cast<uint8_t *>(ntt_scr),
-                                                     ntt_list_scratch_bytes(count_max), st, c.num_cus);
-        case BI_MUL_NTT: return launch_bigmul_ntt_list(c.ntt.c, src, nmax, count_max, ntt_scr, st, c.num_cus);
-        case BI_MUL_NTT_PF64:
-            return launch_bigmul_ntt64_list(c.ntt.c64, src, nmax, count_max, reinterpret_cast<uint64_t *>(ntt_scr), st,
-                                            c.num_cus);
-        default: return launch_bigmul_valu_list(src, nmax, count_max, valu_plan_tuned(nmax, tune), st, c.num_cus);
-    }
+    return launch_bigmul_list_algo(c, tune, src, nmax, count_max, alg, scr, class_scratch_bytes(count_max), st);
 }
 
 hipError_t launch_bigmul_v_binned(const Ctx &c, const Tune &tune, const void *a, const void *b, void *out,
@@ -100,7 +123,7 @@ hipError_t launch_bigmul_v_binned(const Ctx &c, const Tune &tune, const void *a,
         const uint64_t n = host_counts[k];
         if (n == 0) continue;
         const ListInst src{A, B, C, desc, lists + off, counts + k, wpl};
-        const hipError_t e = launch_class(c, tune, src, k, n, algo, static_cast<uint32_t *>(scratch), st);
+        const hipError_t e = launch_class(c, tune, src, k, n, algo, scratch, st);
         if (e != hipSuccess) return e;
         off += n;
     }
@@ -112,7 +135,7 @@ hipError_t launch_bigmul_v_core(const Ctx &c, const Tune &tune, const void *a, c
                                 uint32_t limb_bits, int algo, void *scratch, hipStream_t st) {
     uint32_t *counts = static_cast<uint32_t *>(scratch);
     uint32_t *lists = reinterpret_cast<uint32_t *>(static_cast<char *>(scratch) + 256);
-    uint32_t *ntt_scr = reinterpret_cast<uint32_t *>(static_cast<char *>(scratch) + 256 + lists_bytes(count_max));
+    void *cls_scr = static_cast<char *>(scratch) + 256 + lists_bytes(count_max);
     const uint32_t wpl = limb_bits / 32;
     hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, st, counts, uint32_t(kNumClasses));
     const uint64_t bins = (count_max + 255) / 256;
@@ -125,7 +148,7 @@ hipError_t launch_bigmul_v_core(const Ctx &c, const Tune &tune, const void *a, c
     auto C = static_cast<uint32_t *>(out);
     for (uint32_t k = 0; k < kNumClasses; ++k) {
         const ListInst src{A, B, C, desc, lists + uint64_t(k) * count_max, counts + k, wpl};
-        e = launch_class(c, tune, src, k, count_max, algo, ntt_scr, st);
+        e = launch_class(c, tune, src, k, count_max, algo, cls_scr, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

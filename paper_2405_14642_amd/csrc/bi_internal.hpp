@@ -32,6 +32,9 @@ struct Tune {
     uint8_t valu_nw[kNumClasses];
 };
 bool algo_supports(int algo, uint32_t n32);
+// The algorithm bigmul runs for `algo` at n32 words: BI_MUL_AUTO resolves to
+// the size class's tuned choice (the VALU schoolbook if that cannot run n32).
+int resolve_algo(const Tune &tune, uint32_t n32, int algo);
 
 // NTT field constants (two primes below 2^31) and device twiddle tables.
 constexpr int kNttPrimes = 2;
@@ -294,6 +297,47 @@ uint32_t large_ntt_auto_block(uint64_t n32);
 size_t large_ntt_scratch_bytes(uint64_t n32, uint32_t bw);
 hipError_t launch_bigmul_large_ntt(const Ctx &c, const uint32_t *a, const uint32_t *b, uint32_t *out, uint64_t n32,
                                    uint32_t bw, uint8_t *scratch, hipStream_t st);
+// Ragged list launch of one resolved algorithm `alg` (not BI_MUL_AUTO) over
+// instances of up to nmax words; scr holds scr_bytes of scratch, at least
+// list_algo_scratch_bytes(alg, nmax, count_max).
+size_t list_algo_scratch_bytes(int alg, uint32_t nmax, uint64_t count);
+hipError_t launch_bigmul_list_algo(const Ctx &c, const Tune &tune, const ListInst &src, uint32_t nmax,
+                                   uint64_t count_max, int alg, void *scr, size_t scr_bytes, hipStream_t st);
+
+// Karatsuba levels over a batched base product.  kara_plan(n, base): operand
+// words h[j] of level j (h[0] = n; h[j+1] = ceil(h[j] / 2) rounded up to a
+// multiple of 4) down to the first level of at most `base` words (at least
+// one level).  The base algorithm is the tuned one of the last level's size
+// class (the MFMA schoolbook if that is Karatsuba itself).
+constexpr int kKaraMaxLevels = 4;
+constexpr uint32_t kKaraBase = 1024;       // base products of at most 2^15 bits
+constexpr uint64_t kKaraListRound = 64;    // ragged instances per round of levels
+constexpr size_t kKaraScratchBudget = size_t(256) << 20;  // uniform batches: scratch per round
+struct KaraPlan {
+    int levels = 0;
+    uint32_t h[kKaraMaxLevels + 1] = {};
+};
+KaraPlan kara_plan(uint32_t n32, uint32_t base);
+int kara_base_algo(const Tune &tune, uint32_t h);
+// Scratch of one round of R top-level instances (list: ragged rounds, which
+// also publish the base products as a descriptor list), plus base_bytes for
+// the base algorithm.
+size_t kara_round_bytes(const KaraPlan &p, uint64_t R, bool list, size_t base_bytes);
+// Uniform batch in rounds of `round` instances, each round's levels in `scr`
+// (kara_round_bytes(p, round, false, base_bytes) bytes); base_bytes > 0 gives
+// the base algorithm that fixed share of the scratch.
+bi_status launch_bigmul_kara(Ctx &c, const uint32_t *a, const uint32_t *b, uint32_t *out, uint32_t n32,
+                             uint64_t batch, const KaraPlan &p, int base_algo, size_t base_bytes, uint8_t *scr,
+                             uint64_t round, hipStream_t st);
+// Ragged size-class list of instances of up to nmax words, in rounds that fit
+// scr_bytes; kara_list_scratch_bound(count) bytes suffice for every class.
+hipError_t launch_bigmul_kara_list(const Ctx &c, const Tune &tune, const ListInst &src, uint32_t nmax,
+                                   uint64_t count_max, uint8_t *scr, size_t scr_bytes, hipStream_t st);
+size_t kara_list_scratch_bound(uint64_t count);
+// Scratch bytes per product of a uniform batch of n32-word products (0 when
+// the algorithm needs none).
+size_t uniform_algo_scratch_bytes(int alg, uint32_t n32);
+
 bi_status dispatch_bigmul_v(Ctx &c, const void *a, const void *b, void *out, const bi_desc *desc, uint64_t count,
                             uint32_t limb_bits, int algo, hipStream_t st);
 

@@ -18,20 +18,22 @@ namespace bi {
 
 // src(c, x, y) fills the 4 words of chunk c (words 4c .. 4c+3) of both
 // addends; sink(c, s) receives the 4 sum words of chunk c (only for chunks
-// with c < nchunks).  Words at index >= nwords must read as 0.  Returns, in
-// every thread, the carry out of the whole sum when nwords is a multiple of 4
-// (otherwise that carry stays inside the last chunk's sum words).  Contains
-// barriers: every thread of the workgroup must call it.
+// with c < nchunks).  Words at index >= nwords must read as 0.  cin0 (0 or
+// 1) is a carry into word 0.  Returns, in every thread, the carry out of the
+// whole sum when nwords is a multiple of 4 (otherwise that carry stays inside
+// the last chunk's sum words).  Contains barriers: every thread of the
+// workgroup must call it.
 template <int NW, class Src, class Sink>
 __device__ __forceinline__ uint32_t wg_add_rows_sink(const Src &src, const Sink &sink, uint32_t nwords,
-                                                     uint32_t *summary /* LDS, NW words */) {
+                                                     uint32_t *summary /* LDS, NW words */, uint32_t cin0 = 0) {
     const uint32_t lane = lane_id();
     const uint32_t w = wave_in_block();
     const uint32_t nchunks = (nwords + 3) / 4;
     const uint32_t rows = (nchunks + 63) / 64;
     const uint32_t r0 = (rows * w) / NW, r1 = (rows * (w + 1)) / NW;
 
-    uint32_t cin = 0, allp = 1;
+    // wave 0's summary includes cin0, so the waves above fold it in below
+    uint32_t cin = w == 0 ? cin0 : 0, allp = 1;
     for (uint32_t r = r0; r < r1; ++r) {
         const uint32_t c = r * 64 + lane;
         uint32_t x[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0}, s[4];
@@ -55,6 +57,7 @@ __device__ __forceinline__ uint32_t wg_add_rows_sink(const Src &src, const Sink 
         if (v < w) cin = (sv & 1u) | ((sv >> 1) & cin);
         total = (sv & 1u) | ((sv >> 1) & total);
     }
+    if (w == 0) cin = cin0;
     for (uint32_t r = r0; r < r1; ++r) {
         const uint32_t c = r * 64 + lane;
         uint32_t x[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0}, s[4];

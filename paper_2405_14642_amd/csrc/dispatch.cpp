@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
 
 #include "bi_internal.hpp"
@@ -25,7 +26,29 @@ bool algo_supports(int algo, uint32_t n32) {
         case BI_MUL_SCHOOL_MFMA: return n32 >= 1 && n32 <= kMaxLimbs32;
         case BI_MUL_NTT: return n32 >= 1 && ntt_log_len(n32) != 0;
         case BI_MUL_NTT_PF64: return n32 >= 1 && ntt64_log_len(n32) != 0;
+        case BI_MUL_KARATSUBA: return n32 >= 1 && n32 <= kMaxLimbs32;
         default: return false;
+    }
+}
+
+int resolve_algo(const Tune &tune, uint32_t n32, int algo) {
+    if (algo != BI_MUL_AUTO) return algo;
+    algo = tune.mul_algo[size_class_host(n32)];
+    return algo_supports(algo, n32) ? algo : BI_MUL_SCHOOL_VALU;
+}
+
+int kara_base_algo(const Tune &tune, uint32_t h) {
+    const int alg = tune.mul_algo[size_class_host(h)];
+    if (alg != BI_MUL_KARATSUBA && algo_supports(alg, h)) return alg;
+    return BI_MUL_SCHOOL_MFMA;
+}
+
+size_t uniform_algo_scratch_bytes(int alg, uint32_t n32) {
+    switch (alg) {
+        case BI_MUL_SCHOOL_MFMA: return n32 <= mfma_max_limbs() ? 0 : mfma_big_slot_bytes(n32);
+        case BI_MUL_NTT: return ntt_scratch_bytes(n32, 1);
+        case BI_MUL_NTT_PF64: return ntt64_scratch_bytes(n32, 1);
+        default: return 0;
     }
 }
 
@@ -140,10 +163,7 @@ static bi_status bigmul_scratch(Ctx &c, size_t per_inst, uint64_t batch, hipStre
 
 bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint32_t n32, uint64_t batch, int algo,
                           hipStream_t st, void *fixed, size_t fixed_bytes) {
-    if (algo == BI_MUL_AUTO) {
-        algo = c.tune.mul_algo[size_class_host(n32)];
-        if (!algo_supports(algo, n32)) algo = BI_MUL_SCHOOL_VALU;
-    }
+    algo = resolve_algo(c.tune, n32, algo);
     auto A = static_cast<const uint32_t *>(a);
     auto B = static_cast<const uint32_t *>(b);
     auto C = static_cast<uint32_t *>(out);
@@ -177,6 +197,32 @@ bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint3
             if (s != BI_OK) return s;
             e = launch_bigmul_ntt64(c.ntt.c64, A, B, C, n32, batch, static_cast<uint64_t *>(scr), st, round);
             break;
+        case BI_MUL_KARATSUBA: {
+            const KaraPlan kp = kara_plan(n32, kKaraBase);
+            const uint32_t hb = kp.h[kp.levels];
+            const int base = kara_base_algo(c.tune, hb);
+            uint64_t nbase = 1;  // base products per instance
+            for (int j = 0; j < kp.levels; ++j) nbase *= 3;
+            // the base's own scratch: all of a round's products at once
+            const size_t per_base = uniform_algo_scratch_bytes(base, hb);
+            const size_t per = kara_round_bytes(kp, 1, false, per_base * nbase);
+            uint64_t R = batch;
+            if (fixed) {
+                R = std::min<uint64_t>(batch, fixed_bytes / per);
+                if (R == 0)
+                    return set_error(BI_ESIZE, "one Karatsuba product needs %zu bytes of scratch, the fixed array "
+                                     "holds %zu", per, fixed_bytes);
+                while (R > 1 && kara_round_bytes(kp, R, false, per_base * nbase * R) > fixed_bytes) --R;
+                scr = fixed;
+            } else {
+                // rounds of at most kKaraScratchBudget bytes (at least one instance)
+                R = std::min<uint64_t>(batch, std::max<uint64_t>(1, kKaraScratchBudget / per));
+                s = ctx_scratch(c, kara_round_bytes(kp, R, false, per_base * nbase * R), st, &scr);
+                if (s != BI_OK) return s;
+            }
+            return launch_bigmul_kara(c, A, B, C, n32, batch, kp, base, per_base * nbase * R,
+                                      static_cast<uint8_t *>(scr), R, st);
+        }
         default:
             return set_error(BI_EALGO, "multiplication algorithm %d is not available", algo);
     }

@@ -98,7 +98,7 @@ bi_status bi_stream_open(bi_ctx *ctx, const void *a, uint64_t a_limbs, const voi
         return set_error(BI_ELIMB, "buffers must be aligned to %u-bit limbs", limb_bits);
     if (max_descs == 0 || max_descs > (uint64_t(1) << 24))
         return set_error(BI_ESIZE, "max_descs must be in [1, 2^24] (got %llu)", (unsigned long long)max_descs);
-    if (algo < BI_MUL_AUTO || algo > BI_MUL_NTT_PF64) return set_error(BI_EINVAL, "unknown algorithm %d", algo);
+    if (algo < BI_MUL_AUTO || algo > BI_MUL_KARATSUBA) return set_error(BI_EINVAL, "unknown algorithm %d", algo);
     bi::DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return set_error(BI_EHIP, "hipSetDevice: %s", hipGetErrorString(g.err));
 

@@ -9,7 +9,7 @@ from tests import gpu_util as G
 
 pytestmark = pytest.mark.gpu
 
-ALGOS = {"valu": 1, "mfma": 2, "ntt": 3, "ntt64": 4}
+ALGOS = {"valu": 1, "mfma": 2, "ntt": 3, "ntt64": 4, "kara": 5}
 
 
 @pytest.fixture(scope="module")
@@ -125,6 +125,63 @@ def test_all_ones_closed_form(B, ctx, algo):
         assert (got == exp).all()
 
 
+KARA_SIZES = [1000, 1025, 1500, 2048, 2049, 3000, 4096, 4097, 6000, 8191, 8192]
+
+
+def split_halves(x, h):
+    """(low h words, high words zero-padded to h) of each row."""
+    lo = x[:, :h].copy()
+    hi = np.zeros_like(lo)
+    hi[:, : x.shape[1] - h] = x[:, h:]
+    return lo, hi
+
+
+@pytest.mark.parametrize("n", KARA_SIZES)
+def test_karatsuba_signs_and_borrows(B, ctx, orc, n):
+    """Karatsuba's middle term z0 + z2 - s |a0 - a1| |b0 - b1| for every sign
+    case at the top split (a0 < a1, a0 > a1, a0 = a1, for a and b
+    independently), halves equal at every level (repeated blocks), and
+    |a0 - a1| with a borrow through every word (a0 = 2^(32 (h-1)),
+    a1 = 1, and the reverse); sizes with one to three levels and with padded
+    halves."""
+    rng = np.random.default_rng(5000 + n)
+    h = ((n + 1) // 2 + 3) // 4 * 4
+    rows = []
+    base = rand(rng, 1, n)[0]
+
+    def with_halves(lo, hi):
+        x = np.zeros(n, np.uint32)
+        x[:h] = lo
+        x[h:] = hi[: n - h]
+        return x
+
+    lo, hi = split_halves(base[None], h)
+    lo, hi = lo[0], hi[0]
+    big = hi.copy()
+    big[n - h - 1] = 0xFFFFFFFF
+    small = big.copy()
+    small[n - h - 1] = 0xFFFFFFFE
+    cases = {"lt": with_halves(small, big), "gt": with_halves(big, small), "eq": with_halves(hi, hi), "rnd": base}
+    for ka in cases:
+        for kb in cases:
+            rows.append((cases[ka], cases[kb]))
+    # borrow through every word of |a0 - a1|
+    one = np.zeros(h, np.uint32)
+    one[0] = 1
+    topbit = np.zeros(h, np.uint32)
+    topbit[min(h, n - h) - 1] = 1
+    rows.append((with_halves(one, topbit), with_halves(topbit, one)))
+    rows.append((with_halves(topbit, one), with_halves(topbit, one)))
+    # equal halves at every level: one block repeated
+    blk = max(1, n // 8)
+    rep = np.resize(rand(rng, 1, blk)[0], n).astype(np.uint32)
+    rows.append((rep, rep))
+    rows.append((rep, base))
+    a = np.stack([r[0] for r in rows])
+    b = np.stack([r[1] for r in rows])
+    check(orc, a, b, run_mul(B, ctx, a, b, ALGOS["kara"]))
+
+
 def full_size_check(B, ctx, orc, a, b):
     """Every algorithm that runs this size, in the benchmark's launch
     configuration (one uniform bigmul over the whole batch), against the
@@ -205,7 +262,7 @@ def test_autotune_and_auto_dispatch(B, orc):
     c = B.Context(0)
     try:
         algos = B.autotune(c)
-        assert len(algos) == B.NUM_CLASSES and all(a in (1, 2, 3, 4) for a in algos)
+        assert len(algos) == B.NUM_CLASSES and all(a in (1, 2, 3, 4, 5) for a in algos)
         assert B.tune_get(c) == algos
         for q, w in B.tune_get_valu(c):
             assert q in (2, 4) and w in (1, 2, 4, 8, 16), (q, w)

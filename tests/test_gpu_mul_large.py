@@ -87,7 +87,7 @@ def test_repeat_after_smaller(B, ctx, orc):
         check(orc, a, b, run(B, ctx, a, b))
 
 
-@pytest.mark.parametrize("algo", [1, 2, 3, 4])
+@pytest.mark.parametrize("algo", [1, 2, 3, 4, 5])
 def test_block_algorithms(B, ctx, orc, algo):
     """Every algorithm (3: the NTT path; others: block products of that
     algorithm) gives the same product."""

@@ -53,7 +53,7 @@ def _eager_work(B, ctx):
 
 
 @pytest.mark.parametrize("use_graph", [True, False])
-@pytest.mark.parametrize("algo", [0, 1, 3, 4])
+@pytest.mark.parametrize("algo", [0, 1, 3, 4, 5])
 def test_stream_bursts(B, ctx, orc, use_graph, algo):
     count = 120
     A, Bv, d, out_len = _problem(7 + algo, count)
