@@ -180,6 +180,26 @@ bi_status bigmul(bi_ctx *ctx, const void *a, const void *b, void *out,
                  uint32_t n_limbs, uint32_t limb_bits, uint64_t batch, int algo, void *stream);
 
 /*
+ * bigmul_noalloc -- bigmul for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same products, bit-identical, with every scratch buffer
+ * the kernels use (NTT transforms, the large-product MFMA slots, Karatsuba
+ * levels) in one fixed device array of BI_NOALLOC_SCRATCH_BYTES per GPU that
+ * is part of the library's code object and is held until the process ends.
+ * The call makes no device allocation or free.  Batches whose scratch
+ * exceeds the array run in rounds that fit it; BI_ESIZE if a single product
+ * needs more (never at n_limbs * limb_bits <= BI_MAX_BITS).  Arguments,
+ * errors and aliasing rules are bigmul's.  Every call on one GPU, from any
+ * context, stream or host thread, uses that GPU's one array and leaves its
+ * contents behind: calls that overlap in time on one GPU race and must be
+ * ordered by the caller (one stream, or events).
+ */
+#define BI_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+bi_status bigmul_noalloc(bi_ctx *ctx, const void *a, const void *b, void *out, uint32_t n_limbs,
+                         uint32_t limb_bits, uint64_t batch, int algo, void *stream);
+
+/*
  * bi_mul_plan -- what bigmul runs for n_limbs-limb operands with `algo` on
  * this context (host only, no HIP call): the algorithm (BI_MUL_AUTO resolved
  * through the tuning table), and for BI_MUL_KARATSUBA the number of levels,

@@ -32,7 +32,7 @@ EXPORTS = ("bi_ctx_create", "bi_ctx_destroy", "bi_status_str", "bi_last_error",
            "bi_tune_set", "bi_stream_open", "bi_stream_submit", "bi_stream_poll", "bi_stream_wait",
            "bi_stream_close", "bi_fused", "bi_tune_get_valu",
            "bi_tune_set_valu", "bigadd_large", "bigmul_large", "bi_tune_save",
-           "bi_tune_load", "bi_mul_plan")
+           "bi_tune_load", "bi_mul_plan", "bigmul_noalloc")
 NUM_CLASSES = 10
 
 
@@ -78,6 +78,7 @@ def _load():
     L.bi_last_error.restype = ctypes.c_char_p
     L.bigadd.argtypes = [P, P, P, P, P, U32, U32, U64, P]
     L.bigmul.argtypes = [P, P, P, P, U32, U32, U64, I, P]
+    L.bigmul_noalloc.argtypes = [P, P, P, P, U32, U32, U64, I, P]
     L.bigadd_large.argtypes = [P, P, P, P, P, U64, U32, P]
     L.bigmul_large.argtypes = [P, P, P, P, U64, U32, I, U32, P]
     L.bigadd_v.argtypes = [P, P, P, P, P, P, U64, U32, P]
@@ -97,7 +98,7 @@ def _load():
     L.bi_tune_get_valu.argtypes = [P, P, P, U32]
     L.bi_tune_set_valu.argtypes = [P, P, P, U32]
     L.bi_mul_plan.argtypes = [P, U32, U32, I, P]
-    for f in (L.bi_mul_plan, L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field, L.bi_autotune,
+    for f in (L.bi_mul_plan, L.bigmul_noalloc, L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field, L.bi_autotune,
               L.bi_tune_get, L.bi_tune_set, L.bi_stream_open, L.bi_stream_submit, L.bi_stream_poll,
               L.bi_stream_wait, L.bi_stream_close, L.bi_fused, L.bi_tune_get_valu,
               L.bi_tune_set_valu, L.bigadd_large, L.bigmul_large, L.bi_tune_save, L.bi_tune_load):
@@ -237,6 +238,18 @@ def bigmul(ctx, a, b, out, algo=MUL_AUTO, n_limbs=None, limb_bits=None, batch=No
     w, nb = _width(a), n * bt * lb // 8
     _require(("a", a, nb, w), ("b", b, nb, w), ("out", out, 2 * nb, w))
     _check(lib.bigmul(_h(ctx), _ptr(a), _ptr(b), _ptr(out), n, lb, bt, int(algo), _stream(stream, a)))
+    return out
+
+
+def bigmul_noalloc(ctx, a, b, out, algo=MUL_AUTO, n_limbs=None, limb_bits=None, batch=None, stream=None):
+    """bigmul with every scratch buffer in the library's fixed per-GPU array
+    (no device allocation; calls on one GPU must not overlap in time)."""
+    lb = _limb_bits(a, limb_bits)
+    n = n_limbs if n_limbs is not None else a.shape[-1]
+    bt = batch if batch is not None else (a.numel() // n if n else 0)
+    w, nb = _width(a), n * bt * lb // 8
+    _require(("a", a, nb, w), ("b", b, nb, w), ("out", out, 2 * nb, w))
+    _check(lib.bigmul_noalloc(_h(ctx), _ptr(a), _ptr(b), _ptr(out), n, lb, bt, int(algo), _stream(stream, a)))
     return out
 
 

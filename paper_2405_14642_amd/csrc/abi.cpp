@@ -102,6 +102,7 @@ bi_status bi_ctx_create(int device, bi_ctx **out) {
         return hip_fail(g.err, "hipSetDevice");
     }
     bi_status st = bi::ctx_init(c->impl, device, prop);
+    if (st == BI_OK) st = bi::fixed_scratch_init(device, &c->impl.fixed_scratch);
     if (st != BI_OK) {
         bi::ctx_release(c->impl);
         delete c;
@@ -221,25 +222,50 @@ bi_status bigmul_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
     return BI_OK;
 }
 
-bi_status bigmul(bi_ctx *ctx, const void *a, const void *b, void *out, uint32_t n_limbs, uint32_t limb_bits,
-                 uint64_t batch, int algo, void *stream) {
+// bigmul's argument checks; *n32 receives the operands' 32-bit words.
+static bi_status check_bigmul(bi_ctx *ctx, const void *a, const void *b, const void *out, uint32_t n_limbs,
+                              uint32_t limb_bits, uint64_t batch, int algo, uint32_t *n32) {
     uint64_t ib = 0;
     bi_status s = check_shape(n_limbs, limb_bits, batch, &ib);
     if (s != BI_OK) return s;
     if (algo < BI_MUL_AUTO || algo > BI_MUL_KARATSUBA) return fail(BI_EINVAL, "unknown algorithm %d", algo);
-    if (batch == 0) return ctx ? BI_OK : fail(BI_EINVAL, "ctx is NULL");
-    if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
-    if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;
-    if ((s = check_ptr(out, limb_bits, "out")) != BI_OK) return s;
-    const uint64_t tot = ib * batch;
-    if (overlaps(out, 2 * tot, a, tot) || overlaps(out, 2 * tot, b, tot)) return fail(BI_EALIAS, "out overlaps an input");
+    if (batch > 0) {
+        if ((s = check_ptr(a, limb_bits, "a")) != BI_OK) return s;
+        if ((s = check_ptr(b, limb_bits, "b")) != BI_OK) return s;
+        if ((s = check_ptr(out, limb_bits, "out")) != BI_OK) return s;
+        const uint64_t tot = ib * batch;
+        if (overlaps(out, 2 * tot, a, tot) || overlaps(out, 2 * tot, b, tot))
+            return fail(BI_EALIAS, "out overlaps an input");
+    }
     if (!ctx) return fail(BI_EINVAL, "ctx is NULL");
-    DeviceGuard g(ctx->device);
-    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     // The multiplication kernels work on 32-bit limbs; 64-bit limbs are the
     // same byte string with twice as many limbs.
-    const uint32_t n32 = n_limbs * (limb_bits / 32);
+    *n32 = n_limbs * (limb_bits / 32);
+    return BI_OK;
+}
+
+bi_status bigmul(bi_ctx *ctx, const void *a, const void *b, void *out, uint32_t n_limbs, uint32_t limb_bits,
+                 uint64_t batch, int algo, void *stream) {
+    uint32_t n32 = 0;
+    const bi_status s = check_bigmul(ctx, a, b, out, n_limbs, limb_bits, batch, algo, &n32);
+    if (s != BI_OK || batch == 0) return s;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     return bi::dispatch_bigmul(ctx->impl, a, b, out, n32, batch, algo, static_cast<hipStream_t>(stream));
+}
+
+bi_status bigmul_noalloc(bi_ctx *ctx, const void *a, const void *b, void *out, uint32_t n_limbs, uint32_t limb_bits,
+                         uint64_t batch, int algo, void *stream) {
+    uint32_t n32 = 0;
+    const bi_status s = check_bigmul(ctx, a, b, out, n_limbs, limb_bits, batch, algo, &n32);
+    if (s != BI_OK || batch == 0) return s;
+    if (!ctx->impl.fixed_scratch) return fail(BI_EHIP, "the context has no fixed scratch array");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    // every scratch buffer from the fixed array (batches run in rounds that
+    // fit it; BI_ESIZE if one product does not)
+    return bi::dispatch_bigmul(ctx->impl, a, b, out, n32, batch, algo, static_cast<hipStream_t>(stream),
+                               ctx->impl.fixed_scratch, bi::kFixedScratchBytes);
 }
 
 bi_status bi_fused(bi_ctx *ctx, int program, const void *a, const void *b, void *out, uint32_t n_limbs,

@@ -164,7 +164,16 @@ struct Ctx {
     Scratch scratch;
     char arch[64] = {};               // gcnArchName of the device
     int hip_version = 0;              // hipRuntimeGetVersion
+    void *fixed_scratch = nullptr;    // this device's fixed scratch array (bigmul_noalloc)
 };
+
+// The fixed scratch array of bigmul_noalloc: kFixedScratchBytes of device
+// memory per GPU, part of the library's code object.  fixed_scratch_init
+// (with `device` current) returns its device address on that device, looked
+// up once per device.
+constexpr size_t kFixedScratchBytes = size_t(BI_NOALLOC_SCRATCH_BYTES);
+constexpr int kMaxDevices = 64;
+bi_status fixed_scratch_init(int device, void **out);
 
 
 // Returns a device buffer of at least `bytes` owned by the context; growing it
