@@ -239,14 +239,19 @@ def bench_add(args):
     }
 
 
-# Peak rates used for the multiplication rooflines, derived from the unit counts and clock:
-# VALU schoolbook: one v_mad_u64_u32 (16 lanes/clk/SIMD) + one v_addc_co_u32
-# (32 lanes/clk/SIMD) per 32x32-bit product term -> 10.67 terms/clk/SIMD,
-# x 1024 SIMDs x 2.4 GHz.
-VALU_MAC_PEAK = 1024 * (16 * 32 / 48) * 2.4e9   # 2.62e13 u32 MAC/s
+# Peak rates used for the multiplication rooflines: 1024 SIMDs x 2.4 GHz x
+# the lanes per clock and SIMD of each instruction class, as the register-
+# resident issue-rate probe (--workload peaks) measures them on the device:
+# v_mad_u64_u32, v_mul_lo_u32, v_mul_hi_u32 and v_addc_co_u32 (VOP3 with
+# carry) 16 lanes/clk/SIMD (measured 15.0-15.4), plain 32-bit adds,
+# subtracts and min 32 (measured 25.7).
+# VALU schoolbook: one v_mad_u64_u32 + one v_addc_co_u32 per 32x32-bit
+# product term -> 8 terms/clk/SIMD (the probe's fused term: 7.65).
+VALU_MAC_PEAK = 1024 * 8 * 2.4e9                  # 1.97e13 u32 MAC/s
 # NTT: a radix-2 butterfly with a Shoup twiddle is 3 multiply-class
-# (16 lanes/clk/SIMD) + 7 add-class (32 lanes/clk/SIMD) instructions.
-NTT_BFLY_PEAK = 1024 * 2.4e9 / (3 / 16 + 7 / 32)  # 6.05e12 butterflies/s
+# instructions (v_mul_hi_u32, 2 x v_mul_lo_u32) and 9 add-class ones (the
+# add, subtract and min of add_mod, sub_mod and the Shoup correction).
+NTT_BFLY_PEAK = 1024 * 2.4e9 / (3 / 16 + 9 / 32)  # 5.24e12 butterflies/s
 MFMA_I8_PEAK_OPS = 5.0e15                        # dense int8, ops (2 per MAC)
 # PrimeField64 NTT: a butterfly with a 64-bit Montgomery twiddle product is
 # 7 multiply-class instructions (4 for the 64x64 -> 128-bit product, 3 for the
@@ -255,6 +260,29 @@ MFMA_I8_PEAK_OPS = 5.0e15                        # dense int8, ops (2 per MAC)
 NTT64_BFLY_PEAK = 1024 * 2.4e9 / (7 / 16 + 16 / 32)  # 2.62e12 butterflies/s
 
 ALGO_IDS = {"valu": 1, "mfma": 2, "ntt": 3, "ntt64": 4, "kara": 5}
+
+
+def mul_ideal_seconds(ctx, n, algo=0):
+    """Time of one n-word product at the roofline of the algorithm the
+    context runs for it (AUTO: the tuned choice; Karatsuba: its base
+    products)."""
+    import paper_2405_14642_amd as B
+    plan = B.mul_plan(ctx, n, 32, algo)
+    name = {v: k for k, v in ALGO_IDS.items()}[plan["base_algo"]]
+    return 3 ** plan["kara_levels"] * _unit_seconds(name, plan["base_limbs"])
+
+
+def _unit_seconds(name, n):
+    """Seconds of one n-word product by `name` at its peak (the MFMA one
+    against the int8 rate alone)."""
+    if name == "valu":
+        return float(n) * n / VALU_MAC_PEAK
+    if name in ("ntt", "ntt64"):
+        m = 11
+        while (1 << m) < (4 if name == "ntt" else 2) * n:
+            m += 1
+        return 2.0 * 3 * (1 << m) / 2 * m / (NTT_BFLY_PEAK if name == "ntt" else NTT64_BFLY_PEAK)
+    return 2.0 * (4 * n) ** 2 / MFMA_I8_PEAK_OPS
 
 
 def mul_roofline(name, n, batch, us):
@@ -547,6 +575,14 @@ def bench_stream(args):
             o, m = int(off[i]), int(nn[i])
             assert (Oh[r, : 2 * m] == got[2 * o: 2 * o + 2 * m]).all(), ("plain result", int(i))
             checked += 1
+    # roofline of the mixed stream: the sum over pairs of each product's time
+    # at the roofline of its class's tuned algorithm, against the time taken
+    ideal_n = {int(m): mul_ideal_seconds(ctx, int(m)) for m in np.unique(nn)}
+    ideal = float(sum(ideal_n[int(m)] * c for m, c in zip(*np.unique(nn, return_counts=True))))
+    roofline = {"bound": "alu+mfma (per-class tuned algorithm)", "kernel": "whole stream (all class kernels)",
+                "achieved": round(sum_n2 / sat[best] / 1e12, 3), "peak": round(sum_n2 / ideal / 1e12, 3),
+                "unit": "T u32-MAC-equivalents/s (sum of n^2 per second)", "frac": round(ideal / sat[best], 4),
+                "ideal_s": ideal, "traffic": None}
     cpu = None if args.no_cpu else cpu_baseline_stream(args, a, b, off, nn)
     ctx.close()
     return {
@@ -561,7 +597,7 @@ def bench_stream(args):
         "stream": res["stream"], "stream_host_binned": res["stream_host_binned"],
         "plain_per_class_launches": res["plain"],
         "speedup_vs_plain": round(sat["plain"] / sat[best], 3), "cross_checked_vs_plain": checked,
-        "roofline": None, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu,
     }
 
 

@@ -280,8 +280,8 @@ bi_status bigmul_v(bi_ctx *ctx, const void *a, const void *b, void *out,
  * then).  Until tuned, a context uses a built-in table (the choices
  * bi_autotune made on an MI355X).
  *
- * bi_tune_save writes the context's tables (algorithm and VALU schedule per
- * class, the addition schedules) to the text file `path`, keyed by the
+ * bi_tune_save writes the context's tables (algorithm, VALU schedule and
+ * Karatsuba base per class, the addition schedules) to the text file `path`, keyed by the
  * device's architecture name and the HIP runtime version; bi_tune_load reads
  * such a file into the context.  A file written for another architecture or
  * runtime version, a malformed one, or one naming an algorithm or schedule a
@@ -303,6 +303,13 @@ bi_status bi_tune_load(bi_ctx *ctx, const char *path);
  * nothing is changed then). */
 bi_status bi_tune_get_valu(const bi_ctx *ctx, int *q_out, int *waves_out, uint32_t n_out);
 bi_status bi_tune_set_valu(bi_ctx *ctx, const int *q_in, const int *waves_in, uint32_t n_in);
+
+/* The Karatsuba base per class: BI_MUL_KARATSUBA on class k's sizes splits
+ * until the operands have at most base[k] 32-bit words (512, 1024 or 2048;
+ * default 1024); bi_autotune picks it per class.  bi_tune_set_kara replaces
+ * entries 0 .. n_in-1 (BI_EINVAL, nothing changed, for any other value). */
+bi_status bi_tune_get_kara(const bi_ctx *ctx, uint32_t *base_out, uint32_t n_out);
+bi_status bi_tune_set_kara(bi_ctx *ctx, const uint32_t *base_in, uint32_t n_in);
 
 /*
  * Stream mode: a queue of ragged multiplication bursts over caller-owned

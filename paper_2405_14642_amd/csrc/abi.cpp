@@ -353,12 +353,27 @@ bi_status bi_mul_plan(const bi_ctx *ctx, uint32_t n_limbs, uint32_t limb_bits, i
     r.base_limbs = n32;
     r.base_algo = alg;
     if (alg == BI_MUL_KARATSUBA) {
-        const bi::KaraPlan kp = bi::kara_plan(n32, bi::kKaraBase);
+        const bi::KaraPlan kp = bi::kara_plan_tuned(ctx->impl.tune, n32);
         r.kara_levels = kp.levels;
         r.base_limbs = kp.h[kp.levels];
         r.base_algo = bi::kara_base_algo(ctx->impl.tune, r.base_limbs);
     }
     *out = r;
+    return BI_OK;
+}
+
+bi_status bi_tune_get_kara(const bi_ctx *ctx, uint32_t *base_out, uint32_t n_out) {
+    if (!ctx || !base_out) return fail(BI_EINVAL, "NULL argument");
+    for (uint32_t k = 0; k < n_out && k < bi::kNumClasses; ++k) base_out[k] = ctx->impl.tune.kara_base[k];
+    return BI_OK;
+}
+
+bi_status bi_tune_set_kara(bi_ctx *ctx, const uint32_t *base_in, uint32_t n_in) {
+    if (!ctx || !base_in) return fail(BI_EINVAL, "NULL argument");
+    for (uint32_t k = 0; k < n_in && k < bi::kNumClasses; ++k)
+        if (!bi::kara_base_valid(base_in[k]))
+            return fail(BI_EINVAL, "Karatsuba base %u of class %u is not 512, 1024 or 2048", base_in[k], k);
+    for (uint32_t k = 0; k < n_in && k < bi::kNumClasses; ++k) ctx->impl.tune.kara_base[k] = uint16_t(base_in[k]);
     return BI_OK;
 }
 

@@ -97,13 +97,33 @@ bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out) {
         int best_algo = c.tune.mul_algo[k];
         for (int al : algos) {
             if (!algo_supports(al, n)) continue;
-            float us = 0;
-            s = time_us(st, tm, 3, [&]() { return dispatch_bigmul(c, a, b, o, n, batch, al, st); }, &us);
-            if (s != BI_OK) break;
-            if (best == 0 || us < best) {
-                best = us;
-                best_algo = al;
+            // Karatsuba: each base size that gives a different level count;
+            // the class keeps the fastest base (whichever algorithm wins)
+            int last_levels = -1;
+            float kbest = 0;
+            uint16_t kbase = c.tune.kara_base[k];
+            for (uint32_t base : kKaraBases) {
+                if (al != BI_MUL_KARATSUBA && base != kKaraBases[0]) break;
+                if (al == BI_MUL_KARATSUBA) {
+                    const int lv = kara_plan(n, base).levels;
+                    if (lv == last_levels) continue;
+                    last_levels = lv;
+                    c.tune.kara_base[k] = uint16_t(base);
+                }
+                float us = 0;
+                s = time_us(st, tm, 3, [&]() { return dispatch_bigmul(c, a, b, o, n, batch, al, st); }, &us);
+                if (s != BI_OK) break;
+                if (al == BI_MUL_KARATSUBA && (kbest == 0 || us < kbest)) {
+                    kbest = us;
+                    kbase = uint16_t(base);
+                }
+                if (best == 0 || us < best) {
+                    best = us;
+                    best_algo = al;
+                }
             }
+            if (al == BI_MUL_KARATSUBA) c.tune.kara_base[k] = kbase;
+            if (s != BI_OK) break;
         }
         c.tune.mul_algo[k] = best_algo;
     }
@@ -140,16 +160,19 @@ bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out) {
 //   mul_algo <10 algorithm ids>
 //   valu_q <10 values>    valu_nw <10 values>
 //   add_multi <multi2> <multi4> <multi8>
+//   kara_base <10 values>   (version 2; version-1 files leave the default)
 bi_status tune_save(const Ctx &c, const char *path) {
     std::FILE *f = std::fopen(path, "w");
     if (!f) return set_error(BI_EINVAL, "cannot open %s for writing", path);
-    std::fprintf(f, "bigint-tune 1\narch %s\nhip %d\nmul_algo", c.arch, c.hip_version);
+    std::fprintf(f, "bigint-tune 2\narch %s\nhip %d\nmul_algo", c.arch, c.hip_version);
     for (uint32_t k = 0; k < kNumClasses; ++k) std::fprintf(f, " %d", c.tune.mul_algo[k]);
     std::fprintf(f, "\nvalu_q");
     for (uint32_t k = 0; k < kNumClasses; ++k) std::fprintf(f, " %d", int(c.tune.valu_q[k]));
     std::fprintf(f, "\nvalu_nw");
     for (uint32_t k = 0; k < kNumClasses; ++k) std::fprintf(f, " %d", int(c.tune.valu_nw[k]));
-    std::fprintf(f, "\nadd_multi %d %d %d\n", int(c.add.multi2), int(c.add.multi4), int(c.add.multi8));
+    std::fprintf(f, "\nadd_multi %d %d %d\nkara_base", int(c.add.multi2), int(c.add.multi4), int(c.add.multi8));
+    for (uint32_t k = 0; k < kNumClasses; ++k) std::fprintf(f, " %d", int(c.tune.kara_base[k]));
+    std::fprintf(f, "\n");
     const bool ok = std::fclose(f) == 0;
     return ok ? BI_OK : set_error(BI_EINVAL, "writing %s failed", path);
 }
@@ -159,7 +182,7 @@ bi_status tune_load(Ctx &c, const char *path) {
     if (!f) return set_error(BI_EINVAL, "cannot open %s", path);
     char arch[64] = {}, key[32] = {};
     int version = -1, hip = 0;
-    int algo[kNumClasses], q[kNumClasses], nw[kNumClasses], m[3];
+    int algo[kNumClasses], q[kNumClasses], nw[kNumClasses], m[3], kb[kNumClasses];
     // each record opens with its key, compared as a whole token
     auto expect = [&](const char *k) { return std::fscanf(f, "%31s", key) == 1 && std::strcmp(key, k) == 0; };
     auto ints = [&](int *v, uint32_t cnt) {
@@ -167,10 +190,12 @@ bi_status tune_load(Ctx &c, const char *path) {
             if (std::fscanf(f, "%d", &v[i]) != 1) return false;
         return true;
     };
-    bool ok = expect("bigint-tune") && ints(&version, 1) && version == 1 && expect("arch") &&
+    bool ok = expect("bigint-tune") && ints(&version, 1) && (version == 1 || version == 2) && expect("arch") &&
               std::fscanf(f, "%63s", arch) == 1 && expect("hip") && ints(&hip, 1) && expect("mul_algo") &&
               ints(algo, kNumClasses) && expect("valu_q") && ints(q, kNumClasses) && expect("valu_nw") &&
               ints(nw, kNumClasses) && expect("add_multi") && ints(m, 3);
+    for (uint32_t k = 0; k < kNumClasses; ++k) kb[k] = int(kKaraBase);
+    if (ok && version == 2) ok = expect("kara_base") && ints(kb, kNumClasses);
     std::fclose(f);
     if (!ok) return set_error(BI_EINVAL, "%s is not a tuning file", path);
     if (std::strcmp(arch, c.arch) != 0 || hip != c.hip_version)
@@ -181,11 +206,15 @@ bi_status tune_load(Ctx &c, const char *path) {
             return set_error(BI_EINVAL, "%s: algorithm %d cannot run size class %u", path, algo[k], k);
         if (!(q[k] == 0 && nw[k] == 0) && !valu_plan_fits(class_nmax(k), q[k], nw[k], nullptr))
             return set_error(BI_EINVAL, "%s: VALU schedule (%d, %d) does not fit size class %u", path, q[k], nw[k], k);
+        if (!kara_base_valid(uint32_t(kb[k])))
+            return set_error(BI_EINVAL, "%s: Karatsuba base %d of size class %u is not one of 512, 1024, 2048", path,
+                             kb[k], k);
     }
     for (uint32_t k = 0; k < kNumClasses; ++k) {
         c.tune.mul_algo[k] = algo[k];
         c.tune.valu_q[k] = uint8_t(q[k]);
         c.tune.valu_nw[k] = uint8_t(nw[k]);
+        c.tune.kara_base[k] = uint16_t(kb[k]);
     }
     c.add.multi2 = m[0] != 0;
     c.add.multi4 = m[1] != 0;

@@ -30,6 +30,8 @@ struct Tune {
     // and waves per workgroup; 0 = the size rule of valu_plan.
     uint8_t valu_q[kNumClasses];
     uint8_t valu_nw[kNumClasses];
+    // Karatsuba: levels stop at base products of at most kara_base[k] words
+    uint16_t kara_base[kNumClasses];
 };
 bool algo_supports(int algo, uint32_t n32);
 // The algorithm bigmul runs for `algo` at n32 words: BI_MUL_AUTO resolves to
@@ -319,14 +321,22 @@ hipError_t launch_bigmul_list_algo(const Ctx &c, const Tune &tune, const ListIns
 // one level).  The base algorithm is the tuned one of the last level's size
 // class (the MFMA schoolbook if that is Karatsuba itself).
 constexpr int kKaraMaxLevels = 4;
-constexpr uint32_t kKaraBase = 1024;       // base products of at most 2^15 bits
-constexpr uint64_t kKaraListRound = 64;    // ragged instances per round of levels
+constexpr uint32_t kKaraBase = 1024;       // default base: products of at most 2^15 bits
+constexpr uint32_t kKaraBases[] = {512, 1024, 2048};  // the base sizes tuning chooses from
+inline bool kara_base_valid(uint32_t b) {
+    for (uint32_t v : kKaraBases)
+        if (b == v) return true;
+    return false;
+}
+constexpr uint64_t kKaraListRound = 1024;  // ragged instances per round of levels
 constexpr size_t kKaraScratchBudget = size_t(256) << 20;  // uniform batches: scratch per round
 struct KaraPlan {
     int levels = 0;
     uint32_t h[kKaraMaxLevels + 1] = {};
 };
 KaraPlan kara_plan(uint32_t n32, uint32_t base);
+// The plan of the size class of n32 words under `tune`.
+KaraPlan kara_plan_tuned(const Tune &tune, uint32_t n32);
 int kara_base_algo(const Tune &tune, uint32_t h);
 // Scratch of one round of R top-level instances (list: ragged rounds, which
 // also publish the base products as a descriptor list), plus base_bytes for

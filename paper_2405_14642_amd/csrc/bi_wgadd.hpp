@@ -75,6 +75,65 @@ __device__ __forceinline__ uint32_t wg_add_rows_sink(const Src &src, const Sink 
     return total;
 }
 
+// The same addition with the addends already in registers: wave w owns rows
+// w R .. w R + R - 1 (row r = chunks 64 r .. 64 r + 63), and lane l holds
+// x[i], y[i] for chunk 64 (w R + i) + l (zero at or beyond nwords).  The
+// chunk sums stay in registers between the two halves, so there is one
+// barrier and no recomputation; NW R rows must cover nwords.  cin0 (0 or 1)
+// is a carry into word 0.  Returns the carry out of the whole sum when
+// nwords is a multiple of 4.  Every thread of the workgroup must call it.
+template <int NW, int R, class Sink>
+__device__ __forceinline__ uint32_t wg_add_regs(const uint32_t (&x)[R][4], const uint32_t (&y)[R][4],
+                                                uint32_t nwords, const Sink &sink, uint32_t *summary /* NW words */,
+                                                uint32_t cin0 = 0) {
+    const uint32_t lane = lane_id();
+    const uint32_t w = wave_in_block();
+    const uint32_t nchunks = (nwords + 3) / 4;
+    uint32_t s[R][4];
+    uint64_t G[R], P[R];
+    uint32_t valid[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint32_t r = w * R + uint32_t(i);
+        const uint32_t c = 64 * r + lane;
+        valid[i] = nchunks > 64 * r ? min(nchunks - 64 * r, 64u) : 0u;
+        const uint32_t g = add_words<4>(x[i], y[i], s[i]);
+        G[i] = ballot(c < nchunks && g);
+        P[i] = ballot(c < nchunks && all_ones<4>(s[i]));
+    }
+    // carry out of this wave's rows with carry-in 0 (cin0 for wave 0), and
+    // whether every valid chunk propagates
+    uint32_t cin = w == 0 ? cin0 : 0, allp = 1;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const WaveCarry wc = wave_carry(G[i], P[i], cin);
+        const uint32_t v = valid[i];
+        const uint64_t vmask = v >= 64 ? ~0ull : ((1ull << v) - 1);
+        cin = v >= 64 ? wc.out : uint32_t(wc.into >> v) & 1u;
+        allp &= (P[i] == vmask) ? 1u : 0u;
+    }
+    if (lane == 0) summary[w] = cin | (allp << 1);
+    __syncthreads();
+    cin = 0;
+    uint32_t total = 0;
+    for (uint32_t v = 0; v < uint32_t(NW); ++v) {
+        const uint32_t sv = summary[v];
+        if (v < w) cin = (sv & 1u) | ((sv >> 1) & cin);
+        total = (sv & 1u) | ((sv >> 1) & total);
+    }
+    if (w == 0) cin = cin0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint32_t c = 64 * (w * R + uint32_t(i)) + lane;
+        const WaveCarry wc = wave_carry(G[i], P[i], cin);
+        add_carry_words<4>(s[i], uint32_t(wc.into >> lane) & 1u);
+        const uint32_t v = valid[i];
+        cin = v >= 64 ? wc.out : uint32_t(wc.into >> v) & 1u;
+        if (c < nchunks) sink(c, s[i]);
+    }
+    return total;
+}
+
 // Global-memory sink for wg_add_rows: words >= nwords are dropped.
 struct GlobalSink {
     uint32_t *out;

@@ -13,25 +13,28 @@
 // middle term a0 b1 + a1 b0 is never negative).  Levels repeat the split on
 // all three products until the operands have at most `base` words; the
 // 3^levels products of the last level form one batch for the base algorithm,
-// so a pair costs 3^levels base products instead of 4^levels.
+// so a pair costs 3^levels base products instead of 4^levels.  In a ragged
+// batch every instance keeps its own sizes at every level (h follows its own
+// n), so the work follows the instance, not the size class's largest.
 //
-// Memory, per top-level instance: level j (1 .. levels) holds 3^j operands of
-// h_j words for a and for b (children 3 q, 3 q + 1, 3 q + 2 of parent q are
-// x0, x1 and |x0 - x1|), their products (2 h_j words each) and one sign byte
-// per parent and operand.
-//   kara_split_kernel    one workgroup per (parent, operand): stages the
-//                        parent's words [0, 2 h) (zero beyond its length) in
-//                        LDS and writes them out as x0 | x1, finds the highest
-//                        word where x0 and x1 differ (the sign), and writes
-//                        |x0 - x1| = big + ~small + 1 with the workgroup
-//                        ballot adder.
+// Memory, per top-level instance: level j (1 .. levels) holds 3^j operand
+// slots of hmax_j words (the level size of the batch's largest instance) for
+// a and for b (children 3 q, 3 q + 1, 3 q + 2 of parent q are x0, x1 and
+// |x0 - x1|), their products (2 hmax_j words each) and one sign byte per
+// parent and operand.  Both kernels keep their data in registers, one 4-word
+// chunk per lane and row, and add with the workgroup ballot adder after a
+// single barrier:
+//   kara_split_kernel    one workgroup per (parent, operand): loads x0 and
+//                        x1, stores them as the first two children, and
+//                        forms x0 + ~x1 + 1 and x1 + ~x0 + 1 together; the
+//                        carry out of the first (x0 >= x1) picks |x0 - x1|
+//                        and gives the sign.
 //   kara_combine_kernel  one workgroup per parent: the biased column sum
 //                        V_k = (the five terms above at word k) + 2^63 -
 //                        2^31 [k > 0] is unsigned, and the biases sum to
 //                        2^31 2^(32 W), beyond the W result words; the low
-//                        words of all V_k and their high words are staged
-//                        in LDS, and the ballot adder writes
-//                        sum_k lo(V_k) 2^(32 k) + hi(V_k) 2^(32 (k+1)).
+//                        word of V_k and the high word of V_(k-1) are the
+//                        two addends at word k.
 #include <algorithm>
 #include <atomic>
 
@@ -43,6 +46,8 @@ namespace bi {
 
 namespace {
 
+__host__ __device__ inline uint32_t kara_half(uint32_t n) { return ((n + 1) / 2 + 3) & ~3u; }
+
 // Instance count of a launch: a host value, or a device word times a factor
 // (ragged lists, whose counts are known only on the device).
 struct CountRef {
@@ -51,16 +56,25 @@ struct CountRef {
     __device__ __forceinline__ uint64_t get() const { return ptr ? uint64_t(*ptr) * mult : host; }
 };
 
-// Operands of a level below the top: instance q at a + q n and b + q n; its
-// product at c + 2 q n.
+// Operands of level j >= 1: instance q in slots of `stride` words at a and b
+// (product at c, 2 stride words per slot).  Its size is `stride` (uniform
+// batch), or for a ragged one the level-j size of its top-level instance
+// q / 3^j, whose size top_n holds.
 struct LevelInst {
     const uint32_t *a, *b;
     uint32_t *c;
-    uint32_t n;
+    uint32_t stride, j;
+    const uint32_t *top_n;
+    uint64_t div;  // 3^j
     CountRef cnt;
     __device__ __forceinline__ uint64_t count() const { return cnt.get(); }
     __device__ __forceinline__ InstRef get(uint64_t q) const {
-        return InstRef{a + q * n, b + q * n, c + q * 2 * n, n};
+        uint32_t n = stride;
+        if (top_n) {
+            n = top_n[q / div];
+            for (uint32_t i = 0; i < j; ++i) n = kara_half(n);
+        }
+        return InstRef{a + q * stride, b + q * stride, c + q * 2 * stride, n};
     }
 };
 
@@ -85,13 +99,29 @@ struct BaseList {
 
 __device__ __forceinline__ uint4 ld4(const uint32_t *p) { return *reinterpret_cast<const uint4 *>(p); }
 
-template <int NW, class Src>
-__global__ __launch_bounds__(NW * 64) void kara_split_kernel(Src src, uint32_t h, uint32_t *__restrict__ xa,
+// Words k .. k+3 of x (n words, zero beyond).
+__device__ __forceinline__ void load_chunk(const uint32_t *x, uint32_t n, uint32_t k, bool vec, uint32_t (&v)[4]) {
+    if (vec && k + 4 <= n) {
+        const uint4 t = ld4(x + k);
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = k + uint32_t(t) < n ? x[k + t] : 0u;
+    }
+}
+
+__device__ __forceinline__ void store_chunk(uint32_t *p, const uint32_t (&v)[4]) {
+    *reinterpret_cast<uint4 *>(p) = make_uint4(v[0], v[1], v[2], v[3]);
+}
+
+// Parent q of src (n words, split at h = kara_half(n)) into child slots of
+// hs words at xa / xb + 3 q hs.  Wave w holds rows w R .. w R + R - 1 of the
+// h-word halves (4 words per lane and row).
+template <int NW, int R, class Src>
+__global__ __launch_bounds__(NW * 64) void kara_split_kernel(Src src, uint32_t hs, uint32_t *__restrict__ xa,
                                                                uint32_t *__restrict__ xb, uint8_t *__restrict__ sg,
-                                                               uint32_t *cnt_out, BaseList bl) {
-    extern __shared__ __align__(16) uint32_t sh[];  // 2 h staged words, then NW summary words
-    __shared__ uint32_t top;
-    constexpr uint32_t T = NW * 64;
+                                                               uint32_t *cnt_out, uint32_t *n_out, BaseList bl) {
+    __shared__ uint32_t summary[NW];
     const uint64_t cnt = src.count();
     const uint64_t q = blockIdx.x;
     const uint32_t op = blockIdx.y;
@@ -101,99 +131,141 @@ __global__ __launch_bounds__(NW * 64) void kara_split_kernel(Src src, uint32_t h
     }
     if (q >= cnt) return;  // uniform across the workgroup
     const InstRef in = src.get(q);
-    const uint32_t *x = op ? in.b : in.a;
-    const uint32_t n = in.n;
-    uint32_t *dst = (op ? xb : xa) + 3 * q * h;
-    // x0 | x1 = the parent's words [0, 2 h), zero beyond its length: U
-    // 16-byte groups per thread loaded before any is stored, so several
-    // loads are in flight
-    const bool vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
-    const uint32_t ng = h / 2;  // 16-byte groups in 2 h words
-    constexpr int U = 4;
-    for (uint32_t g0 = threadIdx.x; g0 < ng; g0 += U * T) {
-        uint4 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t w = 4 * (g0 + u * T);
-            if (vec && w + 4 <= n) {
-                v[u] = ld4(x + w);
-            } else {
-                v[u].x = w < n ? x[w] : 0u;
-                v[u].y = w + 1 < n ? x[w + 1] : 0u;
-                v[u].z = w + 2 < n ? x[w + 2] : 0u;
-                v[u].w = w + 3 < n ? x[w + 3] : 0u;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t g = g0 + u * T;
-            if (g < ng) {
-                *reinterpret_cast<uint4 *>(sh + 4 * g) = v[u];
-                *reinterpret_cast<uint4 *>(dst + 4 * g) = v[u];
-            }
-        }
-    }
-    if (threadIdx.x == 0) top = 0;
-    __syncthreads();
-    uint32_t hi = 0;  // 1 + the highest word index where x0 and x1 differ (0: none)
-    for (uint32_t w = threadIdx.x; w < h; w += T)
-        if (sh[w] != sh[h + w]) hi = w + 1;
-    if (hi) atomicMax(&top, hi);
-    __syncthreads();
-    const uint32_t t = top;
-    const uint32_t less = t && sh[t - 1] < sh[h + t - 1] ? 1u : 0u;  // x0 < x1
-    if (threadIdx.x == 0) sg[2 * q + op] = uint8_t(less);
+    const uint32_t n = in.n, h = kara_half(n), nchunks = h / 4;
+    if (n_out && op == 0 && threadIdx.x == 0) n_out[q] = n;
     if (bl.desc && op == 0 && threadIdx.x < 3) {
         const uint64_t child = 3 * q + threadIdx.x;
         bi_desc d;
-        d.a_off = child * h;
-        d.b_off = child * h;
-        d.out_off = child * 2 * h;
+        d.a_off = child * hs;
+        d.b_off = child * hs;
+        d.out_off = child * 2 * hs;
         d.n_limbs = h;
         d.reserved = 0;
         bl.desc[child] = d;
         bl.list[child] = uint32_t(child);
     }
-    // |x0 - x1| = big + ~small + 1 mod 2^(32 h); h is a multiple of 4
-    const uint32_t *big = sh + (less ? h : 0), *small = sh + (less ? 0 : h);
-    auto terms = [&](uint32_t c, uint32_t (&u)[4], uint32_t (&v)[4]) {
-        const uint4 bb = ld4(big + 4 * c), ss = ld4(small + 4 * c);
-        u[0] = bb.x; u[1] = bb.y; u[2] = bb.z; u[3] = bb.w;
-        v[0] = ~ss.x; v[1] = ~ss.y; v[2] = ~ss.z; v[3] = ~ss.w;
-    };
-    uint32_t *dd = dst + 2 * h;
-    const GlobalSink sink{dd, h, (reinterpret_cast<uintptr_t>(dd) & 15) == 0};
-    (void)wg_add_rows_sink<NW>(terms, sink, h, sh + 2 * h, 1u);
+    const uint32_t *x = op ? in.b : in.a;
+    uint32_t *dst = (op ? xb : xa) + 3 * q * hs;
+    const uint32_t lane = lane_id(), w = wave_in_block();
+    const bool vec = (reinterpret_cast<uintptr_t>(x) & 15) == 0;  // h is a multiple of 4
+    uint32_t lo[R][4], hi[R][4];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint32_t k = 4 * (64 * (w * R + uint32_t(i)) + lane);
+        if (k < h) {
+            load_chunk(x, n, k, vec, lo[i]);
+            load_chunk(x, n, h + k, vec, hi[i]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) lo[i][t] = hi[i][t] = 0;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint32_t k = 4 * (64 * (w * R + uint32_t(i)) + lane);
+        if (k < h) {
+            store_chunk(dst + k, lo[i]);
+            store_chunk(dst + hs + k, hi[i]);
+        }
+    }
+    // d1 = x0 + ~x1 + 1 and d2 = x1 + ~x0 + 1 (mod 2^(32 h)), side by side
+    uint32_t s1[R][4], s2[R][4], valid[R];
+    uint64_t G1[R], P1[R], G2[R], P2[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint32_t r = w * R + uint32_t(i), c = 64 * r + lane;
+        const bool in_range = c < nchunks;
+        valid[i] = nchunks > 64 * r ? min(nchunks - 64 * r, 64u) : 0u;
+        uint32_t nhi[4], nlo[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            nhi[t] = in_range ? ~hi[i][t] : 0u;
+            nlo[t] = in_range ? ~lo[i][t] : 0u;
+        }
+        const uint32_t g1 = add_words<4>(lo[i], nhi, s1[i]);
+        const uint32_t g2 = add_words<4>(hi[i], nlo, s2[i]);
+        G1[i] = ballot(in_range && g1);
+        P1[i] = ballot(in_range && all_ones<4>(s1[i]));
+        G2[i] = ballot(in_range && g2);
+        P2[i] = ballot(in_range && all_ones<4>(s2[i]));
+    }
+    uint32_t c1 = w == 0 ? 1u : 0u, c2 = c1, p1 = 1, p2 = 1;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint32_t v = valid[i];
+        const uint64_t vmask = v >= 64 ? ~0ull : ((1ull << v) - 1);
+        const WaveCarry w1 = wave_carry(G1[i], P1[i], c1), w2 = wave_carry(G2[i], P2[i], c2);
+        c1 = v >= 64 ? w1.out : uint32_t(w1.into >> v) & 1u;
+        c2 = v >= 64 ? w2.out : uint32_t(w2.into >> v) & 1u;
+        p1 &= P1[i] == vmask ? 1u : 0u;
+        p2 &= P2[i] == vmask ? 1u : 0u;
+    }
+    if (lane == 0) summary[w] = c1 | (p1 << 1) | (c2 << 2) | (p2 << 3);
+    __syncthreads();
+    uint32_t in1 = 0, in2 = 0, t1 = 0;
+    for (uint32_t v = 0; v < uint32_t(NW); ++v) {
+        const uint32_t sv = summary[v];
+        if (v < w) {
+            in1 = (sv & 1u) | ((sv >> 1) & in1);
+            in2 = ((sv >> 2) & 1u) | ((sv >> 3) & in2);
+        }
+        t1 = (sv & 1u) | ((sv >> 1) & t1);
+    }
+    if (w == 0) in1 = in2 = 1;
+    const bool ge = t1 != 0;  // no borrow out of x0 - x1: x0 >= x1
+    if (threadIdx.x == 0) sg[2 * q + op] = uint8_t(ge ? 0 : 1);
+    uint32_t cin = ge ? in1 : in2;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint32_t c = 64 * (w * R + uint32_t(i)) + lane;
+        const WaveCarry wc = ge ? wave_carry(G1[i], P1[i], cin) : wave_carry(G2[i], P2[i], cin);
+        uint32_t d[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) d[t] = ge ? s1[i][t] : s2[i][t];
+        add_carry_words<4>(d, uint32_t(wc.into >> lane) & 1u);
+        const uint32_t v = valid[i];
+        cin = v >= 64 ? wc.out : uint32_t(wc.into >> v) & 1u;
+        if (c < nchunks) store_chunk(dst + 2 * hs + 4 * c, d);
+    }
 }
 
-// Parent q of Dst (result words 2 n at c) from its children's products at
-// z + 3 q (2 h) (z0, z2, D in that order) and the sign bytes sg[2 q], sg[2 q + 1].
-// The column sums of every word go to LDS first (low words at Ls[k], high
-// words at Hs[k]; 4 h words each), then the ballot adder adds Ls + Hs
-// shifted by one word.
-template <int NW, class Dst>
+// Parent q of Dst (n words; result 2 n words at c) from its children's
+// products in slots of 2 hs words at z + 3 q (2 hs) (z0, z2, D in that order;
+// the children have h = kara_half(n) words) and the sign bytes sg[2 q],
+// sg[2 q + 1].  Wave w holds rows w R .. w R + R - 1 of the result.
+template <int NW, int R, class Dst>
 __global__ __launch_bounds__(NW * 64) void kara_combine_kernel(Dst dst, const uint32_t *__restrict__ z,
-                                                                 const uint8_t *__restrict__ sg, uint32_t h) {
-    extern __shared__ __align__(16) uint32_t sh[];  // Ls (4 h), Hs (4 h), NW summary words
-    constexpr uint32_t T = NW * 64;
+                                                                 const uint8_t *__restrict__ sg, uint32_t hs) {
+    __shared__ uint32_t summary[NW];
     const uint64_t q = blockIdx.x;
     if (q >= dst.count()) return;
     const InstRef o = dst.get(q);
-    const uint32_t W = 2 * o.n;  // result words, at most 4 h
-    const uint32_t *z0 = z + 3 * q * 2 * h, *z2 = z0 + 2 * h, *dv = z2 + 2 * h;
+    const uint32_t W = 2 * o.n, h = kara_half(o.n);  // W <= 4 h
+    const uint32_t *z0 = z + 3 * q * 2 * hs, *z2 = z0 + 2 * hs, *dv = z2 + 2 * hs;
     const bool sub = sg[2 * q] == sg[2 * q + 1];
-    uint32_t *Ls = sh, *Hs = sh + 4 * h, *summary = sh + 8 * h;
+    const uint32_t lane = lane_id(), w = wave_in_block();
     constexpr uint64_t kBias = uint64_t(1) << 63;
-    const uint32_t nchunks = (W + 3) / 4;
-    constexpr int U = 2;
-    for (uint32_t c0 = threadIdx.x; c0 < nchunks; c0 += U * T) {
+    // V_k for one word (the word below a lane-0 chunk)
+    auto col = [&](uint32_t k) -> uint64_t {
+        uint64_t v = kBias - (k > 0 ? (uint64_t(1) << 31) : 0) + (k < 2 * h ? z0[k] : z2[k - 2 * h]);
+        if (k >= h && k < 3 * h) {
+            const uint32_t m = k - h;
+            v += uint64_t(z0[m]) + z2[m];
+            v = sub ? v - dv[m] : v + dv[m];
+        }
+        return v;
+    };
+    uint32_t xs[R][4], ys[R][4];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t c = c0 + u * T;
-            if (c >= nchunks) break;
-            const uint32_t k0 = 4 * c;  // < 4 h; h is a multiple of 4, so the chunk lies in one region
+    for (int i = 0; i < R; ++i) {
+        const uint32_t k0 = 4 * (64 * (w * R + uint32_t(i)) + lane);
+        uint64_t V[4] = {0, 0, 0, 0};
+        if (k0 < W) {  // k0 + 3 < 4 h; h is a multiple of 4, so the chunk lies in one region
             const uint4 A = k0 < 2 * h ? ld4(z0 + k0) : ld4(z2 + (k0 - 2 * h));
-            uint64_t V[4] = {kBias + A.x, kBias + A.y, kBias + A.z, kBias + A.w};
+            V[0] = kBias + A.x;
+            V[1] = kBias + A.y;
+            V[2] = kBias + A.z;
+            V[3] = kBias + A.w;
 #pragma unroll
             for (int t = 0; t < 4; ++t)
                 if (k0 + t > 0) V[t] -= uint64_t(1) << 31;
@@ -210,81 +282,75 @@ __global__ __launch_bounds__(NW * 64) void kara_combine_kernel(Dst dst, const ui
                     V[0] += Dd.x; V[1] += Dd.y; V[2] += Dd.z; V[3] += Dd.w;
                 }
             }
-            *reinterpret_cast<uint4 *>(Ls + k0) =
-                make_uint4(uint32_t(V[0]), uint32_t(V[1]), uint32_t(V[2]), uint32_t(V[3]));
-            *reinterpret_cast<uint4 *>(Hs + k0) = make_uint4(uint32_t(V[0] >> 32), uint32_t(V[1] >> 32),
-                                                             uint32_t(V[2] >> 32), uint32_t(V[3] >> 32));
         }
-    }
-    __syncthreads();
-    auto terms = [&](uint32_t c, uint32_t (&x)[4], uint32_t (&y)[4]) {
-        const uint32_t k0 = 4 * c;
-        const uint4 l = ld4(Ls + k0);
-        x[0] = l.x; x[1] = l.y; x[2] = l.z; x[3] = l.w;
+        // high word of V_(k0 - 1): the lane below, or recomputed at lane 0
+        uint32_t below = __shfl_up(uint32_t(V[3] >> 32), 1);
+        if (lane == 0) below = k0 > 0 && k0 < W ? uint32_t(col(k0 - 1) >> 32) : 0u;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const uint32_t k = k0 + t;
-            if (k >= W) x[t] = 0;
-            y[t] = k > 0 && k < W ? Hs[k - 1] : 0u;
+            const bool in = k0 + uint32_t(t) < W;
+            xs[i][t] = in ? uint32_t(V[t]) : 0u;
+            const uint32_t prev = t == 0 ? below : uint32_t(V[t - 1] >> 32);
+            ys[i][t] = in && k0 + uint32_t(t) > 0 ? prev : 0u;
         }
-    };
-    const GlobalSink sink{o.c, W, (reinterpret_cast<uintptr_t>(o.c) & 15) == 0};
-    (void)wg_add_rows_sink<NW>(terms, sink, W, summary);
-}
-
-// Waves per workgroup for an addition of `words` words: one row of 256 words
-// per wave, 1 to 16 waves.
-int kara_waves(uint32_t words) {
-    const uint32_t rows = (words + 255) / 256;
-    return rows >= 16 ? 16 : rows >= 8 ? 8 : rows >= 4 ? 4 : rows >= 2 ? 2 : 1;
-}
-
-template <int NW, class Src>
-hipError_t launch_split_nw(const Src &src, uint64_t grid, uint32_t h, uint32_t *xa, uint32_t *xb, uint8_t *sg,
-                           uint32_t *cnt_out, const BaseList &bl, hipStream_t st) {
-    const size_t lds = sizeof(uint32_t) * (2 * size_t(h) + NW);
-    hipLaunchKernelGGL((kara_split_kernel<NW, Src>), dim3(uint32_t(grid), 2), dim3(NW * 64), lds, st, src, h, xa, xb,
-                       sg, cnt_out, bl);
-    return hipGetLastError();
-}
-
-// Split of `grid` parents into children of h words (the subtraction adds h words).
-template <class Src>
-hipError_t launch_split(const Src &src, uint64_t grid, uint32_t h, uint32_t *xa, uint32_t *xb, uint8_t *sg,
-                        uint32_t *cnt_out, const BaseList &bl, hipStream_t st) {
-    if (grid == 0) return hipSuccess;
-    switch (kara_waves(h)) {
-        case 16: return launch_split_nw<16>(src, grid, h, xa, xb, sg, cnt_out, bl, st);
-        case 8: return launch_split_nw<8>(src, grid, h, xa, xb, sg, cnt_out, bl, st);
-        case 4: return launch_split_nw<4>(src, grid, h, xa, xb, sg, cnt_out, bl, st);
-        case 2: return launch_split_nw<2>(src, grid, h, xa, xb, sg, cnt_out, bl, st);
-        default: return launch_split_nw<1>(src, grid, h, xa, xb, sg, cnt_out, bl, st);
     }
+    const GlobalSink sink{o.c, W, (reinterpret_cast<uintptr_t>(o.c) & 15) == 0};
+    (void)wg_add_regs<NW, R>(xs, ys, W, sink, summary);
 }
 
-template <int NW, class Dst>
-hipError_t launch_combine_nw(const Dst &dst, uint64_t grid, const uint32_t *z, const uint8_t *sg, uint32_t h,
-                             hipStream_t st) {
-    const size_t lds = sizeof(uint32_t) * (8 * size_t(h) + NW);
-    static std::atomic<uint64_t> lds_set{0};  // up to 128 KiB at 4096-word children
-    const hipError_t e = lds_limit_once(reinterpret_cast<const void *>(&kara_combine_kernel<NW, Dst>), lds_set);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((kara_combine_kernel<NW, Dst>), dim3(uint32_t(grid)), dim3(NW * 64), lds, st, dst, z, sg, h);
+// (waves, rows per wave) for an addition over `words` words: rows of 256
+// words, one per wave up to 16 waves, then 2 or 4 per wave.
+struct Shape {
+    int nw, r;
+};
+Shape kara_shape(uint32_t words) {
+    const uint32_t rows = (words + 255) / 256;
+    if (rows > 32) return {16, 4};
+    if (rows > 16) return {16, 2};
+    return {rows > 8 ? 16 : rows > 4 ? 8 : rows > 2 ? 4 : rows > 1 ? 2 : 1, 1};
+}
+
+template <int NW, int R, class Src>
+hipError_t launch_split_shape(const Src &src, uint64_t grid, uint32_t hs, uint32_t *xa, uint32_t *xb, uint8_t *sg,
+                              uint32_t *cnt_out, uint32_t *n_out, const BaseList &bl, hipStream_t st) {
+    hipLaunchKernelGGL((kara_split_kernel<NW, R, Src>), dim3(uint32_t(grid), 2), dim3(NW * 64), 0, st, src, hs, xa, xb,
+                       sg, cnt_out, n_out, bl);
     return hipGetLastError();
 }
 
-// Combine of `grid` parents of nparent words from children of h words.
+// Split of `grid` parents into child slots of hs words (the largest child).
+template <class Src>
+hipError_t launch_split(const Src &src, uint64_t grid, uint32_t hs, uint32_t *xa, uint32_t *xb, uint8_t *sg,
+                        uint32_t *cnt_out, uint32_t *n_out, const BaseList &bl, hipStream_t st) {
+    if (grid == 0) return hipSuccess;
+    const Shape sh = kara_shape(hs);
+#define BI_KARA_SPLIT(NW_, R_) \
+    if (sh.nw == NW_ && sh.r == R_) return launch_split_shape<NW_, R_>(src, grid, hs, xa, xb, sg, cnt_out, n_out, bl, st);
+    BI_KARA_SPLIT(1, 1) BI_KARA_SPLIT(2, 1) BI_KARA_SPLIT(4, 1) BI_KARA_SPLIT(8, 1) BI_KARA_SPLIT(16, 1)
+    BI_KARA_SPLIT(16, 2) BI_KARA_SPLIT(16, 4)
+#undef BI_KARA_SPLIT
+    return hipErrorInvalidValue;
+}
+
+template <int NW, int R, class Dst>
+hipError_t launch_combine_shape(const Dst &dst, uint64_t grid, const uint32_t *z, const uint8_t *sg, uint32_t hs,
+                                hipStream_t st) {
+    hipLaunchKernelGGL((kara_combine_kernel<NW, R, Dst>), dim3(uint32_t(grid)), dim3(NW * 64), 0, st, dst, z, sg, hs);
+    return hipGetLastError();
+}
+
+// Combine of `grid` parents of at most nparent words from child slots of hs words.
 template <class Dst>
 hipError_t launch_combine(const Dst &dst, uint32_t nparent, uint64_t grid, const uint32_t *z, const uint8_t *sg,
-                          uint32_t h, hipStream_t st) {
+                          uint32_t hs, hipStream_t st) {
     if (grid == 0) return hipSuccess;
-    switch (kara_waves(2 * nparent)) {
-        case 16: return launch_combine_nw<16>(dst, grid, z, sg, h, st);
-        case 8: return launch_combine_nw<8>(dst, grid, z, sg, h, st);
-        case 4: return launch_combine_nw<4>(dst, grid, z, sg, h, st);
-        case 2: return launch_combine_nw<2>(dst, grid, z, sg, h, st);
-        default: return launch_combine_nw<1>(dst, grid, z, sg, h, st);
-    }
+    const Shape sh = kara_shape(2 * nparent);
+#define BI_KARA_COMBINE(NW_, R_) \
+    if (sh.nw == NW_ && sh.r == R_) return launch_combine_shape<NW_, R_>(dst, grid, z, sg, hs, st);
+    BI_KARA_COMBINE(1, 1) BI_KARA_COMBINE(2, 1) BI_KARA_COMBINE(4, 1) BI_KARA_COMBINE(8, 1) BI_KARA_COMBINE(16, 1)
+    BI_KARA_COMBINE(16, 2) BI_KARA_COMBINE(16, 4)
+#undef BI_KARA_COMBINE
+    return hipErrorInvalidValue;
 }
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -296,11 +362,11 @@ uint64_t pow3(int j) {
 }
 
 // Scratch of a round of R top-level instances: per level the operands, the
-// products and the sign bytes; for ragged rounds the base list and the
-// counts; then the base algorithm's own scratch.
+// products and the sign bytes; for ragged rounds the top-level sizes, the
+// base list and the counts; then the base algorithm's own scratch.
 struct KaraLayout {
     size_t xa[kKaraMaxLevels + 1], xb[kKaraMaxLevels + 1], z[kKaraMaxLevels + 1], sg[kKaraMaxLevels + 1];
-    size_t desc, list, counts, base, total;
+    size_t topn, desc, list, counts, base, total;
 };
 
 KaraLayout kara_layout(const KaraPlan &p, uint64_t R, bool list, size_t base_bytes) {
@@ -318,6 +384,8 @@ KaraLayout kara_layout(const KaraPlan &p, uint64_t R, bool list, size_t base_byt
         off = al256(off + 2 * (cj / 3));
     }
     const uint64_t cl = R * pow3(p.levels);
+    l.topn = off;
+    if (list) off = al256(off + 4 * R);
     l.desc = off;
     if (list) off = al256(off + sizeof(bi_desc) * cl);
     l.list = off;
@@ -336,7 +404,7 @@ KaraPlan kara_plan(uint32_t n32, uint32_t base) {
     p.h[0] = n32;
     uint32_t h = n32;
     do {
-        h = ((h + 1) / 2 + 3) & ~3u;
+        h = kara_half(h);
         p.h[++p.levels] = h;
     } while (h > base && p.levels < kKaraMaxLevels);
     return p;
@@ -360,15 +428,20 @@ static bi_status kara_run(const Top &top, uint64_t grid0, const KaraPlan &p, uin
     auto cref = [&](int j) {
         return list ? CountRef{counts, pow3(j), 0} : CountRef{nullptr, 1, grid0 * pow3(j)};
     };
+    // ragged rounds: every instance's own sizes, from its top-level size
+    uint32_t *top_n = list ? P(l.topn) : nullptr;
+    auto level = [&](uint32_t *a, uint32_t *b, uint32_t *c, int j) {
+        return LevelInst{a, b, c, p.h[j], uint32_t(j), top_n, pow3(j), cref(j)};
+    };
     hipError_t e = hipSuccess;
     for (int j = 0; j < p.levels && e == hipSuccess; ++j) {
         const BaseList &b = (list && j + 1 == p.levels) ? bl : none;
         uint8_t *sg = scr + l.sg[j + 1];
         if (j == 0)
-            e = launch_split(top, grid0, p.h[1], P(l.xa[1]), P(l.xb[1]), sg, list ? counts : nullptr, b, st);
+            e = launch_split(top, grid0, p.h[1], P(l.xa[1]), P(l.xb[1]), sg, list ? counts : nullptr, top_n, b, st);
         else
-            e = launch_split(LevelInst{P(l.xa[j]), P(l.xb[j]), nullptr, p.h[j], cref(j)}, grid0 * pow3(j), p.h[j + 1],
-                             P(l.xa[j + 1]), P(l.xb[j + 1]), sg, nullptr, b, st);
+            e = launch_split(level(P(l.xa[j]), P(l.xb[j]), nullptr, j), grid0 * pow3(j), p.h[j + 1], P(l.xa[j + 1]),
+                             P(l.xb[j + 1]), sg, nullptr, nullptr, b, st);
     }
     if (e != hipSuccess) return set_error(BI_EHIP, "Karatsuba split launch: %s", hipGetErrorString(e));
     const int L = p.levels;
@@ -379,8 +452,8 @@ static bi_status kara_run(const Top &top, uint64_t grid0, const KaraPlan &p, uin
         if (j == 0)
             e = launch_combine(top, p.h[0], grid0, P(l.z[1]), sg, p.h[1], st);
         else
-            e = launch_combine(LevelInst{nullptr, nullptr, P(l.z[j]), p.h[j], cref(j)}, p.h[j], grid0 * pow3(j),
-                               P(l.z[j + 1]), sg, p.h[j + 1], st);
+            e = launch_combine(level(nullptr, nullptr, P(l.z[j]), j), p.h[j], grid0 * pow3(j), P(l.z[j + 1]), sg,
+                               p.h[j + 1], st);
     }
     if (e != hipSuccess) return set_error(BI_EHIP, "Karatsuba combine launch: %s", hipGetErrorString(e));
     return BI_OK;
@@ -408,7 +481,7 @@ bi_status launch_bigmul_kara(Ctx &c, const uint32_t *a, const uint32_t *b, uint3
 
 hipError_t launch_bigmul_kara_list(const Ctx &c, const Tune &tune, const ListInst &src, uint32_t nmax,
                                    uint64_t count_max, uint8_t *scr, size_t scr_bytes, hipStream_t st) {
-    const KaraPlan p = kara_plan(nmax, kKaraBase);
+    const KaraPlan p = kara_plan_tuned(tune, nmax);
     const int L = p.levels;
     const int alg = kara_base_algo(tune, p.h[L]);
     // rounds of as many instances as the scratch holds with the base's list scratch
@@ -434,16 +507,20 @@ hipError_t launch_bigmul_kara_list(const Ctx &c, const Tune &tune, const ListIns
 }
 
 size_t kara_list_scratch_bound(uint64_t count) {
-    // the largest class in full rounds with a base that needs no scratch (the
-    // schoolbook kernels), or in rounds of one instance with the largest base
-    // scratch any algorithm takes (launch_bigmul_kara_list shrinks its rounds
-    // to fit)
-    const KaraPlan p = kara_plan(kMaxLimbs32, kKaraBase);
-    const uint64_t R = std::max<uint64_t>(1, std::min<uint64_t>(count, kKaraListRound));
-    size_t base = 0;
-    for (int alg : {BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_MFMA, BI_MUL_NTT, BI_MUL_NTT_PF64})
-        base = std::max(base, list_algo_scratch_bytes(alg, p.h[p.levels], pow3(p.levels)));
-    return std::max(kara_round_bytes(p, R, true, 0), kara_round_bytes(p, 1, true, base));
+    // the largest class, for each base size the tuning may choose: full
+    // rounds with a base that needs no scratch (the schoolbook kernels), or
+    // rounds of one instance with the largest base scratch any algorithm
+    // takes (launch_bigmul_kara_list shrinks its rounds to fit)
+    size_t bound = 0;
+    for (uint32_t b : kKaraBases) {
+        const KaraPlan p = kara_plan(kMaxLimbs32, b);
+        const uint64_t R = std::max<uint64_t>(1, std::min<uint64_t>(count, kKaraListRound));
+        size_t base = 0;
+        for (int alg : {BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_MFMA, BI_MUL_NTT, BI_MUL_NTT_PF64})
+            base = std::max(base, list_algo_scratch_bytes(alg, p.h[p.levels], pow3(p.levels)));
+        bound = std::max({bound, kara_round_bytes(p, R, true, 0), kara_round_bytes(p, 1, true, base)});
+    }
+    return bound;
 }
 
 }  // namespace bi

@@ -435,10 +435,20 @@ __global__ __launch_bounds__((1 << M) / (2 * E)) void ntt_inv_half_kernel(NttCon
 struct CrtCoef {
     const uint32_t *tr;
     uint32_t L, p1, p2, crt, crt_sh;
-    __device__ __forceinline__ uint64_t operator()(uint64_t q, uint32_t k) const {
-        const uint32_t a1 = tr[4 * q * L + k], a2 = tr[(4 * q + 1) * L + k];
+    __device__ __forceinline__ uint64_t from(uint32_t a1, uint32_t a2) const {
         const uint32_t tq = mul_shoup(sub_mod(a2, a1, p2), crt, crt_sh, p2);
         return uint64_t(p1) * tq + a1;  // < p1 p2; equals the coefficient (< 2^46)
+    }
+    __device__ __forceinline__ uint64_t operator()(uint64_t q, uint32_t k) const {
+        return from(tr[4 * q * L + k], tr[(4 * q + 1) * L + k]);
+    }
+    // coefficients k0 .. k0 + 7 (k0 a multiple of 8, k0 + 7 < L), vector loads
+    __device__ __forceinline__ void eight(uint64_t q, uint32_t k0, uint64_t (&c)[8]) const {
+        const uint4 *r1 = reinterpret_cast<const uint4 *>(tr + 4 * q * L + k0);
+        const uint4 *r2 = reinterpret_cast<const uint4 *>(tr + (4 * q + 1) * L + k0);
+        const uint4 x0 = r1[0], x1 = r1[1], y0 = r2[0], y1 = r2[1];
+        c[0] = from(x0.x, y0.x); c[1] = from(x0.y, y0.y); c[2] = from(x0.z, y0.z); c[3] = from(x0.w, y0.w);
+        c[4] = from(x1.x, y1.x); c[5] = from(x1.y, y1.y); c[6] = from(x1.z, y1.z); c[7] = from(x1.w, y1.w);
     }
 };
 
@@ -460,6 +470,45 @@ struct CrtCoefSplit {
         const uint32_t a1 = residue(q, 0, k, p1), a2 = residue(q, 1, k, p2);
         const uint32_t tq = mul_shoup(sub_mod(a2, a1, p2), crt, crt_sh, p2);
         return uint64_t(p1) * tq + a1;
+    }
+    // residues k0 .. k0 + 7 of prime i (k0 a multiple of 8): z words and,
+    // at full table resolution (shift 0), the twiddles by vector loads
+    __device__ __forceinline__ void residue8(uint64_t q, int i, uint32_t k0, uint32_t p, uint32_t (&r)[8]) const {
+        const uint32_t half = L / 2, j0 = k0 & (half - 1);
+        const uint32_t *z = tr + (4 * q + i) * L;
+        const uint4 *z0 = reinterpret_cast<const uint4 *>(z + j0), *z1 = reinterpret_cast<const uint4 *>(z + half + j0);
+        const uint4 a0 = z0[0], a1 = z0[1], b0 = z1[0], b1 = z1[1];
+        const uint32_t av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+        const uint32_t bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+        uint2 w[8];
+        if (shift == 0) {
+            const uint4 *wt = reinterpret_cast<const uint4 *>(inv[i] + j0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint4 t = wt[e];
+                w[2 * e] = make_uint2(t.x, t.y);
+                w[2 * e + 1] = make_uint2(t.z, t.w);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) w[e] = inv[i][(j0 + e) << shift];
+        }
+        const bool lo = k0 < half;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t t = mul_shoup(bv[e], w[e].x, w[e].y, p);
+            r[e] = lo ? add_mod(av[e], t, p) : sub_mod(av[e], t, p);
+        }
+    }
+    __device__ __forceinline__ void eight(uint64_t q, uint32_t k0, uint64_t (&c)[8]) const {
+        uint32_t a1[8], a2[8];
+        residue8(q, 0, k0, p1, a1);
+        residue8(q, 1, k0, p2, a2);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t tq = mul_shoup(sub_mod(a2[e], a1[e], p2), crt, crt_sh, p2);
+            c[e] = uint64_t(p1) * tq + a1[e];
+        }
     }
 };
 
@@ -483,6 +532,29 @@ struct Half64Coef {
         }
         return v >> 1;
     }
+    __device__ __forceinline__ void eight(uint64_t q, uint32_t k0, uint64_t (&c)[8]) const {
+        const uint64_t *cyc = tr + 4 * q * H, *neg = cyc + H;
+        const bool lo = k0 < H;
+        const uint32_t j0 = lo ? k0 : k0 - H;
+        const ulonglong2 *cv = reinterpret_cast<const ulonglong2 *>(cyc + j0);
+        const ulonglong2 *nv = reinterpret_cast<const ulonglong2 *>(neg + j0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const ulonglong2 cc = cv[e], nn = nv[e];
+            const uint64_t cs[2] = {cc.x, cc.y}, ns[2] = {nn.x, nn.y};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                uint64_t v;
+                if (lo) {
+                    v = cs[h] + ns[h];
+                    if (v >= kP64) v -= kP64;
+                } else {
+                    v = cs[h] >= ns[h] ? cs[h] - ns[h] : cs[h] - ns[h] + kP64;
+                }
+                c[2 * e + h] = v >> 1;
+            }
+        }
+    }
 };
 
 // One workgroup per instance: coefficients from `coef`, per-thread combine of
@@ -502,10 +574,12 @@ __global__ __launch_bounds__(64 * NW) void ntt_crt_carry_kernel(Coef coef, Src s
         for (uint32_t g = threadIdx.x; g < ngroups; g += 64 * NW) {
             // column sums of sum_e c_{8g+e} 2^(16 e), one 64-bit column per word
             uint64_t col[6] = {0, 0, 0, 0, 0, 0};
+            uint64_t cf[8];
+            coef.eight(q, 8 * g, cf);  // 8 g + 7 < L (the padded length is a multiple of 8)
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const uint32_t k = 8 * g + e;
-                const uint64_t c = k < nout ? coef(q, k) : 0;
+                const uint64_t c = k < nout ? cf[e] : 0;
                 const uint64_t v = c << (16 * (e & 1));  // < 2^62
                 col[e >> 1] += uint32_t(v);
                 col[(e >> 1) + 1] += uint32_t(v >> 32);
@@ -545,10 +619,12 @@ __global__ __launch_bounds__(256) void ntt_fold_kernel(Coef coef, Src src, uint6
         if (g >= ngroups) continue;
         // column sums of sum_e c_{8g+e} 2^(16 e), one 64-bit column per word
         uint64_t col[6] = {0, 0, 0, 0, 0, 0};
+        uint64_t cf[8];
+        coef.eight(q, 8 * g, cf);  // 8 g + 7 < L (the padded length is a multiple of 8)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const uint32_t k = 8 * g + e;
-            const uint64_t c = k < nout ? coef(q, k) : 0;
+            const uint64_t c = k < nout ? cf[e] : 0;
             const uint64_t v = c << (16 * (e & 1));  // < 2^62
             col[e >> 1] += uint32_t(v);
             col[(e >> 1) + 1] += uint32_t(v >> 32);

@@ -69,7 +69,13 @@ static void default_tune(Tune &t) {
         t.mul_algo[k] = algo[k];
         t.valu_q[k] = q[k];
         t.valu_nw[k] = nw[k];
+        t.kara_base[k] = kKaraBase;
     }
+}
+
+KaraPlan kara_plan_tuned(const Tune &tune, uint32_t n32) {
+    const uint32_t b = tune.kara_base[size_class_host(n32)];
+    return kara_plan(n32, b ? b : kKaraBase);
 }
 
 bi_status ctx_init(Ctx &c, int device, const hipDeviceProp_t &prop) {
@@ -85,6 +91,13 @@ bi_status ctx_init(Ctx &c, int device, const hipDeviceProp_t &prop) {
     c.add.multi2 = true;
     c.add.multi4 = true;
     c.add.multi8 = false;
+    // Experiment override: BI_KARA_BASE=<words> sets every class's Karatsuba base.
+    if (const char *env = std::getenv("BI_KARA_BASE")) {
+        const int b = std::atoi(env);
+        for (uint32_t v : kKaraBases)
+            if (b == int(v))
+                for (uint32_t k = 0; k < kNumClasses; ++k) c.tune.kara_base[k] = uint16_t(b);
+    }
     // Experiment override: BI_ADD_TUNE="rows,nt,max_waves,multi_mask"
     // (e.g. "8,1,32768,7"; multi_mask bit 0/1/2 = 2/4/8-row instances).
     if (const char *env = std::getenv("BI_ADD_TUNE")) {
@@ -198,7 +211,7 @@ bi_status dispatch_bigmul(Ctx &c, const void *a, const void *b, void *out, uint3
             e = launch_bigmul_ntt64(c.ntt.c64, A, B, C, n32, batch, static_cast<uint64_t *>(scr), st, round);
             break;
         case BI_MUL_KARATSUBA: {
-            const KaraPlan kp = kara_plan(n32, kKaraBase);
+            const KaraPlan kp = kara_plan_tuned(c.tune, n32);
             const uint32_t hb = kp.h[kp.levels];
             const int base = kara_base_algo(c.tune, hb);
             uint64_t nbase = 1;  // base products per instance

@@ -182,6 +182,38 @@ def test_karatsuba_signs_and_borrows(B, ctx, orc, n):
     check(orc, a, b, run_mul(B, ctx, a, b, ALGOS["kara"]))
 
 
+@pytest.mark.parametrize("base", [512, 1024, 2048])
+def test_karatsuba_bases(B, orc, base):
+    """Every Karatsuba base size (levels down to at most 512, 1024 or 2048
+    words), uniform batches at sizes that give one to four levels and ragged
+    batches through bigmul_v whose instances keep their own level sizes."""
+    c = B.Context(0)
+    try:
+        B.tune_set_kara(c, [base] * B.NUM_CLASSES)
+        rng = np.random.default_rng(base)
+        for n in (600, 1025, 2047, 2049, 4096, 5000, 8192):
+            a, b = patterned(rng, 4, n)
+            plan = B.mul_plan(c, n, 32, ALGOS["kara"])
+            assert plan["base_limbs"] <= max(base, 4) or plan["kara_levels"] == 4, plan
+            check(orc, a, b, run_mul(B, c, a, b, ALGOS["kara"]))
+        ns = np.array([1, 5, 700, 1500, 2100, 3000, 4097, 5000, 6500, 8191, 8192, 4200], dtype=np.int64)
+        A = rng.integers(0, 2**32, int(ns.sum()), dtype=np.uint64).astype(np.uint32)
+        Bv = rng.integers(0, 2**32, int(ns.sum()), dtype=np.uint64).astype(np.uint32)
+        A[: int(ns[:3].sum())] = 0xFFFFFFFF
+        off = np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.uint64)
+        out = G.empty_dev((2 * int(ns.sum()),), np.uint32)
+        B.bigmul_v(c, G.to_dev(A), G.to_dev(Bv), out, G.desc_dev(off, off, 2 * off, ns), len(ns), 32,
+                   algo=ALGOS["kara"])
+        G.sync()
+        got = G.from_dev(out, np.uint32)
+        for i, n in enumerate(ns.tolist()):
+            o = int(off[i])
+            want = orc.mul(A[o: o + n][None], Bv[o: o + n][None])[0]
+            assert (got[2 * o: 2 * o + 2 * n] == want).all(), (base, i, n)
+    finally:
+        c.close()
+
+
 def full_size_check(B, ctx, orc, a, b):
     """Every algorithm that runs this size, in the benchmark's launch
     configuration (one uniform bigmul over the whole batch), against the
@@ -292,6 +324,8 @@ def test_tune_save_load(B, orc, tmp_path):
     try:
         algos = B.autotune(c)
         valu = B.tune_get_valu(c)
+        kara = B.tune_get_kara(c)
+        assert all(k in (512, 1024, 2048) for k in kara)
         path = str(tmp_path / "tune.txt")
         B.tune_save(c, path)
     finally:
@@ -299,8 +333,9 @@ def test_tune_save_load(B, orc, tmp_path):
     d = B.Context(0)
     try:
         B.tune_set(d, [1] * B.NUM_CLASSES)
+        B.tune_set_kara(d, [512] * B.NUM_CLASSES)
         B.tune_load(d, path)
-        assert B.tune_get(d) == algos and B.tune_get_valu(d) == valu
+        assert B.tune_get(d) == algos and B.tune_get_valu(d) == valu and B.tune_get_kara(d) == kara
         rng = np.random.default_rng(7)
         for n in (40, 700, 5000):
             a, b = patterned(rng, 3, n)
@@ -318,6 +353,19 @@ def test_tune_save_load(B, orc, tmp_path):
         with pytest.raises(B.BigIntError):
             B.tune_load(d, str(tmp_path / "missing.txt"))
         assert B.tune_get(d) == [2] * B.NUM_CLASSES
+        # a version-1 file (no Karatsuba bases) loads with the default base
+        v1 = "\n".join(l for l in text.splitlines() if not l.startswith("kara_base")).replace(
+            "bigint-tune 2", "bigint-tune 1")
+        open(other, "w").write(v1 + "\n")
+        B.tune_load(d, other)
+        assert B.tune_get(d) == algos and B.tune_get_kara(d) == [1024] * B.NUM_CLASSES
+        open(other, "w").write(text.replace("kara_base 512", "kara_base 500").replace("kara_base 1024", "kara_base 1000")
+                               .replace("kara_base 2048", "kara_base 2000"))
+        with pytest.raises(B.BigIntError):
+            B.tune_load(d, other)
+        with pytest.raises(B.BigIntError):
+            B.tune_set_kara(d, [1000] + [1024] * (B.NUM_CLASSES - 1))
+        assert B.tune_get_kara(d) == [1024] * B.NUM_CLASSES
     finally:
         d.close()
 
