@@ -266,22 +266,27 @@ bi_status bigmul_v(bi_ctx *ctx, const void *a, const void *b, void *out,
                    const bi_desc *desc, uint64_t count, uint32_t limb_bits, int algo, void *stream);
 
 /*
- * Tuning.  Ragged batches and BI_MUL_AUTO pick a multiplication algorithm per
- * size class: class k holds instances of (16 << (k-1), 16 << k] 32-bit limbs
- * (class 0: up to 16), k < BI_NUM_CLASSES.  bi_autotune first picks, per
- * class, the VALU schoolbook's schedule (Q = 2 or 4 output words per lane --
- * the paper's sequentialisation factor, Section 3 -- and 1..16 waves per
- * workgroup), then times every algorithm on synthetic operands of each
- * class's largest size on the context's device (and the addition schedules
- * for 2-, 4- and 8-row instances), keeps the fastest, and copies the
- * per-class choice to algo_out[0 .. n_out) if not NULL.  It allocates and frees 64 MiB of device memory and synchronises
- * `stream`.  bi_tune_get / bi_tune_set read or replace the per-class choice
- * (BI_EALGO if an algorithm cannot run a class's sizes; nothing is changed
- * then).  Until tuned, a context uses a built-in table (the choices
- * bi_autotune made on an MI355X).
+ * Tuning.  BI_MUL_AUTO picks a multiplication algorithm per size class:
+ * class k holds instances of (16 << (k-1), 16 << k] 32-bit limbs (class 0:
+ * up to 16), k < BI_NUM_CLASSES.  Uniform batches (bigmul) use one table,
+ * ragged batches (bigmul_v, the stream queue) another.  bi_autotune first
+ * picks, per class, the VALU schoolbook's schedule (Q = 2 or 4 output words
+ * per lane -- the paper's sequentialisation factor, Section 3 -- and 1..16
+ * waves per workgroup), then times every algorithm (Karatsuba at each base
+ * size) on synthetic operands of each class's largest size and keeps the
+ * fastest for the uniform table, then times every algorithm on a ragged
+ * batch of the class (sizes spread over the class) for the ragged table,
+ * and the addition schedules for 2-, 4- and 8-row instances; it copies the
+ * uniform per-class choice to algo_out[0 .. n_out) if not NULL.  It allocates
+ * and frees about 64 MiB of device memory, may grow the context's scratch,
+ * and synchronises `stream`.  bi_tune_get / bi_tune_set read or replace the
+ * uniform per-class choice (BI_EALGO if an algorithm cannot run a class's
+ * sizes; nothing is changed then).  Until tuned, a context uses built-in
+ * tables (the choices bi_autotune made on an MI355X).
  *
- * bi_tune_save writes the context's tables (algorithm, VALU schedule and
- * Karatsuba base per class, the addition schedules) to the text file `path`, keyed by the
+ * bi_tune_save writes the context's tables (uniform and ragged algorithm,
+ * VALU schedule and Karatsuba base per class, the addition schedules) to the
+ * text file `path`, keyed by the
  * device's architecture name and the HIP runtime version; bi_tune_load reads
  * such a file into the context.  A file written for another architecture or
  * runtime version, a malformed one, or one naming an algorithm or schedule a
@@ -304,6 +309,14 @@ bi_status bi_tune_load(bi_ctx *ctx, const char *path);
 bi_status bi_tune_get_valu(const bi_ctx *ctx, int *q_out, int *waves_out, uint32_t n_out);
 bi_status bi_tune_set_valu(bi_ctx *ctx, const int *q_in, const int *waves_in, uint32_t n_in);
 
+/* The ragged-batch table: bigmul_v and the stream queue with BI_MUL_AUTO run
+ * class k's instances (spread over the class's sizes) with list_algo[k];
+ * bi_autotune times every algorithm on such a batch per class.  Set / get as
+ * bi_tune_set / bi_tune_get (BI_EALGO, nothing changed, if an algorithm
+ * cannot run a class). */
+bi_status bi_tune_get_list(const bi_ctx *ctx, int *algo_out, uint32_t n_out);
+bi_status bi_tune_set_list(bi_ctx *ctx, const int *algo_in, uint32_t n_in);
+
 /* The Karatsuba base per class: BI_MUL_KARATSUBA on class k's sizes splits
  * until the operands have at most base[k] 32-bit words (512, 1024 or 2048;
  * default 1024); bi_autotune picks it per class.  bi_tune_set_kara replaces
@@ -314,7 +327,14 @@ bi_status bi_tune_set_kara(bi_ctx *ctx, const uint32_t *base_in, uint32_t n_in);
 /*
  * Stream mode: a queue of ragged multiplication bursts over caller-owned
  * operand buffers a (a_limbs limbs), b (b_limbs) and out (out_limbs), all of
- * `limb_bits`-bit limbs, executed in submission order on `stream`.
+ * `limb_bits`-bit limbs.  Bursts run on the queue's own two streams (burst t
+ * on the (t mod 2)-th), so consecutive bursts may overlap on the GPU; each
+ * starts once its descriptors have been copied.  The queue starts after the
+ * work queued on `stream` when it is opened, and `stream` waits for every
+ * burst in submission order, so work queued on `stream` after a submission
+ * sees that burst's results.  The caller must not change operand data, or
+ * give two bursts that may be in flight overlapping output ranges, without
+ * waiting for the earlier ticket.
  *
  * bi_stream_open allocates a few staging slots (each a pinned host buffer and
  * a device buffer of max_descs descriptors and class-list entries), the
@@ -326,7 +346,7 @@ bi_status bi_tune_set_kara(bi_ctx *ctx, const uint32_t *base_in, uint32_t n_in);
  * device-side binning into size classes, then one persistent list kernel per
  * class that reads its instance count on the device -- into a HIP graph that
  * every submission replays.  The per-class algorithm is `algo`, or for
- * BI_MUL_AUTO the context's tuning table at open time.  The queue keeps
+ * BI_MUL_AUTO the context's ragged-batch table at open time.  The queue keeps
  * pointers to ctx and the buffers; they must outlive it.  BI_ENOMEM / BI_EHIP
  * on allocation or capture failure (nothing is left allocated then).
  *

@@ -362,6 +362,21 @@ bi_status bi_mul_plan(const bi_ctx *ctx, uint32_t n_limbs, uint32_t limb_bits, i
     return BI_OK;
 }
 
+bi_status bi_tune_get_list(const bi_ctx *ctx, int *algo_out, uint32_t n_out) {
+    if (!ctx || !algo_out) return fail(BI_EINVAL, "NULL argument");
+    for (uint32_t k = 0; k < n_out && k < bi::kNumClasses; ++k) algo_out[k] = ctx->impl.tune.list_algo[k];
+    return BI_OK;
+}
+
+bi_status bi_tune_set_list(bi_ctx *ctx, const int *algo_in, uint32_t n_in) {
+    if (!ctx || !algo_in) return fail(BI_EINVAL, "NULL argument");
+    for (uint32_t k = 0; k < n_in && k < bi::kNumClasses; ++k)
+        if (!bi::algo_supports(algo_in[k], bi::class_nmax(k)))
+            return fail(BI_EALGO, "algorithm %d cannot run size class %u", algo_in[k], k);
+    for (uint32_t k = 0; k < n_in && k < bi::kNumClasses; ++k) ctx->impl.tune.list_algo[k] = algo_in[k];
+    return BI_OK;
+}
+
 bi_status bi_tune_get_kara(const bi_ctx *ctx, uint32_t *base_out, uint32_t n_out) {
     if (!ctx || !base_out) return fail(BI_EINVAL, "NULL argument");
     for (uint32_t k = 0; k < n_out && k < bi::kNumClasses; ++k) base_out[k] = ctx->impl.tune.kara_base[k];

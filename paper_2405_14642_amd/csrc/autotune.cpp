@@ -8,6 +8,8 @@
 // kernel families and their schedules.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -52,6 +54,61 @@ bi_status time_us(hipStream_t st, Timer &t, int reps, F &&launch, float *us) {
     return BI_OK;
 }
 
+constexpr uint64_t kRaggedMax = 4096;  // instances of a ragged timing batch
+const int kAlgos[5] = {BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_MFMA, BI_MUL_NTT, BI_MUL_NTT_PF64, BI_MUL_KARATSUBA};
+
+// The list algorithm of class k from a ragged batch: instances of sizes
+// spread log-uniformly over the class (a fixed 64-bit LCG), operands at a +
+// i nmax and b + i nmax, results at o + 2 i nmax, launched as the one class
+// of a host-binned batch; every algorithm that runs the class is timed and
+// the fastest kept in c.tune.list_algo[k].
+bi_status tune_ragged_class(Ctx &c, uint32_t k, const uint32_t *a, const uint32_t *b, uint32_t *o, uint64_t limbs,
+                            void *rdesc, hipStream_t st, Timer &tm) {
+    const uint32_t nmax = class_nmax(k), nmin = k ? nmax / 2 + 1 : 1;
+    const uint64_t count = std::min<uint64_t>(limbs / nmax, kRaggedMax);
+    std::vector<bi_desc> d(count);
+    std::vector<uint32_t> list(count);
+    uint64_t x = 0x2405146420ull + k;
+    for (uint64_t i = 0; i < count; ++i) {
+        x = x * 6364136223846793005ull + 1442695040888963407ull;
+        const double u = double(x >> 11) * (1.0 / 9007199254740992.0);  // [0, 1)
+        uint32_t n = uint32_t(double(nmin) * std::pow(double(nmax) / double(nmin), u));
+        n = std::min(std::max(n, nmin), nmax);
+        d[i] = bi_desc{i * nmax, i * nmax, 2 * i * nmax, n, 0};
+        list[i] = uint32_t(i);
+    }
+    auto *dd = static_cast<bi_desc *>(rdesc);
+    auto *dl = reinterpret_cast<uint32_t *>(dd + kRaggedMax);
+    auto *dc = dl + kRaggedMax;
+    uint32_t hc[kNumClasses] = {};
+    hc[k] = uint32_t(count);
+    if (hipMemcpyAsync(dd, d.data(), count * sizeof(bi_desc), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(dl, list.data(), count * sizeof(uint32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(dc, hc, sizeof hc, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return set_error(BI_EHIP, "autotune descriptor copy");
+    void *scr = nullptr;
+    bi_status s = ctx_scratch(c, batch_scratch_bytes(count, c.num_cus), st, &scr);
+    if (s != BI_OK) return s;
+    float best = 0;
+    int best_algo = c.tune.list_algo[k];
+    for (int al : kAlgos) {
+        if (!algo_supports(al, nmax)) continue;
+        float us = 0;
+        s = time_us(st, tm, 3, [&]() {
+            return launch_bigmul_v_binned(c, c.tune, a, b, o, dd, dl, dc, hc, 32, al, scr, st) == hipSuccess ? BI_OK
+                                                                                                          : BI_EHIP;
+        }, &us);
+        if (s != BI_OK) return s;
+        if (best == 0 || us < best) {
+            best = us;
+            best_algo = al;
+        }
+    }
+    c.tune.list_algo[k] = best_algo;
+    return BI_OK;
+}
+
 }  // namespace
 
 bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out) {
@@ -63,6 +120,12 @@ bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out) {
     hipLaunchKernelGGL(fill_hash_kernel, dim3(1024), dim3(256), 0, st, a, 2 * limbs, 0x2405u);
     Timer tm;
     bi_status s = BI_OK;
+    // descriptors, list and count of the ragged batches
+    void *rdesc = nullptr;
+    if (hipMalloc(&rdesc, kRaggedMax * (sizeof(bi_desc) + sizeof(uint32_t)) + 256) != hipSuccess) {
+        (void)hipFree(buf);
+        return set_error(BI_ENOMEM, "autotune buffers");
+    }
     const int algos[5] = {BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_MFMA, BI_MUL_NTT, BI_MUL_NTT_PF64, BI_MUL_KARATSUBA};
     for (uint32_t k = 0; k < kNumClasses && s == BI_OK; ++k) {
         const uint32_t n = class_nmax(k);
@@ -126,7 +189,10 @@ bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out) {
             if (s != BI_OK) break;
         }
         c.tune.mul_algo[k] = best_algo;
+        if (s != BI_OK) break;
+        s = tune_ragged_class(c, k, a, b, o, limbs, rdesc, st, tm);
     }
+    if (rdesc) (void)hipFree(rdesc);
     // Addition: workgroup-cooperative vs one wave per instance, per row class.
     for (int rc = 0; rc < 3 && s == BI_OK; ++rc) {
         const uint32_t rows = rc == 0 ? 2 : rc == 1 ? 4 : 8;
@@ -160,7 +226,9 @@ bi_status autotune(Ctx &c, hipStream_t st, int *algo_out, uint32_t n_out) {
 //   mul_algo <10 algorithm ids>
 //   valu_q <10 values>    valu_nw <10 values>
 //   add_multi <multi2> <multi4> <multi8>
-//   kara_base <10 values>   (version 2; version-1 files leave the default)
+//   kara_base <10 values>   list_algo <10 algorithm ids>
+//   (version 2; a version-1 file gives the default Karatsuba bases and its
+//   mul_algo table to ragged batches as well)
 bi_status tune_save(const Ctx &c, const char *path) {
     std::FILE *f = std::fopen(path, "w");
     if (!f) return set_error(BI_EINVAL, "cannot open %s for writing", path);
@@ -172,6 +240,8 @@ bi_status tune_save(const Ctx &c, const char *path) {
     for (uint32_t k = 0; k < kNumClasses; ++k) std::fprintf(f, " %d", int(c.tune.valu_nw[k]));
     std::fprintf(f, "\nadd_multi %d %d %d\nkara_base", int(c.add.multi2), int(c.add.multi4), int(c.add.multi8));
     for (uint32_t k = 0; k < kNumClasses; ++k) std::fprintf(f, " %d", int(c.tune.kara_base[k]));
+    std::fprintf(f, "\nlist_algo");
+    for (uint32_t k = 0; k < kNumClasses; ++k) std::fprintf(f, " %d", c.tune.list_algo[k]);
     std::fprintf(f, "\n");
     const bool ok = std::fclose(f) == 0;
     return ok ? BI_OK : set_error(BI_EINVAL, "writing %s failed", path);
@@ -182,7 +252,7 @@ bi_status tune_load(Ctx &c, const char *path) {
     if (!f) return set_error(BI_EINVAL, "cannot open %s", path);
     char arch[64] = {}, key[32] = {};
     int version = -1, hip = 0;
-    int algo[kNumClasses], q[kNumClasses], nw[kNumClasses], m[3], kb[kNumClasses];
+    int algo[kNumClasses], q[kNumClasses], nw[kNumClasses], m[3], kb[kNumClasses], la[kNumClasses];
     // each record opens with its key, compared as a whole token
     auto expect = [&](const char *k) { return std::fscanf(f, "%31s", key) == 1 && std::strcmp(key, k) == 0; };
     auto ints = [&](int *v, uint32_t cnt) {
@@ -194,16 +264,19 @@ bi_status tune_load(Ctx &c, const char *path) {
               std::fscanf(f, "%63s", arch) == 1 && expect("hip") && ints(&hip, 1) && expect("mul_algo") &&
               ints(algo, kNumClasses) && expect("valu_q") && ints(q, kNumClasses) && expect("valu_nw") &&
               ints(nw, kNumClasses) && expect("add_multi") && ints(m, 3);
-    for (uint32_t k = 0; k < kNumClasses; ++k) kb[k] = int(kKaraBase);
-    if (ok && version == 2) ok = expect("kara_base") && ints(kb, kNumClasses);
+    for (uint32_t k = 0; k < kNumClasses; ++k) {  // version 1: ragged batches used the uniform table
+        kb[k] = int(kKaraBase);
+        la[k] = algo[k];
+    }
+    if (ok && version == 2) ok = expect("kara_base") && ints(kb, kNumClasses) && expect("list_algo") && ints(la, kNumClasses);
     std::fclose(f);
     if (!ok) return set_error(BI_EINVAL, "%s is not a tuning file", path);
     if (std::strcmp(arch, c.arch) != 0 || hip != c.hip_version)
         return set_error(BI_EINVAL, "%s was tuned for %s with HIP %d, this context is %s with HIP %d", path, arch, hip,
                          c.arch, c.hip_version);
     for (uint32_t k = 0; k < kNumClasses; ++k) {
-        if (!algo_supports(algo[k], class_nmax(k)))
-            return set_error(BI_EINVAL, "%s: algorithm %d cannot run size class %u", path, algo[k], k);
+        if (!algo_supports(algo[k], class_nmax(k)) || !algo_supports(la[k], class_nmax(k)))
+            return set_error(BI_EINVAL, "%s: algorithm %d / %d cannot run size class %u", path, algo[k], la[k], k);
         if (!(q[k] == 0 && nw[k] == 0) && !valu_plan_fits(class_nmax(k), q[k], nw[k], nullptr))
             return set_error(BI_EINVAL, "%s: VALU schedule (%d, %d) does not fit size class %u", path, q[k], nw[k], k);
         if (!kara_base_valid(uint32_t(kb[k])))
@@ -215,6 +288,7 @@ bi_status tune_load(Ctx &c, const char *path) {
         c.tune.valu_q[k] = uint8_t(q[k]);
         c.tune.valu_nw[k] = uint8_t(nw[k]);
         c.tune.kara_base[k] = uint16_t(kb[k]);
+        c.tune.list_algo[k] = la[k];
     }
     c.add.multi2 = m[0] != 0;
     c.add.multi4 = m[1] != 0;

@@ -105,7 +105,7 @@ hipError_t launch_bigmul_list_algo(const Ctx &c, const Tune &tune, const ListIns
 static hipError_t launch_class(const Ctx &c, const Tune &tune, const ListInst &src, uint32_t k, uint64_t count_max,
                                int algo, void *scr, hipStream_t st) {
     const uint32_t nmax = class_nmax(k);
-    int alg = tune.mul_algo[k];
+    int alg = tune.list_algo[k];
     if (algo != BI_MUL_AUTO && algo_supports(algo, nmax)) alg = algo;
     return launch_bigmul_list_algo(c, tune, src, nmax, count_max, alg, scr, class_scratch_bytes(count_max), st);
 }

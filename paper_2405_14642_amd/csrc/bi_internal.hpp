@@ -23,9 +23,12 @@ constexpr uint32_t kMaxLimbs32 = BI_MAX_BITS / 32;  // 8192
 constexpr uint32_t kNumClasses = 10;               // ragged size classes: <= 16, 32, ..., 8192 limbs
 uint32_t class_nmax(uint32_t c);
 
-// Per-context tuning: multiplication algorithm per size class (BI_MUL_AUTO).
+// Per-context tuning: multiplication algorithm per size class for uniform
+// batches (BI_MUL_AUTO in bigmul) and for ragged ones (bigmul_v and the
+// stream queue, whose instances spread over the class's sizes).
 struct Tune {
     int mul_algo[kNumClasses];
+    int list_algo[kNumClasses];
     // VALU schoolbook schedule per class: output words per lane (Q = 2 or 4)
     // and waves per workgroup; 0 = the size rule of valu_plan.
     uint8_t valu_q[kNumClasses];
@@ -337,7 +340,7 @@ struct KaraPlan {
 KaraPlan kara_plan(uint32_t n32, uint32_t base);
 // The plan of the size class of n32 words under `tune`.
 KaraPlan kara_plan_tuned(const Tune &tune, uint32_t n32);
-int kara_base_algo(const Tune &tune, uint32_t h);
+int kara_base_algo(const Tune &tune, uint32_t h, bool ragged = false);
 // Scratch of one round of R top-level instances (list: ragged rounds, which
 // also publish the base products as a descriptor list), plus base_bytes for
 // the base algorithm.

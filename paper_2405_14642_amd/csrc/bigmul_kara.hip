@@ -483,7 +483,7 @@ hipError_t launch_bigmul_kara_list(const Ctx &c, const Tune &tune, const ListIns
                                    uint64_t count_max, uint8_t *scr, size_t scr_bytes, hipStream_t st) {
     const KaraPlan p = kara_plan_tuned(tune, nmax);
     const int L = p.levels;
-    const int alg = kara_base_algo(tune, p.h[L]);
+    const int alg = kara_base_algo(tune, p.h[L], true);
     // rounds of as many instances as the scratch holds with the base's list scratch
     uint64_t R = std::max<uint64_t>(1, std::min<uint64_t>(count_max, kKaraListRound));
     while (R > 1 && kara_round_bytes(p, R, true, list_algo_scratch_bytes(alg, p.h[L], R * pow3(L))) > scr_bytes)

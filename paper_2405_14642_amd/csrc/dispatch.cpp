@@ -37,8 +37,9 @@ int resolve_algo(const Tune &tune, uint32_t n32, int algo) {
     return algo_supports(algo, n32) ? algo : BI_MUL_SCHOOL_VALU;
 }
 
-int kara_base_algo(const Tune &tune, uint32_t h) {
-    const int alg = tune.mul_algo[size_class_host(h)];
+int kara_base_algo(const Tune &tune, uint32_t h, bool ragged) {
+    const uint32_t k = size_class_host(h);
+    const int alg = ragged ? tune.list_algo[k] : tune.mul_algo[k];
     if (alg != BI_MUL_KARATSUBA && algo_supports(alg, h)) return alg;
     return BI_MUL_SCHOOL_MFMA;
 }
@@ -52,21 +53,29 @@ size_t uniform_algo_scratch_bytes(int alg, uint32_t n32) {
     }
 }
 
-// Built-in per-class table, as bi_autotune measured it on MI355X (one GPU, a
-// fresh context, each class timed at its largest size): the VALU schoolbook
-// up to 64 limbs (2^11 bits), the int8-MFMA schoolbook up to 4096 limbs
-// (2^17 bits), the two-prime NTT at 8192 limbs; and the VALU schedule
-// (Q output words per lane, waves per workgroup) it picked per class.
-// bi_autotune re-measures and replaces it on the device at hand.
+// Built-in per-class tables, as bi_autotune measured them on MI355X (one
+// GPU, a fresh context).  Uniform batches, each class at its largest size:
+// the VALU schoolbook up to 64 limbs (2^11 bits), the int8-MFMA schoolbook up
+// to 4096 limbs (2^17 bits), the two-prime NTT at 8192 limbs.  Ragged batches
+// (sizes spread over each class): the same up to 4096 limbs, Karatsuba over
+// 8192 (its work follows each instance's size; an NTT's transform length is
+// the class's).  Also the VALU schedule (Q output words per lane, waves per
+// workgroup) per class.  bi_autotune re-measures and replaces them on the
+// device at hand.
 static void default_tune(Tune &t) {
     static const int algo[kNumClasses] = {BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_VALU,
                                           BI_MUL_SCHOOL_MFMA, BI_MUL_SCHOOL_MFMA, BI_MUL_SCHOOL_MFMA,
                                           BI_MUL_SCHOOL_MFMA, BI_MUL_SCHOOL_MFMA, BI_MUL_SCHOOL_MFMA,
                                           BI_MUL_NTT};
+    static const int list[kNumClasses] = {BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_VALU,
+                                          BI_MUL_SCHOOL_MFMA, BI_MUL_SCHOOL_MFMA, BI_MUL_SCHOOL_MFMA,
+                                          BI_MUL_SCHOOL_MFMA, BI_MUL_SCHOOL_MFMA, BI_MUL_SCHOOL_MFMA,
+                                          BI_MUL_KARATSUBA};
     static const uint8_t q[kNumClasses] = {2, 2, 2, 4, 2, 2, 4, 4, 4, 4};
     static const uint8_t nw[kNumClasses] = {1, 1, 1, 1, 2, 4, 4, 8, 16, 16};
     for (uint32_t k = 0; k < kNumClasses; ++k) {
         t.mul_algo[k] = algo[k];
+        t.list_algo[k] = list[k];
         t.valu_q[k] = q[k];
         t.valu_nw[k] = nw[k];
         t.kara_base[k] = kKaraBase;

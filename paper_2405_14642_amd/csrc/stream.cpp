@@ -10,8 +10,15 @@
 // with a grid sized to its count.  Descriptors pass through staging slots, each a
 // pinned host buffer and a device buffer of its own; a slot is reused only
 // after the event of its previous burst has completed.  The copies run on a
-// side stream, so the copy of a burst overlaps the bursts queued before it
-// and the queue's stream only waits on a copy that has already finished.
+// side stream, so the copy of a burst overlaps the bursts queued before it.
+//
+// Bursts run on kLanes lanes, each a stream of the queue's own with its own
+// binning and transform scratch: burst t on lane t mod kLanes, after its
+// descriptor copy, so consecutive bursts overlap on the GPU (a burst's class
+// kernels are sized to its instances and rarely fill the GPU alone).  The
+// lanes start after the work queued on the caller's stream at open; the
+// caller's stream waits for every burst in submission order, so work queued
+// there after a submission sees its results.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -22,6 +29,7 @@
 namespace {
 
 constexpr int kSlots = 4;
+constexpr int kLanes = 2;  // kSlots is a multiple of it: a slot always runs on the same lane
 // Staging layout: count (u64) at 0, per-class counts (u32, host binning) at
 // kCountsAt, descriptors from kHeader, then (host binning) the class lists.
 constexpr size_t kHeader = 256;
@@ -50,7 +58,8 @@ struct bi_stream {
     bi::Tune tune{};
     hipStream_t st = nullptr;
     hipStream_t copy_st = nullptr;  // descriptor copies
-    void *scratch = nullptr;  // binning lists and transform scratch
+    hipStream_t lane_st[kLanes] = {};
+    void *scratch[kLanes] = {};  // per lane: binning lists and transform scratch
     Slot slots[kSlots];
     uint64_t next = 0;
     bool graphs = false;
@@ -67,16 +76,21 @@ void release(bi_stream *q) {
         if (s.dev) (void)hipFree(s.dev);
     }
     if (q->copy_st) (void)hipStreamDestroy(q->copy_st);
-    if (q->scratch) (void)hipFree(q->scratch);
+    for (int l = 0; l < kLanes; ++l) {
+        if (q->lane_st[l]) (void)hipStreamDestroy(q->lane_st[l]);
+        if (q->scratch[l]) (void)hipFree(q->scratch[l]);
+    }
     delete q;
 }
 
-// One burst over the descriptors in the device copy of `slot`.
-hipError_t launch_burst(bi_stream *q, const Slot &slot, hipStream_t st) {
+// One burst over the descriptors in the device copy of slot `s`, with the
+// scratch of the slot's lane.
+hipError_t launch_burst(bi_stream *q, int s, hipStream_t st) {
+    const Slot &slot = q->slots[s];
     const bi_desc *d = reinterpret_cast<const bi_desc *>(static_cast<char *>(slot.dev) + kHeader);
     const uint64_t *cnt = static_cast<const uint64_t *>(slot.dev);
     return bi::launch_bigmul_v_core(q->ctx->impl, q->tune, q->a, q->b, q->out, d, q->max_descs, cnt, q->limb_bits,
-                                    q->algo, q->scratch, st);
+                                    q->algo, q->scratch[s % kLanes], st);
 }
 
 }  // namespace
@@ -113,9 +127,15 @@ bi_status bi_stream_open(bi_ctx *ctx, const void *a, uint64_t a_limbs, const voi
     q->tune = ctx->impl.tune;
     q->st = static_cast<hipStream_t>(stream);
     const size_t dbytes = kHeader + max_descs * (sizeof(bi_desc) + sizeof(uint32_t));
-    if (hipMalloc(&q->scratch, bi::batch_scratch_bytes(max_descs, ctx->impl.num_cus)) != hipSuccess) {
-        release(q);
-        return set_error(BI_ENOMEM, "queue device buffers");
+    for (int l = 0; l < kLanes; ++l) {
+        if (hipMalloc(&q->scratch[l], bi::batch_scratch_bytes(max_descs, ctx->impl.num_cus)) != hipSuccess) {
+            release(q);
+            return set_error(BI_ENOMEM, "queue device buffers");
+        }
+        if (hipStreamCreateWithFlags(&q->lane_st[l], hipStreamNonBlocking) != hipSuccess) {
+            release(q);
+            return set_error(BI_EHIP, "lane stream creation");
+        }
     }
     if (hipStreamCreateWithFlags(&q->copy_st, hipStreamNonBlocking) != hipSuccess) {
         release(q);
@@ -137,7 +157,8 @@ bi_status bi_stream_open(bi_ctx *ctx, const void *a, uint64_t a_limbs, const voi
     hipError_t e = hipSuccess;
     for (Slot &s : q->slots)
         if (e == hipSuccess) e = hipMemsetAsync(s.dev, 0, kHeader, q->st);
-    if (e == hipSuccess) e = launch_burst(q, q->slots[0], q->st);
+    if (e == hipSuccess) e = launch_burst(q, 0, q->st);
+    // the lanes start after everything queued on the caller's stream so far
     if (e == hipSuccess) e = hipStreamSynchronize(q->st);
     if (e != hipSuccess) {
         release(q);
@@ -146,11 +167,12 @@ bi_status bi_stream_open(bi_ctx *ctx, const void *a, uint64_t a_limbs, const voi
     if (use_graph) {
         hipStream_t cap = nullptr;
         e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-        for (Slot &s : q->slots) {
+        for (int si = 0; si < kSlots; ++si) {
+            Slot &s = q->slots[si];
             hipGraph_t graph = nullptr;
             if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
             if (e != hipSuccess) break;
-            const hipError_t le = launch_burst(q, s, cap);
+            const hipError_t le = launch_burst(q, si, cap);
             e = hipStreamEndCapture(cap, &graph);
             if (le != hipSuccess) e = le;
             if (e == hipSuccess) e = hipGraphInstantiate(&s.exec, graph, nullptr, nullptr, 0);
@@ -189,6 +211,8 @@ bi_status bi_stream_submit(bi_stream *q, const bi_desc *descs, uint64_t count, u
     if (g.err != hipSuccess) return set_error(BI_EHIP, "hipSetDevice: %s", hipGetErrorString(g.err));
     const uint64_t t = q->next;
     Slot &s = q->slots[t % kSlots];
+    const int lane = int(t % kSlots) % kLanes;
+    const hipStream_t ls = q->lane_st[lane];
     if (s.ticket != ~0ull) {
         const hipError_t e = hipEventSynchronize(s.done);
         if (e != hipSuccess) return set_error(BI_EHIP, "staging slot wait: %s", hipGetErrorString(e));
@@ -214,20 +238,22 @@ bi_status bi_stream_submit(bi_stream *q, const bi_desc *descs, uint64_t count, u
     }
     hipError_t e = hipMemcpyAsync(s.dev, s.host, bytes, hipMemcpyHostToDevice, q->copy_st);
     if (e == hipSuccess) e = hipEventRecord(s.copied, q->copy_st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(q->st, s.copied, 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ls, s.copied, 0);
     if (e == hipSuccess) {
         if (q->graphs) {
-            e = hipGraphLaunch(s.exec, q->st);
+            e = hipGraphLaunch(s.exec, ls);
         } else {
             char *d = static_cast<char *>(s.dev);
             e = bi::launch_bigmul_v_binned(q->ctx->impl, q->tune, q->a, q->b, q->out,
                                            reinterpret_cast<const bi_desc *>(d + kHeader),
                                            reinterpret_cast<const uint32_t *>(d + kHeader + count * sizeof(bi_desc)),
                                            reinterpret_cast<const uint32_t *>(d + kCountsAt), counts, q->limb_bits,
-                                           q->algo, q->scratch, q->st);
+                                           q->algo, q->scratch[lane], ls);
         }
     }
-    if (e == hipSuccess) e = hipEventRecord(s.done, q->st);
+    if (e == hipSuccess) e = hipEventRecord(s.done, ls);
+    // the caller's stream sees the bursts complete in submission order
+    if (e == hipSuccess) e = hipStreamWaitEvent(q->st, s.done, 0);
     if (e != hipSuccess) return set_error(BI_EHIP, "burst launch: %s", hipGetErrorString(e));
     s.ticket = t;
     q->next = t + 1;

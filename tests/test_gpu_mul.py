@@ -296,6 +296,11 @@ def test_autotune_and_auto_dispatch(B, orc):
         algos = B.autotune(c)
         assert len(algos) == B.NUM_CLASSES and all(a in (1, 2, 3, 4, 5) for a in algos)
         assert B.tune_get(c) == algos
+        ragged = B.tune_get_list(c)
+        assert len(ragged) == B.NUM_CLASSES and all(a in (1, 2, 3, 4, 5) for a in ragged)
+        with pytest.raises(B.BigIntError):
+            B.tune_set_list(c, [9] + [1] * (B.NUM_CLASSES - 1))   # no such algorithm
+        assert B.tune_get_list(c) == ragged
         for q, w in B.tune_get_valu(c):
             assert q in (2, 4) and w in (1, 2, 4, 8, 16), (q, w)
         rng = np.random.default_rng(99)
@@ -325,6 +330,7 @@ def test_tune_save_load(B, orc, tmp_path):
         algos = B.autotune(c)
         valu = B.tune_get_valu(c)
         kara = B.tune_get_kara(c)
+        ragged = B.tune_get_list(c)
         assert all(k in (512, 1024, 2048) for k in kara)
         path = str(tmp_path / "tune.txt")
         B.tune_save(c, path)
@@ -334,8 +340,10 @@ def test_tune_save_load(B, orc, tmp_path):
     try:
         B.tune_set(d, [1] * B.NUM_CLASSES)
         B.tune_set_kara(d, [512] * B.NUM_CLASSES)
+        B.tune_set_list(d, [1] * B.NUM_CLASSES)
         B.tune_load(d, path)
         assert B.tune_get(d) == algos and B.tune_get_valu(d) == valu and B.tune_get_kara(d) == kara
+        assert B.tune_get_list(d) == ragged
         rng = np.random.default_rng(7)
         for n in (40, 700, 5000):
             a, b = patterned(rng, 3, n)
@@ -354,11 +362,12 @@ def test_tune_save_load(B, orc, tmp_path):
             B.tune_load(d, str(tmp_path / "missing.txt"))
         assert B.tune_get(d) == [2] * B.NUM_CLASSES
         # a version-1 file (no Karatsuba bases) loads with the default base
-        v1 = "\n".join(l for l in text.splitlines() if not l.startswith("kara_base")).replace(
+        v1 = "\n".join(l for l in text.splitlines() if not l.startswith(("kara_base", "list_algo"))).replace(
             "bigint-tune 2", "bigint-tune 1")
         open(other, "w").write(v1 + "\n")
         B.tune_load(d, other)
         assert B.tune_get(d) == algos and B.tune_get_kara(d) == [1024] * B.NUM_CLASSES
+        assert B.tune_get_list(d) == algos  # a version-1 file's table serves ragged batches too
         open(other, "w").write(text.replace("kara_base 512", "kara_base 500").replace("kara_base 1024", "kara_base 1000")
                                .replace("kara_base 2048", "kara_base 2000"))
         with pytest.raises(B.BigIntError):
