@@ -857,13 +857,10 @@ def bench_add_large(args):
 
 
 def large_ntt_block_words(n32):
-    """Block size (words) bigmul_large's NTT path picks by default: the
-    smallest power of two >= 512 that keeps the operands within 64 blocks
-    (the rule of large_ntt_auto_block in the library)."""
-    bw = 512
-    while bw < 8192 and -(-n32 // bw) > 64:
-        bw *= 2
-    return bw
+    """Block size (words) bigmul_large's NTT path picks by default, as the
+    library reports it."""
+    import paper_2405_14642_amd as B
+    return B.mul_large_plan(n32, 32, 0)[0] // 32
 
 
 def large_ntt_butterflies(n32, bw):

@@ -127,8 +127,8 @@ bi_status bigadd_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
  * out must not overlap a or b (BI_EALIAS); pointers limb-aligned (BI_ELIMB).
  * algo BI_MUL_AUTO or BI_MUL_NTT: a two-dimensional NTT convolution (n log n
  * work): the operands are cut into k <= 64 blocks of block_bits bits (a
- * power of two in [2^14, 2^18]; 0 lets the library choose the smallest of at
- * least 2^14 bits that gives at most 64 blocks), each block's 16-bit
+ * power of two in [2^14, 2^18]; 0 lets the library choose: the smallest of at
+ * least 2^16 bits that gives at most 32 blocks, or 2^18), each block's 16-bit
  * coefficients are transformed along the block (length 4 * block words)
  * and the results across the blocks (length 2k rounded up to a power of
  * two), modulo the two primes of BI_MUL_NTT; pointwise products, both
@@ -144,6 +144,10 @@ bi_status bigadd_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
  * unknown algorithm or block size.  BI_ENOMEM if the context's scratch
  * cannot grow.  Asynchronous like every call.
  */
+/* The block size (bits) and block count bigmul_large picks for block_bits = 0
+ * (host only; errors as bigmul_large's size and algorithm checks). */
+bi_status bi_mul_large_plan(uint64_t n_limbs, uint32_t limb_bits, int algo, uint32_t *block_bits, uint32_t *blocks);
+
 bi_status bigmul_large(bi_ctx *ctx, const void *a, const void *b, void *out, uint64_t n_limbs, uint32_t limb_bits,
                        int algo, uint32_t block_bits, void *stream);
 

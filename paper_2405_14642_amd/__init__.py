@@ -33,7 +33,7 @@ EXPORTS = ("bi_ctx_create", "bi_ctx_destroy", "bi_status_str", "bi_last_error",
            "bi_stream_close", "bi_fused", "bi_tune_get_valu",
            "bi_tune_set_valu", "bigadd_large", "bigmul_large", "bi_tune_save",
            "bi_tune_load", "bi_mul_plan", "bigmul_noalloc", "bi_tune_get_kara", "bi_tune_set_kara",
-           "bi_tune_get_list", "bi_tune_set_list")
+           "bi_tune_get_list", "bi_tune_set_list", "bi_mul_large_plan")
 NUM_CLASSES = 10
 
 
@@ -99,11 +99,12 @@ def _load():
     L.bi_tune_get_valu.argtypes = [P, P, P, U32]
     L.bi_tune_set_valu.argtypes = [P, P, P, U32]
     L.bi_mul_plan.argtypes = [P, U32, U32, I, P]
+    L.bi_mul_large_plan.argtypes = [U64, U32, I, ctypes.POINTER(U32), ctypes.POINTER(U32)]
     L.bi_tune_get_list.argtypes = [P, P, U32]
     L.bi_tune_set_list.argtypes = [P, P, U32]
     L.bi_tune_get_kara.argtypes = [P, P, U32]
     L.bi_tune_set_kara.argtypes = [P, P, U32]
-    for f in (L.bi_tune_get_list, L.bi_tune_set_list, L.bi_tune_get_kara, L.bi_tune_set_kara, L.bi_mul_plan, L.bigmul_noalloc, L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field, L.bi_autotune,
+    for f in (L.bi_mul_large_plan, L.bi_tune_get_list, L.bi_tune_set_list, L.bi_tune_get_kara, L.bi_tune_set_kara, L.bi_mul_plan, L.bigmul_noalloc, L.bi_ctx_create, L.bigadd, L.bigmul, L.bigadd_v, L.bigmul_v, L.bi_ntt_field, L.bi_autotune,
               L.bi_tune_get, L.bi_tune_set, L.bi_stream_open, L.bi_stream_submit, L.bi_stream_poll,
               L.bi_stream_wait, L.bi_stream_close, L.bi_fused, L.bi_tune_get_valu,
               L.bi_tune_set_valu, L.bigadd_large, L.bigmul_large, L.bi_tune_save, L.bi_tune_load):
@@ -300,6 +301,13 @@ def mul_plan(ctx, n_limbs, limb_bits=32, algo=MUL_AUTO):
     info = MulPlanInfo()
     _check(lib.bi_mul_plan(_h(ctx), n_limbs, limb_bits, algo, ctypes.byref(info)))
     return {k: getattr(info, k) for k, _ in MulPlanInfo._fields_}
+
+
+def mul_large_plan(n_limbs, limb_bits=32, algo=MUL_AUTO):
+    """(block_bits, blocks) bigmul_large picks by default."""
+    bb, k = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib.bi_mul_large_plan(n_limbs, limb_bits, int(algo), ctypes.byref(bb), ctypes.byref(k)))
+    return bb.value, k.value
 
 
 def tune_get_list(ctx):

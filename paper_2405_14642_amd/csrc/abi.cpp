@@ -172,6 +172,22 @@ bi_status bigadd_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
     return BI_OK;
 }
 
+bi_status bi_mul_large_plan(uint64_t n_limbs, uint32_t limb_bits, int algo, uint32_t *block_bits, uint32_t *blocks) {
+    if (limb_bits != 32 && limb_bits != 64) return fail(BI_ELIMB, "limb_bits must be 32 or 64 (got %u)", limb_bits);
+    if (n_limbs == 0) return fail(BI_EINVAL, "n_limbs must be >= 1");
+    if (n_limbs > BI_MAX_LARGE_MUL_BITS / limb_bits)
+        return fail(BI_ESIZE, "n_limbs * limb_bits exceeds %u bits (n_limbs = %llu)", BI_MAX_LARGE_MUL_BITS,
+                    (unsigned long long)n_limbs);
+    if (algo < BI_MUL_AUTO || algo > BI_MUL_KARATSUBA) return fail(BI_EINVAL, "unknown algorithm %d", algo);
+    if (!block_bits || !blocks) return fail(BI_EINVAL, "NULL argument");
+    const uint64_t n32 = n_limbs * (limb_bits / 32);
+    const bool two_dim = algo == BI_MUL_AUTO || algo == BI_MUL_NTT;
+    const uint32_t bw = two_dim ? bi::large_ntt_auto_block(n32) : bi::large_mul_auto_block(n32);
+    *block_bits = 32 * bw;
+    *blocks = uint32_t((n32 + bw - 1) / bw);
+    return BI_OK;
+}
+
 bi_status bigmul_large(bi_ctx *ctx, const void *a, const void *b, void *out, uint64_t n_limbs, uint32_t limb_bits,
                        int algo, uint32_t block_bits, void *stream) {
     if (limb_bits != 32 && limb_bits != 64) return fail(BI_ELIMB, "limb_bits must be 32 or 64 (got %u)", limb_bits);

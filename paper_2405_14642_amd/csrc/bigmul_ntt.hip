@@ -1161,11 +1161,13 @@ hipError_t launch_cols(uint32_t R, const NttConst &K, uint32_t *tr, uint32_t M, 
 
 }  // namespace
 
-// Blocks of 2^(9..13) words: as many as the column transform takes (64), so
-// the row transforms fill the GPU, on blocks of at least 512 words.
+// Blocks of 2^(11..13) words: the smallest that gives at most 32 blocks (64
+// at 8192 words).  Measured on one product each (MI355X): 2^19 / 2^20 bits
+// fastest with 2048-word blocks (58 / 66 us against 76 / 103 with 512-word
+// ones), 2^22 bits with 4096 (104 against 120 with 2048 and 111 with 8192).
 uint32_t large_ntt_auto_block(uint64_t n32) {
-    uint32_t bw = 512;
-    while (bw < kMaxLimbs32 && (n32 + bw - 1) / bw > kLargeNttMaxBlocks) bw *= 2;
+    uint32_t bw = 2048;
+    while (bw < kMaxLimbs32 && (n32 + bw - 1) / bw > kLargeNttMaxBlocks / 2) bw *= 2;
     return bw;
 }
 

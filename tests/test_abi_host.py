@@ -260,3 +260,25 @@ def test_binding_checks_tensor_arguments(B):
         B.bigmul_v(None, x, x, x, torch.zeros(63, dtype=torch.uint8), 2, 32)
     with pytest.raises(ValueError, match="device tensor"):
         B.bigmul(None, a, a, prod)                           # right sizes, host memory
+
+
+def test_mul_large_plan(B):
+    """The default block of bigmul_large: on the NTT path the smallest of at
+    least 2^16 bits with at most 32 blocks (2^18 bits up to 64 blocks at
+    2^24 bits); block products 2^16 bits up to 2^20-bit operands, 2^18
+    above; argument errors as bigmul_large's."""
+    for bits, want in ((1 << 19, 1 << 16), (1 << 20, 1 << 16), (1 << 21, 1 << 16), (1 << 22, 1 << 17),
+                       ((1 << 22) + 32, 1 << 18), (1 << 24, 1 << 18)):
+        bb, k = B.mul_large_plan(bits // 32, 32, 0)
+        assert bb == want and k == -(-bits // bb) and k <= 64, (bits, bb, k)
+        if bits % 64 == 0:
+            assert B.mul_large_plan(bits // 64, 64, 3) == (bb, k)
+    assert B.mul_large_plan(1 << 15, 32, 2) == (1 << 16, 16)
+    assert B.mul_large_plan((1 << 15) + 1, 32, 5)[0] == 1 << 18
+    assert B.lib.bi_mul_large_plan(0, 32, 0, None, None) == -1
+    with pytest.raises(B.BigIntError):
+        B.mul_large_plan((1 << 19) + 1, 32, 0)   # beyond 2^24 bits
+    with pytest.raises(B.BigIntError):
+        B.mul_large_plan(100, 48, 0)
+    with pytest.raises(B.BigIntError):
+        B.mul_large_plan(100, 32, 9)
