@@ -27,7 +27,20 @@
 // Work split.  Supertile st needs the u in [32 st - nb + 1, 32 st + 31]
 // clipped to [0, nb].  Each wave owns two adjacent supertiles, whose ranges
 // coincide but for 32 steps at each end, keeps their accumulators in
-// registers (no atomics), and reads each A operand once for both.
+// registers (no atomics), and reads each A operand once for both: three
+// 1 KiB LDS reads per two MFMAs, the traffic that bounds the loop.
+//
+// 1024-limb products (nb = 128, eight supertiles) take a k-major order
+// instead.  Since B(st + i, u) = B(st, u - 32 i), a wave that owns four
+// consecutive supertiles sb + i and walks u = k + 32 m with the residue k
+// outer needs one A operand per m and one B operand beta_j = B(sb, k + 32 j)
+// per j: supertile sb + i at m takes A(k + 32 m) and beta_(m - i), so each
+// read serves up to four MFMAs (0.8 KiB per MFMA).  At nb = 128 the in-band
+// (i, m) of every residue form a fixed triangle: m <= i for supertiles 0-3
+// (k = 0 .. 31), m >= i for supertiles 4-7 (k = 1 .. 32).  The two waves of
+// a group take alternate residues and each finalises two of the four
+// supertiles, adding the other wave's 64-bit partial word sums, passed
+// through LDS, to its own.
 //
 // Normalisation.  A lane holds, for each of its output words w, the four
 // coefficients of bytes 4w .. 4w+3.  V_w = sum_e c_e 2^(8e) + 2^63 - 2^31 [w > 0]
@@ -36,6 +49,7 @@
 // lies above the product.  L + H is added with the workgroup ballot-adder, as
 // for the other products (Section 3.1 combines its low and high parts the
 // same way).
+#include <algorithm>
 #include <atomic>
 
 #include "bi_common.hpp"
@@ -134,6 +148,45 @@ __device__ __forceinline__ void recode_chunks(Chunks &x, uint32_t nchunks, uint3
     }
 }
 
+// k-major MFMA steps of a 1024-limb product for one group of four
+// supertiles sb .. sb + 3 (HIGH: sb = 4), residues k = k0, k0 + 2, ...
+// bbs: this lane's B entry of supertile sb at step 0.  Supertile sb + i
+// accumulates into acc[i ^ X]: with X = 2 the second wave of the group also
+// holds the two supertiles it finalises in acc[0..1].  Every read lies in
+// band, hence inside the padded arrays.
+template <bool HIGH, int X>
+__device__ __forceinline__ void mfma_kmajor_1024(const uint8_t *lds, uint32_t oA, const uint8_t *bbs, int32_t k0,
+                                                 v16i (&acc)[4]) {
+    constexpr int32_t J0 = HIGH ? 0 : -3;  // beta_j for j = J0 .. J0 + 3
+    for (int32_t k = k0; k < (HIGH ? 33 : 32); k += 2) {
+        v4i A[4], Bt[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) A[m] = load_a(lds, oA, k + 32 * m);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Bt[j] = *reinterpret_cast<const v4i *>(bbs - 16 * (k + 32 * (j + J0)));
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (HIGH ? m >= i : m <= i)
+                    acc[i ^ X] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[m], Bt[m - i - J0], acc[i ^ X], 0, 0, 0);
+    }
+}
+
+// Sum_e c_e 2^(8e) of output word j of a lane's accumulator block.
+__device__ __forceinline__ int64_t word_sum(const v16i &a, int j) {
+    return int64_t(a[4 * j]) + (int64_t(a[4 * j + 1]) << 8) + (int64_t(a[4 * j + 2]) << 16) +
+           (int64_t(a[4 * j + 3]) << 24);
+}
+
+// Byte offset of the partial-sum exchange between the two waves of a group
+// (NW * 4 KiB: per wave 2 supertiles x 4 words x 64 lanes x 8 bytes): the
+// windows of a, dead by then, when they are large enough, else past the
+// layout.
+__host__ __device__ inline uint32_t xchg_offset(const MfmaLayout &l, uint32_t nw) {
+    return nw * 4096u <= l.a0 ? 0u : l.total;
+}
+
 }  // namespace
 
 // OCC: minimum waves per SIMD the registers are sized for (1: no bound).
@@ -141,7 +194,9 @@ __device__ __forceinline__ void recode_chunks(Chunks &x, uint32_t nchunks, uint3
 // workgroups per SIMD, their per-product phases are latency chains, and the
 // unbounded kernel's 180 registers allow only 2.  Larger ones keep the
 // compiler's choice.
-template <int NW, int OCC, class Src>
+// KM: every product has 1017-1024 limbs (n32p = 1024) and takes the k-major
+// MFMA order (NW = 4).
+template <int NW, int OCC, class Src, bool KM>
 __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
     extern __shared__ __align__(16) uint8_t lds[];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = wave_in_block();
@@ -211,60 +266,95 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
         // next pair's operands, in flight during the products
         if (pair + gridDim.x < count) fetch_chunks(src.get(pair + gridDim.x), 64 * wave + lane, x);
 
-        // 3. MFMA: this wave's adjacent supertiles s0 = 2 p and s1 = 2 p + 1.
-        //    Their u-ranges overlap except for 32 steps at each end; inside
-        //    the overlap both share every A operand (3 LDS reads per 2
-        //    MFMAs).  p rotates with the pair index so that every SIMD sees
-        //    the light (band-edge) and heavy (middle) supertiles equally.
+        // 3. MFMA.  Wave role p (rotating with the pair so that every SIMD
+        //    sees the light band-edge and heavy middle supertiles) finalises
+        //    supertiles s0 = 2 p and s1 = 2 p + 1.
         const uint32_t nst = (n32p + 127) / 128, npt = (nst + 1) / 2;
         const uint32_t r = lane & 31u, g = lane >> 5;
         const uint32_t pw = (wave + uint32_t(pair % NW)) % NW;
         const uint32_t s0 = 2 * pw, s1 = s0 + 1;
         const bool has0 = pw < npt, has1 = has0 && s1 < nst;
+        const uint32_t oA = 8 * (r + kPA - 16 * g - 15);
         uint32_t Lo[2][4], Hi[2][4];
-        if (has0) {
-            const uint32_t oA = 8 * (r + kPA - 16 * g - 15);
-            const uint8_t *bb0 = bpl + g * 16 * NBE + 16 * (32 * s0 + r + kBPad);
-            const uint8_t *bb1 = bb0 + 16 * 32;
-            const int32_t lo0 = max(0, int32_t(32 * s0) - int32_t(nb) + 1);
-            const int32_t hi0 = min(int32_t(nb), int32_t(32 * s0 + 31)) + 1;
-            const int32_t lo1 = has1 ? max(0, int32_t(32 * s1) - int32_t(nb) + 1) : hi0;
-            const int32_t hi1 = has1 ? min(int32_t(nb), int32_t(32 * s1 + 31)) + 1 : hi0;
-            v16i acc[2] = {};
-            mfma_steps<1>(lo0, min(lo1, hi0), lds, oA, bb0, bb1, acc);
-            if (has1) {
-                mfma_steps<3>(lo1, hi0, lds, oA, bb0, bb1, acc);
-                mfma_steps<2>(max(hi0, lo1), hi1, lds, oA, bb0, bb1, acc);
-            }
+        // Lo / Hi of supertile st from its coefficient sums acc (plus the
+        // word sums ext of the other wave, k-major order)
+        auto finalise = [&](const v16i &acc, uint32_t st, const int64_t (&ext)[4], uint32_t (&lo4)[4],
+                            uint32_t (&hi4)[4]) {
             // acc[4j + i] at lane (r, g) is coefficient 32 K + 8 j + 4 g + i,
             // K = 32 st + r: the four bytes of word w = 8 K + 2 j + g.
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const uint32_t st = s0 + uint32_t(t);
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t w = 256 * st + 8 * r + 2 * uint32_t(j) + g;
+                int32_t c[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t w = 256 * st + 8 * r + 2 * uint32_t(j) + g;
-                    int32_t c[4];
+                for (int e = 0; e < 4; ++e) c[e] = acc[4 * j + e];
+                if (w >= n32p && w < 2 * n32p && (tA | tB)) {
+                    const uint32_t m = w - n32p, cc = m >> 2;
+                    const uint32_t aw = *reinterpret_cast<const uint32_t *>(adg + kPA + 4 * m);
+                    const uint32_t bw = *reinterpret_cast<const uint32_t *>(
+                        bpl + (cc & 1u) * 16 * NBE + 16 * (kBPad + (cc >> 1)) + 4 * (3 - (m & 3u)));
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) c[e] = acc[t][4 * j + e];
-                    if (w >= n32p && w < 2 * n32p && (tA | tB)) {
-                        const uint32_t m = w - n32p, cc = m >> 2;
-                        const uint32_t aw = *reinterpret_cast<const uint32_t *>(adg + kPA + 4 * m);
-                        const uint32_t bw = *reinterpret_cast<const uint32_t *>(
-                            bpl + (cc & 1u) * 16 * NBE + 16 * (kBPad + (cc >> 1)) + 4 * (3 - (m & 3u)));
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            c[e] += int32_t(tA) * sbyte(bw, 3 - e) + int32_t(tB) * sbyte(aw, e);
-                    }
-                    uint64_t V = uint64_t(int64_t(c[0])) + (uint64_t(int64_t(c[1])) << 8) +
-                                 (uint64_t(int64_t(c[2])) << 16) + (uint64_t(int64_t(c[3])) << 24);
-                    V += (1ull << 63) - (w > 0 ? (1ull << 31) : 0ull);
-                    Lo[t][j] = uint32_t(V);
-                    Hi[t][j] = uint32_t(V >> 32);
+                    for (int e = 0; e < 4; ++e)
+                        c[e] += int32_t(tA) * sbyte(bw, 3 - e) + int32_t(tB) * sbyte(aw, e);
                 }
+                uint64_t V = uint64_t(ext[j]) + uint64_t(int64_t(c[0])) + (uint64_t(int64_t(c[1])) << 8) +
+                             (uint64_t(int64_t(c[2])) << 16) + (uint64_t(int64_t(c[3])) << 24);
+                V += (1ull << 63) - (w > 0 ? (1ull << 31) : 0ull);
+                lo4[j] = uint32_t(V);
+                hi4[j] = uint32_t(V >> 32);
+            }
+        };
+        if constexpr (KM) {
+            // group pw / 2 = supertiles 4 (pw / 2) + i, residues of parity
+            // pw % 2; all eight supertiles exist (has0 = has1 = true)
+            static_assert(NW == 4, "the k-major order takes four waves");
+            const uint32_t grp = pw >> 1, q = pw & 1u;
+            const uint8_t *bbs = bpl + g * 16 * NBE + 16 * (32 * 4 * grp + r + kBPad);
+            v16i acc[4] = {};
+            if (grp == 0) {
+                if (q == 0) mfma_kmajor_1024<false, 0>(lds, oA, bbs, 0, acc);
+                else mfma_kmajor_1024<false, 2>(lds, oA, bbs, 1, acc);
+            } else {
+                if (q == 0) mfma_kmajor_1024<true, 0>(lds, oA, bbs, 1, acc);
+                else mfma_kmajor_1024<true, 2>(lds, oA, bbs, 2, acc);
+            }
+            __syncthreads();  // every wave is done with the windows of a
+            int64_t *xb = reinterpret_cast<int64_t *>(lds + xchg_offset(lo, NW));
+            // slot (pw, t, j): the sender's partial sums of word j of the
+            // receiver's supertile t, 64 lanes of 8 bytes
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) xb[((pw * 2 + t) * 4 + j) * 64 + lane] = word_sum(acc[2 + t], j);
+            __syncthreads();
+            const uint32_t peer = pw ^ 1u;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                int64_t ext[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) ext[j] = xb[((peer * 2 + t) * 4 + j) * 64 + lane];
+                finalise(acc[t], s0 + uint32_t(t), ext, Lo[t], Hi[t]);
+            }
+        } else {
+            if (has0) {
+                const uint8_t *bb0 = bpl + g * 16 * NBE + 16 * (32 * s0 + r + kBPad);
+                const uint8_t *bb1 = bb0 + 16 * 32;
+                const int32_t lo0 = max(0, int32_t(32 * s0) - int32_t(nb) + 1);
+                const int32_t hi0 = min(int32_t(nb), int32_t(32 * s0 + 31)) + 1;
+                const int32_t lo1 = has1 ? max(0, int32_t(32 * s1) - int32_t(nb) + 1) : hi0;
+                const int32_t hi1 = has1 ? min(int32_t(nb), int32_t(32 * s1 + 31)) + 1 : hi0;
+                v16i acc[2] = {};
+                mfma_steps<1>(lo0, min(lo1, hi0), lds, oA, bb0, bb1, acc);
+                if (has1) {
+                    mfma_steps<3>(lo1, hi0, lds, oA, bb0, bb1, acc);
+                    mfma_steps<2>(max(hi0, lo1), hi1, lds, oA, bb0, bb1, acc);
+                }
+                const int64_t none[4] = {};
+#pragma unroll
+                for (int t = 0; t < 2; ++t) finalise(acc[t], s0 + uint32_t(t), none, Lo[t], Hi[t]);
             }
         }
-        __syncthreads();  // every wave is done with the windows of a
+        __syncthreads();  // every wave is done with the windows of a and the exchange
 
         // 4. L and H (aliasing the windows), then product = L + H
         const uint32_t W = 2 * n32p;
@@ -297,27 +387,35 @@ static uint32_t mfma_waves(uint32_t nmax) {
     return h <= 1 ? 1 : h <= 2 ? 2 : 4;
 }
 
-template <int NW, int OCC, class Src>
+// Dynamic LDS bytes of a launch whose products have at most nmax limbs:
+// the largest layout, with the partial-sum exchange where it lies past it.
+template <int NW, bool KM>
+static uint32_t mfma_lds_bytes(uint32_t nmax) {
+    const MfmaLayout l = mfma_layout((nmax + 7) & ~7u);
+    return KM ? std::max(l.total, xchg_offset(l, NW) + NW * 4096u) : l.total;
+}
+
+template <int NW, int OCC, class Src, bool KM = false>
 static hipError_t launch_nw(const Src &src, uint32_t nmax, uint64_t count, hipStream_t st, int num_cus) {
-    const MfmaLayout lo = mfma_layout((nmax + 7) & ~7u);
-    const void *fn = reinterpret_cast<const void *>(&bigmul_mfma_kernel<NW, OCC, Src>);
+    const uint32_t lds_bytes = mfma_lds_bytes<NW, KM>(nmax);
+    const void *fn = reinterpret_cast<const void *>(&bigmul_mfma_kernel<NW, OCC, Src, KM>);
     // (LDS bytes << 32 | resident workgroups per CU) of the last launch shape
     static std::atomic<uint64_t> occ{0}, lds_set{0};
     hipError_t e = lds_limit_once(fn, lds_set);
     if (e != hipSuccess) return e;
     uint64_t o = occ.load(std::memory_order_relaxed);
-    if ((o >> 32) != lo.total) {
+    if ((o >> 32) != lds_bytes) {
         int nblk = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, fn, 64 * NW, lo.total);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, fn, 64 * NW, lds_bytes);
         if (e != hipSuccess) return e;
-        o = (uint64_t(lo.total) << 32) | uint32_t(nblk < 1 ? 1 : nblk);
+        o = (uint64_t(lds_bytes) << 32) | uint32_t(nblk < 1 ? 1 : nblk);
         occ.store(o, std::memory_order_relaxed);
     }
     // persistent workgroups: each loops over pairs, prefetching the next
     const uint64_t cap = uint64_t(uint32_t(o)) * uint64_t(num_cus > 0 ? num_cus : 1);
     const uint32_t grid = uint32_t(count < cap ? count : cap);
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((bigmul_mfma_kernel<NW, OCC, Src>), dim3(grid), dim3(64 * NW), lo.total, st, src);
+    hipLaunchKernelGGL((bigmul_mfma_kernel<NW, OCC, Src, KM>), dim3(grid), dim3(64 * NW), lds_bytes, st, src);
     return hipGetLastError();
 }
 
@@ -339,7 +437,10 @@ static hipError_t launch_mfma(const Src &src, uint32_t nmax, uint64_t count, hip
 hipError_t launch_bigmul_mfma(const uint32_t *a, const uint32_t *b, uint32_t *c, uint32_t n32, uint64_t batch,
                               hipStream_t st, int num_cus) {
     if (batch == 0) return hipSuccess;
-    return launch_mfma(UniformInst{a, b, c, n32, batch}, n32, batch, st, num_cus);
+    const UniformInst src{a, b, c, n32, batch};
+    // 1017-1024 limbs: eight supertiles of 128 digit blocks, the k-major order
+    if (((n32 + 7) & ~7u) == 1024) return launch_nw<4, 3, UniformInst, true>(src, n32, batch, st, num_cus);
+    return launch_mfma(src, n32, batch, st, num_cus);
 }
 
 hipError_t launch_bigmul_mfma_list(const ListInst &src, uint32_t nmax, uint64_t count_max, hipStream_t st,
