@@ -288,7 +288,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
         const uint32_t s0 = 2 * pw, s1 = s0 + 1;
         const bool has0 = pw < npt, has1 = has0 && s1 < nst;
         const uint32_t oA = 8 * (r + kPA - 16 * g - 15);
-        uint32_t Lo[2][4], Hi[2][4];
+        uint32_t Lo[2][4] = {}, Hi[2][4] = {};
         // Lo / Hi of supertile st from its coefficient sums acc (plus the
         // word sums ext of the other wave, k-major order)
         auto finalise = [&](const v16i &acc, uint32_t st, const int64_t (&ext)[4], uint32_t (&lo4)[4],
@@ -367,102 +367,80 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
                 for (int t = 0; t < 2; ++t) finalise(acc[t], s0 + uint32_t(t), none, Lo[t], Hi[t]);
             }
         }
-        if constexpr (KM) {
-            // 4. product = L + H in registers.  Lane (r, g) holds the low and
-            //    high words of V_w for w = 256 st + 8 r + 2 j + g; two lane
-            //    swaps (r, 0) <-> (r, 1) give it words 8 r + 4 g + 0..3 of the
-            //    supertile, chunk 2 r + g of row st of the product, whose
-            //    high addends are the high words of the word below each.
-            uint32_t x[2][4], hv[2][4], y[2][4];
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const auto l02 = __builtin_amdgcn_permlane32_swap(Lo[t][0], Lo[t][2], false, false);
-                const auto l13 = __builtin_amdgcn_permlane32_swap(Lo[t][1], Lo[t][3], false, false);
-                const auto h02 = __builtin_amdgcn_permlane32_swap(Hi[t][0], Hi[t][2], false, false);
-                const auto h13 = __builtin_amdgcn_permlane32_swap(Hi[t][1], Hi[t][3], false, false);
-                x[t][0] = l02[0]; x[t][1] = l02[1]; x[t][2] = l13[0]; x[t][3] = l13[1];
-                hv[t][0] = h02[0]; hv[t][1] = h02[1]; hv[t][2] = h13[0]; hv[t][3] = h13[1];
-            }
-            // the word below chunk 2 r + g: chunk 2 r + g - 1, at lane r (g = 1)
-            // or r - 1 + 32 (g = 0); below row st's chunk 0, the last word
-            // of row st - 1 (the other row of this wave, or the wave below)
-            uint32_t *bnd = reinterpret_cast<uint32_t *>(lds + 16384);  // dead window space
-            const uint32_t top1 = __builtin_amdgcn_readlane(hv[1][3], 63);
-            if (lane == 0) bnd[pw] = top1;
-            const int src = int(g ? lane - 32 : lane + 31);
-            uint32_t below[2];
-#pragma unroll
-            for (int t = 0; t < 2; ++t) below[t] = __shfl(hv[t][3], src);
-            __syncthreads();
-            if (lane == 0) {
-                below[0] = pw > 0 ? bnd[pw - 1] : 0u;
-                below[1] = __builtin_amdgcn_readlane(hv[0][3], 63);
-            }
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                y[t][0] = below[t];
-                y[t][1] = hv[t][0];
-                y[t][2] = hv[t][1];
-                y[t][3] = hv[t][2];
-            }
-            // carry scan over the wave's two rows in chunk order, then over
-            // the waves (rows 2 pw, 2 pw + 1 lie above those of waves < pw)
-            const uint32_t cpos = 2 * r + g;
-            uint32_t sm[2][4];
-            uint64_t G[2], Pm[2];
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const uint32_t gc = add_words<4>(x[t], y[t], sm[t]);
-                G[t] = lanes_to_chunks(ballot(gc != 0));
-                Pm[t] = lanes_to_chunks(ballot(all_ones<4>(sm[t])));
-            }
-            uint32_t cin = 0, allp = 1;
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                cin = wave_carry(G[t], Pm[t], cin).out;
-                allp &= Pm[t] == ~0ull ? 1u : 0u;
-            }
-            uint32_t *csum = summary + 8;
-            if (lane == 0) csum[pw] = cin | (allp << 1);
-            __syncthreads();
-            cin = 0;
-            for (uint32_t v = 0; v < pw; ++v) {
-                const uint32_t sv = csum[v];
-                cin = (sv & 1u) | ((sv >> 1) & cin);
-            }
-            const GlobalSink sink{in.c, 2 * n32, (reinterpret_cast<uintptr_t>(in.c) & 15) == 0};
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const WaveCarry wc = wave_carry(G[t], Pm[t], cin);
-                add_carry_words<4>(sm[t], uint32_t(wc.into >> cpos) & 1u);
-                cin = wc.out;
-                const uint32_t c = 64 * (s0 + uint32_t(t)) + cpos;
-                if (4 * c < 2 * n32) sink(c, sm[t]);
-            }
-            __syncthreads();  // summary and the window space are free for the next pair
-            continue;
-        }
-        __syncthreads();  // every wave is done with the windows of a and the exchange
-
-        // 4. L and H (aliasing the windows), then product = L + H
-        const uint32_t W = 2 * n32p;
-        uint32_t *L = reinterpret_cast<uint32_t *>(lds);
-        uint32_t *H = L + W;
+        // 4. product = L + H in registers.  Lane (r, g) holds the low and
+        //    high words of V_w for w = 256 st + 8 r + 2 j + g; two lane swaps
+        //    (r, 0) <-> (r, 1) give it words 8 r + 4 g + 0..3 of supertile
+        //    st, chunk 2 r + g of row st of the product, whose high addends
+        //    are the high words of the word below each.  Wave pw owns rows
+        //    s0, s1 (absent rows, and words at or above 2 n32p, lie above
+        //    every stored word and only carry upwards).
+        uint32_t x[2][4], hv[2][4], y[2][4];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            const uint32_t st = s0 + uint32_t(t);
-            if (!(t == 0 ? has0 : has1)) continue;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t w = 256 * st + 8 * r + 2 * uint32_t(j) + g;
-                if (w < W) L[w] = Lo[t][j];
-                if (w + 1 < W) H[w + 1] = Hi[t][j];
-            }
+            const auto l02 = __builtin_amdgcn_permlane32_swap(Lo[t][0], Lo[t][2], false, false);
+            const auto l13 = __builtin_amdgcn_permlane32_swap(Lo[t][1], Lo[t][3], false, false);
+            const auto h02 = __builtin_amdgcn_permlane32_swap(Hi[t][0], Hi[t][2], false, false);
+            const auto h13 = __builtin_amdgcn_permlane32_swap(Hi[t][1], Hi[t][3], false, false);
+            x[t][0] = l02[0]; x[t][1] = l02[1]; x[t][2] = l13[0]; x[t][3] = l13[1];
+            hv[t][0] = h02[0]; hv[t][1] = h02[1]; hv[t][2] = h13[0]; hv[t][3] = h13[1];
         }
-        if (tid == 0) H[0] = 0;
+        // the word below chunk 2 r + g: chunk 2 r + g - 1, at lane r (g = 1)
+        // or r - 1 + 32 (g = 0); below row st's chunk 0, the last word of
+        // row st - 1 (the other row of this wave, or the wave below's, passed
+        // in the recode summary words, dead by now)
+        uint32_t *bnd = summary;
+        if (lane == 0) bnd[pw] = __builtin_amdgcn_readlane(hv[1][3], 63);
+        const int src = int(g ? lane - 32 : lane + 31);
+        uint32_t below[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) below[t] = __shfl(hv[t][3], src);
         __syncthreads();
-        wg_add_rows<NW>(LHSrc{L, H, 2 * n32}, in.c, 2 * n32, summary + 8);
+        if (lane == 0) {
+            below[0] = pw > 0 ? bnd[pw - 1] : 0u;
+            below[1] = __builtin_amdgcn_readlane(hv[0][3], 63);
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            y[t][0] = below[t];
+            y[t][1] = hv[t][0];
+            y[t][2] = hv[t][1];
+            y[t][3] = hv[t][2];
+        }
+        // carry scan over the wave's two rows in chunk order, then over the
+        // waves (rows 2 pw, 2 pw + 1 lie above those of waves < pw)
+        const uint32_t cpos = 2 * r + g;
+        uint32_t sm[2][4];
+        uint64_t G[2], Pm[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const uint32_t gc = add_words<4>(x[t], y[t], sm[t]);
+            G[t] = lanes_to_chunks(ballot(gc != 0));
+            Pm[t] = lanes_to_chunks(ballot(all_ones<4>(sm[t])));
+        }
+        uint32_t cin = 0, allp = 1;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            cin = wave_carry(G[t], Pm[t], cin).out;
+            allp &= Pm[t] == ~0ull ? 1u : 0u;
+        }
+        uint32_t *csum = summary + 8;
+        if (lane == 0) csum[pw] = cin | (allp << 1);
         __syncthreads();
+        cin = 0;
+        for (uint32_t v = 0; v < pw; ++v) {
+            const uint32_t sv = csum[v];
+            cin = (sv & 1u) | ((sv >> 1) & cin);
+        }
+        const GlobalSink sink{in.c, 2 * n32, (reinterpret_cast<uintptr_t>(in.c) & 15) == 0};
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const WaveCarry wc = wave_carry(G[t], Pm[t], cin);
+            add_carry_words<4>(sm[t], uint32_t(wc.into >> cpos) & 1u);
+            cin = wc.out;
+            const uint32_t c = 64 * (s0 + uint32_t(t)) + cpos;
+            if ((t == 0 ? has0 : has1) && 4 * c < 2 * n32) sink(c, sm[t]);
+        }
+        __syncthreads();  // the summary words are free for the next pair
     }
 }
 
