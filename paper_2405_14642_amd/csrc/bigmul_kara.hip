@@ -242,50 +242,68 @@ __global__ __launch_bounds__(NW * 64) void kara_combine_kernel(Dst dst, const ui
     const InstRef o = dst.get(q);
     const uint32_t W = 2 * o.n, h = kara_half(o.n);  // W <= 4 h
     const uint32_t *z0 = z + 3 * q * 2 * hs, *z2 = z0 + 2 * hs, *dv = z2 + 2 * hs;
-    const bool sub = sg[2 * q] == sg[2 * q + 1];
     const uint32_t lane = lane_id(), w = wave_in_block();
     constexpr uint64_t kBias = uint64_t(1) << 63;
-    // V_k for one word (the word below a lane-0 chunk)
-    auto col = [&](uint32_t k) -> uint64_t {
-        uint64_t v = kBias - (k > 0 ? (uint64_t(1) << 31) : 0) + (k < 2 * h ? z0[k] : z2[k - 2 * h]);
-        if (k >= h && k < 3 * h) {
-            const uint32_t m = k - h;
-            v += uint64_t(z0[m]) + z2[m];
-            v = sub ? v - dv[m] : v + dv[m];
-        }
-        return v;
-    };
-    uint32_t xs[R][4], ys[R][4];
+    // Every read first, so that they overlap: per row the chunk's z0 / z2
+    // words and, inside the middle band [h, 3 h), z0, z2 and D at k0 - h
+    // (addresses outside the chunk's regions are clamped into the slots and
+    // their words unused); and for lane 0 of the wave's first row the terms
+    // of the word below it, the wave below's last word.
+    const uint8_t sgn0 = sg[2 * q], sgn1 = sg[2 * q + 1];
+    uint4 A[R], Bm[R], Cm[R], Dm[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const uint32_t k0 = 4 * (64 * (w * R + uint32_t(i)) + lane);
-        uint64_t V[4] = {0, 0, 0, 0};
-        if (k0 < W) {  // k0 + 3 < 4 h; h is a multiple of 4, so the chunk lies in one region
-            const uint4 A = k0 < 2 * h ? ld4(z0 + k0) : ld4(z2 + (k0 - 2 * h));
-            V[0] = kBias + A.x;
-            V[1] = kBias + A.y;
-            V[2] = kBias + A.z;
-            V[3] = kBias + A.w;
+        const uint32_t ka = k0 < W ? k0 : 0u;  // k0 + 3 < 4 h; h is a multiple of 4: one region per chunk
+        const uint32_t m = k0 >= h && k0 < 3 * h && k0 < W ? k0 - h : 0u;
+        A[i] = ka < 2 * h ? ld4(z0 + ka) : ld4(z2 + (ka - 2 * h));
+        Bm[i] = ld4(z0 + m);
+        Cm[i] = ld4(z2 + m);
+        Dm[i] = ld4(dv + m);
+    }
+    const uint32_t kb = lane == 0 && w > 0 ? 256 * w * R - 1 : 0u;  // < W: the rows below hold words
+    const bool bmid = kb >= h && kb < 3 * h;
+    const uint32_t mb = bmid ? kb - h : 0u;
+    const uint32_t eb0 = kb < 2 * h ? z0[kb] : z2[kb - 2 * h], eb1 = z0[mb], eb2 = z2[mb], eb3 = dv[mb];
+    const bool sub = sgn0 == sgn1;
+    uint32_t xs[R][4], ys[R][4];
+    uint32_t top_prev = 0;  // high word of the previous row's last V (lane 63)
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                if (k0 + t > 0) V[t] -= uint64_t(1) << 31;
-            if (k0 >= h && k0 < 3 * h) {
-                const uint32_t m = k0 - h;
-                const uint4 B = ld4(z0 + m), C = ld4(z2 + m), Dd = ld4(dv + m);
-                V[0] += uint64_t(B.x) + C.x;
-                V[1] += uint64_t(B.y) + C.y;
-                V[2] += uint64_t(B.z) + C.z;
-                V[3] += uint64_t(B.w) + C.w;
-                if (sub) {
-                    V[0] -= Dd.x; V[1] -= Dd.y; V[2] -= Dd.z; V[3] -= Dd.w;
-                } else {
-                    V[0] += Dd.x; V[1] += Dd.y; V[2] += Dd.z; V[3] += Dd.w;
-                }
+    for (int i = 0; i < R; ++i) {
+        const uint32_t k0 = 4 * (64 * (w * R + uint32_t(i)) + lane);
+        uint64_t V[4] = {kBias + A[i].x, kBias + A[i].y, kBias + A[i].z, kBias + A[i].w};
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (k0 + t > 0) V[t] -= uint64_t(1) << 31;
+        if (k0 >= h && k0 < 3 * h) {
+            V[0] += uint64_t(Bm[i].x) + Cm[i].x;
+            V[1] += uint64_t(Bm[i].y) + Cm[i].y;
+            V[2] += uint64_t(Bm[i].z) + Cm[i].z;
+            V[3] += uint64_t(Bm[i].w) + Cm[i].w;
+            if (sub) {
+                V[0] -= Dm[i].x; V[1] -= Dm[i].y; V[2] -= Dm[i].z; V[3] -= Dm[i].w;
+            } else {
+                V[0] += Dm[i].x; V[1] += Dm[i].y; V[2] += Dm[i].z; V[3] += Dm[i].w;
             }
         }
-        // high word of V_(k0 - 1): the lane below, or recomputed at lane 0
+        // high word of V_(k0 - 1): the lane below; at lane 0 the previous
+        // row's lane 63, or for the wave's first row the word recomputed
         uint32_t below = __shfl_up(uint32_t(V[3] >> 32), 1);
-        if (lane == 0) below = k0 > 0 && k0 < W ? uint32_t(col(k0 - 1) >> 32) : 0u;
+        if (lane == 0) {
+            if (i > 0) {
+                below = top_prev;
+            } else if (kb > 0) {
+                uint64_t v = kBias - (uint64_t(1) << 31) + eb0;
+                if (bmid) {
+                    v += uint64_t(eb1) + eb2;
+                    v = sub ? v - eb3 : v + eb3;
+                }
+                below = uint32_t(v >> 32);
+            } else {
+                below = 0u;
+            }
+        }
+        top_prev = __builtin_amdgcn_readlane(uint32_t(V[3] >> 32), 63);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const bool in = k0 + uint32_t(t) < W;
@@ -299,7 +317,8 @@ __global__ __launch_bounds__(NW * 64) void kara_combine_kernel(Dst dst, const ui
 }
 
 // (waves, rows per wave) for an addition over `words` words: rows of 256
-// words, one per wave up to 16 waves, then 2 or 4 per wave.
+// words, one per wave up to 8 waves, then 2 per wave on 8 or 16 waves, then
+// 4 (512-thread workgroups up to 16 rows keep four workgroups per CU).
 struct Shape {
     int nw, r;
 };
@@ -307,7 +326,8 @@ Shape kara_shape(uint32_t words) {
     const uint32_t rows = (words + 255) / 256;
     if (rows > 32) return {16, 4};
     if (rows > 16) return {16, 2};
-    return {rows > 8 ? 16 : rows > 4 ? 8 : rows > 2 ? 4 : rows > 1 ? 2 : 1, 1};
+    if (rows > 8) return {8, 2};
+    return {rows > 4 ? 8 : rows > 2 ? 4 : rows > 1 ? 2 : 1, 1};
 }
 
 template <int NW, int R, class Src>
@@ -326,7 +346,7 @@ hipError_t launch_split(const Src &src, uint64_t grid, uint32_t hs, uint32_t *xa
     const Shape sh = kara_shape(hs);
 #define BI_KARA_SPLIT(NW_, R_) \
     if (sh.nw == NW_ && sh.r == R_) return launch_split_shape<NW_, R_>(src, grid, hs, xa, xb, sg, cnt_out, n_out, bl, st);
-    BI_KARA_SPLIT(1, 1) BI_KARA_SPLIT(2, 1) BI_KARA_SPLIT(4, 1) BI_KARA_SPLIT(8, 1) BI_KARA_SPLIT(16, 1)
+    BI_KARA_SPLIT(1, 1) BI_KARA_SPLIT(2, 1) BI_KARA_SPLIT(4, 1) BI_KARA_SPLIT(8, 1) BI_KARA_SPLIT(8, 2)
     BI_KARA_SPLIT(16, 2) BI_KARA_SPLIT(16, 4)
 #undef BI_KARA_SPLIT
     return hipErrorInvalidValue;
@@ -347,7 +367,7 @@ hipError_t launch_combine(const Dst &dst, uint32_t nparent, uint64_t grid, const
     const Shape sh = kara_shape(2 * nparent);
 #define BI_KARA_COMBINE(NW_, R_) \
     if (sh.nw == NW_ && sh.r == R_) return launch_combine_shape<NW_, R_>(dst, grid, z, sg, hs, st);
-    BI_KARA_COMBINE(1, 1) BI_KARA_COMBINE(2, 1) BI_KARA_COMBINE(4, 1) BI_KARA_COMBINE(8, 1) BI_KARA_COMBINE(16, 1)
+    BI_KARA_COMBINE(1, 1) BI_KARA_COMBINE(2, 1) BI_KARA_COMBINE(4, 1) BI_KARA_COMBINE(8, 1) BI_KARA_COMBINE(8, 2)
     BI_KARA_COMBINE(16, 2) BI_KARA_COMBINE(16, 4)
 #undef BI_KARA_COMBINE
     return hipErrorInvalidValue;
