@@ -643,19 +643,39 @@ __global__ __launch_bounds__(256) void ntt_fold_kernel(Coef coef, Src src, uint6
     }
 }
 
-// One workgroup per instance: the product = L + H with the ballot-adder.
-template <int NW, class Src>
+// One workgroup per instance: the product = L + H with the ballot-adder,
+// the addends of all R rows of a wave read at once into registers (chunk c:
+// L words 4 c .. 4 c + 3 and H's pair c - 1 at words 4 c, 4 c + 1).
+template <int NW, int R, class Src>
 __global__ __launch_bounds__(64 * NW) void ntt_carry_kernel(Src src, uint64_t base, uint64_t chunk,
                                                             const uint32_t *__restrict__ lh, uint64_t lh_stride,
                                                             uint32_t gmax) {
     __shared__ uint32_t summary[NW];
     const uint64_t cnt = chunk_count(src, base, chunk);
+    const uint32_t lane = lane_id(), w = wave_in_block();
     for (uint64_t q = blockIdx.x; q < cnt; q += gridDim.x) {
         const InstRef in = src.get(base + q);
-        const uint32_t nwords = 2 * in.n;
+        const uint32_t nwords = 2 * in.n, nchunks = (nwords + 3) / 4;
         const uint32_t *L = lh + q * lh_stride;
-        wg_add_rows<NW>(LHSrc4{L, reinterpret_cast<const uint2 *>(L + 4 * gmax), nwords}, in.c, nwords, summary);
-        __syncthreads();
+        const uint2 *H = reinterpret_cast<const uint2 *>(L + 4 * gmax);
+        uint32_t x[R][4], y[R][4];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const uint32_t c = 64 * (w * uint32_t(R) + uint32_t(i)) + lane;
+            const bool in_l = c < nchunks, in_h = in_l && c >= 1;
+            const uint4 l = reinterpret_cast<const uint4 *>(L)[in_l ? c : 0u];
+            const uint2 h = H[in_h ? c - 1 : 0u];
+            x[i][0] = l.x; x[i][1] = l.y; x[i][2] = l.z; x[i][3] = l.w;
+            y[i][0] = in_h ? h.x : 0u;
+            y[i][1] = in_h ? h.y : 0u;
+            y[i][2] = y[i][3] = 0u;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (!in_l || 4 * c + uint32_t(t) >= nwords) x[i][t] = y[i][t] = 0u;
+        }
+        const GlobalSink sink{in.c, nwords, (reinterpret_cast<uintptr_t>(in.c) & 15) == 0};
+        (void)wg_add_regs<NW, R>(x, y, nwords, sink, summary);
+        __syncthreads();  // summary is free for the next instance
     }
 }
 
@@ -741,7 +761,8 @@ static hipError_t launch_crt(const Coef &coef, const Src &src, uint64_t base, ui
     const uint64_t items = std::min(chunk, grid * 65536) * gmax;
     hipLaunchKernelGGL((ntt_fold_kernel<Src, Coef>), dim3(uint32_t(std::min<uint64_t>((items + 255) / 256, 65536))),
                        dim3(256), 0, st, coef, src, base, chunk, lh, lh_stride, gmax);
-    hipLaunchKernelGGL((ntt_carry_kernel<16, Src>), dim3(uint32_t(grid)), dim3(1024), 0, st, src, base, chunk, lh,
+    // 16 waves of 4 rows: up to 16384 words (gmax <= 4096)
+    hipLaunchKernelGGL((ntt_carry_kernel<16, 4, Src>), dim3(uint32_t(grid)), dim3(1024), 0, st, src, base, chunk, lh,
                        lh_stride, gmax);
     return hipGetLastError();
 }
