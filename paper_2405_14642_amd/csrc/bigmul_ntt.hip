@@ -970,19 +970,21 @@ hipError_t launch_bigmul_ntt64_list(const NttConst64 &K, const ListInst &src, ui
 // all of its entries before writing any).
 // ---------------------------------------------------------------------------
 
-// One thread per (column x, prime): the K-point column transforms of a and b
-// as their even (cyclic, H points) and odd (negacyclic: inputs times psi^i,
-// psi of order K) halves, pointwise Montgomery products, H-point inverses,
-// recombination c_j = (E_j + psi^-j O_j) / K, c_{j+H} = (E_j - psi^-j O_j) / K,
-// and the scale that undoes the Montgomery factor and the row transform's L.
+// Two waves per (64 columns x, prime): the K-point column transforms of a
+// and b as their even (cyclic, H points; wave 0) and odd (negacyclic: inputs
+// times psi^i, psi of order K; wave 1) halves, pointwise Montgomery
+// products, H-point inverses, then through LDS the recombination
+// c_j = (E_j + psi^-j O_j) / K (wave 0), c_{j+H} = (E_j - psi^-j O_j) / K
+// (wave 1), and the scale that undoes the Montgomery factor and the row
+// transform's L.
 template <int R>
-__global__ __launch_bounds__(64) void ntt_col_kernel(NttConst K, uint32_t *__restrict__ tr, uint32_t L, uint32_t M,
-                                                     uint32_t k) {
+__global__ __launch_bounds__(128) void ntt_col_kernel(NttConst K, uint32_t *__restrict__ tr, uint32_t L, uint32_t M,
+                                                      uint32_t k) {
     constexpr int H = 1 << R;
-    __shared__ uint32_t esh[H * 64];  // E_j of lane l at esh[64 j + l]
+    __shared__ uint32_t hsh[2][H * 64];  // E_j and psi^-j O_j of lane l at [64 j + l]
     const uint32_t wgs_per_prime = L / 64;
     const int pr = int(blockIdx.x / wgs_per_prime);  // uniform: twiddles come through scalar loads
-    const uint32_t lane = threadIdx.x;
+    const uint32_t half = wave_in_block(), lane = lane_id();
     const uint32_t x = (blockIdx.x - uint32_t(pr) * wgs_per_prime) * 64 + lane;
     const uint32_t p = K.p[pr], pneg = K.pneg[pr];
     const Fp32 f{p};
@@ -990,41 +992,40 @@ __global__ __launch_bounds__(64) void ntt_col_kernel(NttConst K, uint32_t *__res
     const uint32_t *col = tr + x;
     auto ld = [&](uint32_t slot) { return col[uint64_t(slot) * L]; };
     uint32_t ya[H], yb[H];
-    // even half: DFT_H of the zero-padded block columns
 #pragma unroll
     for (int i = 0; i < H; ++i) {
         ya[i] = uint32_t(i) < k ? ld(4 * i + pr) : 0u;
         yb[i] = uint32_t(i) < k ? ld(4 * i + 2 + pr) : 0u;
     }
-    small_dif<R>(ya, fw, f);
-    small_dif<R>(yb, fw, f);
+    if (half) {  // odd half: inputs twisted by psi^i (psi = w^(2^(14 - R)))
 #pragma unroll
-    for (int i = 0; i < H; ++i) ya[i] = mul_mont(ya[i], yb[i], p, pneg);
-    small_dit_inv<R>(ya, iw, f);
-#pragma unroll
-    for (int i = 0; i < H; ++i) esh[64 * i + lane] = ya[i];
-    // odd half: the same on inputs twisted by psi^i (psi = w^(2^(14 - R)))
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-        const uint2 ps = fw[uint32_t(i) << (14 - R)];
-        ya[i] = uint32_t(i) < k ? f.mulw(ld(4 * i + pr), ps) : 0u;
-        yb[i] = uint32_t(i) < k ? f.mulw(ld(4 * i + 2 + pr), ps) : 0u;
+        for (int i = 0; i < H; ++i) {
+            const uint2 ps = fw[uint32_t(i) << (14 - R)];
+            ya[i] = f.mulw(ya[i], ps);
+            yb[i] = f.mulw(yb[i], ps);
+        }
     }
     small_dif<R>(ya, fw, f);
     small_dif<R>(yb, fw, f);
 #pragma unroll
     for (int i = 0; i < H; ++i) ya[i] = mul_mont(ya[i], yb[i], p, pneg);
     small_dit_inv<R>(ya, iw, f);
+    if (half) {
+#pragma unroll
+        for (int j = 0; j < H; ++j) ya[j] = f.mulw(ya[j], iw[uint32_t(j) << (14 - R)]);
+    }
+#pragma unroll
+    for (int j = 0; j < H; ++j) hsh[half][64 * j + lane] = ya[j];
+    __syncthreads();
     // recombine and scale by 2^-(R + 1 + M) 2^32; rows v < 2k - 1
     const uint2 sc = make_uint2(K.scale[pr][R + 1 + M], K.scale_sh[pr][R + 1 + M]);
     const uint32_t nrows = 2 * k - 1;
     uint32_t *out = tr + x;
 #pragma unroll
     for (int j = 0; j < H; ++j) {
-        const uint32_t e = esh[64 * j + lane];
-        const uint32_t o = f.mulw(ya[j], iw[uint32_t(j) << (14 - R)]);
-        if (uint32_t(j) < nrows) out[uint64_t(2 * j + pr) * L] = f.mulw(f.add(e, o), sc);
-        if (uint32_t(j + H) < nrows) out[uint64_t(2 * (j + H) + pr) * L] = f.mulw(f.sub(e, o), sc);
+        const uint32_t e = hsh[0][64 * j + lane], o = hsh[1][64 * j + lane];
+        const uint32_t v = uint32_t(j) + half * H;
+        if (v < nrows) out[uint64_t(2 * v + pr) * L] = f.mulw(half ? f.sub(e, o) : f.add(e, o), sc);
     }
 }
 
@@ -1166,7 +1167,7 @@ hipError_t launch_rows(uint32_t M, const NttConst &K, const BlockInst &src, uint
 
 hipError_t launch_cols(uint32_t R, const NttConst &K, uint32_t *tr, uint32_t M, uint32_t k, hipStream_t st) {
     const uint32_t L = 1u << M;
-    const dim3 grid(2 * L / 64), blk(64);
+    const dim3 grid(2 * L / 64), blk(128);
     switch (R) {
         case 0: hipLaunchKernelGGL((ntt_col_kernel<0>), grid, blk, 0, st, K, tr, L, M, k); break;
         case 1: hipLaunchKernelGGL((ntt_col_kernel<1>), grid, blk, 0, st, K, tr, L, M, k); break;
