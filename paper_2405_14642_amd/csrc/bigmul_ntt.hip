@@ -1061,16 +1061,29 @@ struct LargeCoef {
     const uint32_t *tr;
     uint32_t L, bw2, nrows;  // bw2 = 2 bw coefficients per block; nrows = 2k - 1
     uint32_t p1, p2, crt, crt_sh;
-    __device__ __forceinline__ uint64_t entry(uint32_t v, uint32_t u) const {
-        const uint32_t r1 = tr[uint64_t(2 * v) * L + u], r2 = tr[uint64_t(2 * v + 1) * L + u];
-        const uint32_t tq = mul_shoup(sub_mod(r2, r1, p2), crt, crt_sh, p2);
-        return uint64_t(p1) * tq + r1;  // < p1 p2; equals c(v, u) (< 2^52)
+    // Garner: c(v, u) = p1 t + r1 < p1 p2 (it is below 2^52)
+    __device__ __forceinline__ uint32_t crt1(uint32_t r1, uint32_t r2) const {
+        return mul_shoup(sub_mod(r2, r1, p2), crt, crt_sh, p2);
     }
-    __device__ __forceinline__ uint64_t operator()(uint64_t P) const {
-        const uint32_t v = uint32_t(P / bw2), u = uint32_t(P - uint64_t(v) * bw2);
-        uint64_t c = v < nrows ? entry(v, u) : 0;
-        if (v >= 1 && v - 1 < nrows) c += entry(v - 1, u + bw2);
-        return c;  // < 2^53
+    // Coefficients P .. P + 3 (P a multiple of 4; bw2 is one too, so they lie
+    // in one block row): four rows' reads at once, at clamped rows where a
+    // term is absent (the scratch holds 4 k >= 2 nrows + 2 rows).
+    __device__ __forceinline__ void four(uint32_t P, uint64_t (&c)[4]) const {
+        const uint32_t v = P / bw2, u = P - v * bw2;
+        const bool t0 = v < nrows, t1 = v >= 1 && v - 1 < nrows;
+        const uint32_t va = t0 ? v : 0u, vb = t1 ? v - 1 : 0u;
+        const uint4 a1 = *reinterpret_cast<const uint4 *>(tr + uint64_t(2 * va) * L + u);
+        const uint4 a2 = *reinterpret_cast<const uint4 *>(tr + uint64_t(2 * va + 1) * L + u);
+        const uint4 b1 = *reinterpret_cast<const uint4 *>(tr + uint64_t(2 * vb) * L + u + bw2);
+        const uint4 b2 = *reinterpret_cast<const uint4 *>(tr + uint64_t(2 * vb + 1) * L + u + bw2);
+        const uint32_t x1[4] = {a1.x, a1.y, a1.z, a1.w}, x2[4] = {a2.x, a2.y, a2.z, a2.w};
+        const uint32_t y1[4] = {b1.x, b1.y, b1.z, b1.w}, y2[4] = {b2.x, b2.y, b2.z, b2.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint64_t ca = uint64_t(p1) * crt1(x1[e], x2[e]) + x1[e];
+            const uint64_t cb = uint64_t(p1) * crt1(y1[e], y2[e]) + y1[e];
+            c[e] = (t0 ? ca : 0ull) + (t1 ? cb : 0ull);  // < 2^53
+        }
     }
 };
 
@@ -1078,37 +1091,60 @@ struct LargeCoef {
 // < 2^70, written lo_w + m_w 2^32 (m_w < 2^38).  Then
 //     product = sum_w S_w 2^(32 w),  S_w = lo_w + (m_{w-1} mod 2^32) + floor(m_{w-2} / 2^32) < 2^34,
 // stored as the low words Lw[w] = S_w mod 2^32 and high words Hw[w + 1] =
-// floor(S_w / 2^32) for the final addition.  One thread per 8 words (it
-// recomputes the two words below its group).
+// floor(S_w / 2^32) for the final addition.  One thread per 8 words w0 ..
+// w0 + 7: it reads coefficients 2 w0 - 8 .. 2 w0 + 15 (six groups of four,
+// all issued before use) and recomputes the words below its group, so both
+// of its output runs, Lw[w0 ..] and Hw[w0 ..], are aligned 8-word stores.
 __global__ __launch_bounds__(256) void large_ntt_fold_kernel(LargeCoef coef, uint64_t nwords, uint32_t *__restrict__ Lw,
                                                              uint32_t *__restrict__ Hw) {
     const uint64_t ngroups = (nwords + 7) / 8;
+    const uint32_t pmax = uint32_t(2 * nwords - 4);  // last group of four coefficients
     for (uint64_t g = uint64_t(blockIdx.x) * 256 + threadIdx.x; g < ngroups; g += uint64_t(gridDim.x) * 256) {
         const uint64_t w0 = 8 * g;
-        uint32_t lo[10];
-        uint64_t m[10];
+        uint64_t cf[24];  // coefficient 2 w0 - 8 + i
 #pragma unroll
-        for (int i = 0; i < 10; ++i) {
-            const uint64_t w = w0 + uint64_t(i) - 2;  // wraps for w0 = 0, i < 2: then >= nwords
-            if (w >= nwords) {
-                lo[i] = 0;
-                m[i] = 0;
-                continue;
-            }
-            const uint64_t c0 = coef(2 * w), c1 = coef(2 * w + 1);
+        for (int q = 0; q < 6; ++q) {
+            const int64_t P = int64_t(2 * w0) - 8 + 4 * q;
+            const bool ok = P >= 0 && P <= int64_t(pmax);
+            uint64_t c4[4];
+            coef.four(ok ? uint32_t(P) : 0u, c4);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cf[4 * q + e] = ok ? c4[e] : 0ull;
+        }
+        // words w0 - 4 + i, i < 12
+        uint32_t lo[12];
+        uint64_t m[12];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            const uint64_t c0 = cf[2 * i], c1 = cf[2 * i + 1];
             const uint64_t t = c0 + ((c1 & 0xFFFFu) << 16);  // < 2^53 + 2^32
             lo[i] = uint32_t(t);
             m[i] = (t >> 32) + (c1 >> 16);
         }
+        // S_w for w = w0 - 1 + j, j < 9 (i = j + 3)
+        uint64_t S[9];
 #pragma unroll
-        for (int i = 2; i < 10; ++i) {
-            const uint64_t w = w0 + uint64_t(i) - 2;
-            if (w >= nwords) break;
-            const uint64_t sw = uint64_t(lo[i]) + uint32_t(m[i - 1]) + (m[i - 2] >> 32);
-            Lw[w] = uint32_t(sw);
-            if (w + 1 < nwords) Hw[w + 1] = uint32_t(sw >> 32);
+        for (int j = 0; j < 9; ++j) S[j] = uint64_t(lo[j + 3]) + uint32_t(m[j + 2]) + (m[j + 1] >> 32);
+        uint32_t lw[8], hw[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            lw[j] = uint32_t(S[j + 1]);
+            hw[j] = w0 + uint64_t(j) >= 1 ? uint32_t(S[j] >> 32) : 0u;  // Hw[w] = floor(S_(w-1) / 2^32), Hw[0] = 0
         }
-        if (g == 0) Hw[0] = 0;
+        if (w0 + 8 <= nwords) {
+            uint4 *pl = reinterpret_cast<uint4 *>(Lw + w0), *ph = reinterpret_cast<uint4 *>(Hw + w0);
+            pl[0] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+            pl[1] = make_uint4(lw[4], lw[5], lw[6], lw[7]);
+            ph[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+            ph[1] = make_uint4(hw[4], hw[5], hw[6], hw[7]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (w0 + uint64_t(j) < nwords) {
+                    Lw[w0 + j] = lw[j];
+                    Hw[w0 + j] = hw[j];
+                }
+        }
     }
 }
 
