@@ -30,15 +30,16 @@
 // registers (no atomics), and reads each A operand once for both: three
 // 1 KiB LDS reads per two MFMAs, the traffic that bounds the loop.
 //
-// 1024-limb products (nb = 128, eight supertiles) take a k-major order
-// instead.  Since B(st + i, u) = B(st, u - 32 i), a wave that owns four
+// 1024-limb products (nb = 128, eight supertiles) and 512-limb products
+// (nb = 64, four supertiles) take a k-major order instead.  Since B(st + i, u) = B(st, u - 32 i), a wave that owns four
 // consecutive supertiles sb + i and walks u = k + 32 m with the residue k
 // outer needs one A operand per m and one B operand beta_j = B(sb, k + 32 j)
 // per j: supertile sb + i at m takes A(k + 32 m) and beta_(m - i), so each
 // read serves up to four MFMAs (0.8 KiB per MFMA).  At nb = 128 the in-band
 // (i, m) of every residue form a fixed triangle: m <= i for supertiles 0-3
-// (k = 0 .. 31), m >= i for supertiles 4-7 (k = 1 .. 32).  The two waves of
-// a group take alternate residues and each finalises two of the four
+// (k = 0 .. 31), m >= i for supertiles 4-7 (k = 1 .. 32); at nb = 64 the
+// four supertiles form one group whose (i, m) are fixed for k = 1 .. 31.
+// The two waves of a group take alternate residues and each finalises two of the four
 // supertiles, adding the other wave's 64-bit partial word sums, passed
 // through LDS, to its own.
 //
@@ -115,26 +116,28 @@ __device__ __forceinline__ void recode_chunks(Chunks &x, uint32_t nchunks, uint3
     const uint32_t gb = add_words<4>(x.b, R, sb);
     const uint64_t Ga = ballot(ga != 0), Pa = ballot(c < nchunks && all_ones<4>(sa));
     const uint64_t Gb = ballot(gb != 0), Pb = ballot(c < nchunks && all_ones<4>(sb));
-    {
-        const WaveCarry ca = wave_carry(Ga, Pa, 0), cb = wave_carry(Gb, Pb, 0);
-        const uint32_t oa = valid >= 64 ? ca.out : uint32_t(ca.into >> valid) & 1u;
-        const uint32_t ob = valid >= 64 ? cb.out : uint32_t(cb.into >> valid) & 1u;
+    // carries out of this wave's chunks; one wave: the operands' carries
+    const WaveCarry ca0 = wave_carry(Ga, Pa, 0), cb0 = wave_carry(Gb, Pb, 0);
+    const uint32_t oa = valid >= 64 ? ca0.out : uint32_t(ca0.into >> valid) & 1u;
+    const uint32_t ob = valid >= 64 ? cb0.out : uint32_t(cb0.into >> valid) & 1u;
+    uint32_t cina = 0, cinb = 0, ta = oa, tb = ob;
+    if constexpr (NW > 1) {
         if (lane == 0) {
             summary[w] = oa | ((Pa == vmask ? 1u : 0u) << 1);
             summary[4 + w] = ob | ((Pb == vmask ? 1u : 0u) << 1);
         }
-    }
-    __syncthreads();
-    uint32_t cina = 0, cinb = 0, ta = 0, tb = 0;
+        __syncthreads();
+        ta = tb = 0;
 #pragma unroll
-    for (uint32_t v = 0; v < uint32_t(NW); ++v) {
-        const uint32_t sva = summary[v], svb = summary[4 + v];
-        if (v < w) {
-            cina = (sva & 1u) | ((sva >> 1) & cina);
-            cinb = (svb & 1u) | ((svb >> 1) & cinb);
+        for (uint32_t v = 0; v < uint32_t(NW); ++v) {
+            const uint32_t sva = summary[v], svb = summary[4 + v];
+            if (v < w) {
+                cina = (sva & 1u) | ((sva >> 1) & cina);
+                cinb = (svb & 1u) | ((svb >> 1) & cinb);
+            }
+            ta = (sva & 1u) | ((sva >> 1) & ta);
+            tb = (svb & 1u) | ((svb >> 1) & tb);
         }
-        ta = (sva & 1u) | ((sva >> 1) & ta);
-        tb = (svb & 1u) | ((svb >> 1) & tb);
     }
     t[0] = ta;
     t[1] = tb;
@@ -173,6 +176,49 @@ __device__ __forceinline__ void mfma_kmajor_1024(const uint8_t *lds, uint32_t oA
     }
 }
 
+// k-major MFMA steps of a 512-limb product (nb = 64: supertiles 0 .. 3, one
+// group of two waves), residues k = k0, k0 + 2, .. 31.  At k = 1 .. 31
+// supertile i takes u = k + 32 m for m in [max(0, i - 2), min(i, 1)], whose
+// B is beta_(m - i): two A and three B reads feed six MFMAs.  Residue 0 takes
+// u = 0, 32, 64 instead (m = 2 lies in band for supertiles 2 and 3 only
+// there, and u = 0 / u = 32 leave the bands of supertiles 2 / 3).
+template <int X>
+__device__ __forceinline__ void mfma_kmajor_512(const uint8_t *lds, uint32_t oA, const uint8_t *bbs, int32_t k0,
+                                                v16i (&acc)[4]) {
+    auto beta = [bbs](int32_t k, int32_t j) { return *reinterpret_cast<const v4i *>(bbs - 16 * (k + 32 * j)); };
+    // operands of residue k: A(k), A(k + 32), beta_0, beta_-1, beta_-2
+    auto operands = [&](int32_t k, v4i (&o)[5]) {
+        o[0] = load_a(lds, oA, k);
+        o[1] = load_a(lds, oA, k + 32);
+        o[2] = beta(k, 0);
+        o[3] = beta(k, -1);
+        o[4] = beta(k, -2);
+    };
+    int32_t k = k0;
+    if (k0 == 0) {
+        const v4i A0 = load_a(lds, oA, 0), A1 = load_a(lds, oA, 32), A2 = load_a(lds, oA, 64);
+        const v4i b0 = beta(0, 0), b1 = beta(0, -1);
+        acc[0 ^ X] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, b0, acc[0 ^ X], 0, 0, 0);
+        acc[1 ^ X] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, b1, acc[1 ^ X], 0, 0, 0);
+        acc[1 ^ X] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, b0, acc[1 ^ X], 0, 0, 0);
+        acc[2 ^ X] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, b1, acc[2 ^ X], 0, 0, 0);
+        acc[2 ^ X] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A2, b0, acc[2 ^ X], 0, 0, 0);
+        acc[3 ^ X] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A2, b1, acc[3 ^ X], 0, 0, 0);
+        k = 2;
+    }
+#pragma unroll 1
+    for (; k < 32; k += 2) {
+        v4i o[5];
+        operands(k, o);
+        acc[0 ^ X] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o[0], o[2], acc[0 ^ X], 0, 0, 0);
+        acc[1 ^ X] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o[0], o[3], acc[1 ^ X], 0, 0, 0);
+        acc[1 ^ X] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o[1], o[2], acc[1 ^ X], 0, 0, 0);
+        acc[2 ^ X] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o[0], o[4], acc[2 ^ X], 0, 0, 0);
+        acc[2 ^ X] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o[1], o[3], acc[2 ^ X], 0, 0, 0);
+        acc[3 ^ X] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o[1], o[4], acc[3 ^ X], 0, 0, 0);
+    }
+}
+
 // Lane-order mask (lane r + 32 g) to chunk order (chunk 2 r + g).
 __device__ __forceinline__ uint64_t lanes_to_chunks(uint64_t m) {
     auto spread = [](uint32_t x) {
@@ -207,10 +253,14 @@ __host__ __device__ inline uint32_t xchg_offset(const MfmaLayout &l, uint32_t nw
 // workgroups per SIMD, their per-product phases are latency chains, and the
 // unbounded kernel's 180 registers allow only 2.  Larger ones keep the
 // compiler's choice.
-// KM: every product has 1017-1024 limbs (n32p = 1024) and takes the k-major
-// MFMA order (NW = 4).
-template <int NW, int OCC, class Src, bool KM>
+// KM: every product has 1017-1024 limbs (n32p = 1024, NW = 4) or 505-512
+// limbs (n32p = 512, NW = 2) and takes the k-major MFMA order.
+// S1: every product fits one supertile (n32p <= 128, NW = 1): one row of
+// accumulators, words and carries.
+template <int NW, int OCC, class Src, bool KM, bool S1 = false>
 __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
+    constexpr int NT = S1 ? 1 : 2;  // rows (supertiles) a wave finalises
+    static_assert(!S1 || (NW == 1 && !KM), "one supertile takes one wave");
     extern __shared__ __align__(16) uint8_t lds[];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = wave_in_block();
     constexpr uint32_t T = 64 * NW;
@@ -286,7 +336,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
         const uint32_t r = lane & 31u, g = lane >> 5;
         const uint32_t pw = (wave + uint32_t(pair % NW)) % NW;
         const uint32_t s0 = 2 * pw, s1 = s0 + 1;
-        const bool has0 = pw < npt, has1 = has0 && s1 < nst;
+        const bool has0 = pw < npt, has1 = !S1 && has0 && s1 < nst;
         const uint32_t oA = 8 * (r + kPA - 16 * g - 15);
         uint32_t Lo[2][4] = {}, Hi[2][4] = {};
         // Lo / Hi of supertile st from its coefficient sums acc (plus the
@@ -320,11 +370,14 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
         if constexpr (KM) {
             // group pw / 2 = supertiles 4 (pw / 2) + i, residues of parity
             // pw % 2; all eight supertiles exist (has0 = has1 = true)
-            static_assert(NW == 4, "the k-major order takes four waves");
+            static_assert(NW == 2 || NW == 4, "the k-major order takes two or four waves");
             const uint32_t grp = pw >> 1, q = pw & 1u;
             const uint8_t *bbs = bpl + g * 16 * NBE + 16 * (32 * 4 * grp + r + kBPad);
             v16i acc[4] = {};
-            if (grp == 0) {
+            if constexpr (NW == 2) {
+                if (q == 0) mfma_kmajor_512<0>(lds, oA, bbs, 0, acc);
+                else mfma_kmajor_512<2>(lds, oA, bbs, 1, acc);
+            } else if (grp == 0) {
                 if (q == 0) mfma_kmajor_1024<false, 0>(lds, oA, bbs, 0, acc);
                 else mfma_kmajor_1024<false, 2>(lds, oA, bbs, 1, acc);
             } else {
@@ -364,7 +417,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
                 }
                 const int64_t none[4] = {};
 #pragma unroll
-                for (int t = 0; t < 2; ++t) finalise(acc[t], s0 + uint32_t(t), none, Lo[t], Hi[t]);
+                for (int t = 0; t < NT; ++t) finalise(acc[t], s0 + uint32_t(t), none, Lo[t], Hi[t]);
             }
         }
         // 4. product = L + H in registers.  Lane (r, g) holds the low and
@@ -376,7 +429,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
         //    every stored word and only carry upwards).
         uint32_t x[2][4], hv[2][4], y[2][4];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < NT; ++t) {
             const auto l02 = __builtin_amdgcn_permlane32_swap(Lo[t][0], Lo[t][2], false, false);
             const auto l13 = __builtin_amdgcn_permlane32_swap(Lo[t][1], Lo[t][3], false, false);
             const auto h02 = __builtin_amdgcn_permlane32_swap(Hi[t][0], Hi[t][2], false, false);
@@ -389,18 +442,19 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
         // row st - 1 (the other row of this wave, or the wave below's, passed
         // in the recode summary words, dead by now)
         uint32_t *bnd = summary;
-        if (lane == 0) bnd[pw] = __builtin_amdgcn_readlane(hv[1][3], 63);
+        if constexpr (NW > 1)
+            if (lane == 0) bnd[pw] = __builtin_amdgcn_readlane(hv[NT - 1][3], 63);
         const int src = int(g ? lane - 32 : lane + 31);
         uint32_t below[2];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) below[t] = __shfl(hv[t][3], src);
-        __syncthreads();
+        for (int t = 0; t < NT; ++t) below[t] = __shfl(hv[t][3], src);
+        if constexpr (NW > 1) __syncthreads();
         if (lane == 0) {
             below[0] = pw > 0 ? bnd[pw - 1] : 0u;
-            below[1] = __builtin_amdgcn_readlane(hv[0][3], 63);
+            if constexpr (NT > 1) below[1] = __builtin_amdgcn_readlane(hv[0][3], 63);
         }
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < NT; ++t) {
             y[t][0] = below[t];
             y[t][1] = hv[t][0];
             y[t][2] = hv[t][1];
@@ -412,20 +466,22 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
         uint32_t sm[2][4];
         uint64_t G[2], Pm[2];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < NT; ++t) {
             const uint32_t gc = add_words<4>(x[t], y[t], sm[t]);
             G[t] = lanes_to_chunks(ballot(gc != 0));
             Pm[t] = lanes_to_chunks(ballot(all_ones<4>(sm[t])));
         }
         uint32_t cin = 0, allp = 1;
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < NT; ++t) {
             cin = wave_carry(G[t], Pm[t], cin).out;
             allp &= Pm[t] == ~0ull ? 1u : 0u;
         }
         uint32_t *csum = summary + 8;
-        if (lane == 0) csum[pw] = cin | (allp << 1);
-        __syncthreads();
+        if constexpr (NW > 1) {
+            if (lane == 0) csum[pw] = cin | (allp << 1);
+            __syncthreads();
+        }
         cin = 0;
         for (uint32_t v = 0; v < pw; ++v) {
             const uint32_t sv = csum[v];
@@ -433,7 +489,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
         }
         const GlobalSink sink{in.c, 2 * n32, (reinterpret_cast<uintptr_t>(in.c) & 15) == 0};
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < NT; ++t) {
             const WaveCarry wc = wave_carry(G[t], Pm[t], cin);
             add_carry_words<4>(sm[t], uint32_t(wc.into >> cpos) & 1u);
             cin = wc.out;
@@ -461,10 +517,10 @@ static uint32_t mfma_lds_bytes(uint32_t nmax) {
     return KM ? std::max(l.total, xchg_offset(l, NW) + NW * 4096u) : l.total;
 }
 
-template <int NW, int OCC, class Src, bool KM = false>
+template <int NW, int OCC, class Src, bool KM = false, bool S1 = false>
 static hipError_t launch_nw(const Src &src, uint32_t nmax, uint64_t count, hipStream_t st, int num_cus) {
     const uint32_t lds_bytes = mfma_lds_bytes<NW, KM>(nmax);
-    const void *fn = reinterpret_cast<const void *>(&bigmul_mfma_kernel<NW, OCC, Src, KM>);
+    const void *fn = reinterpret_cast<const void *>(&bigmul_mfma_kernel<NW, OCC, Src, KM, S1>);
     // (LDS bytes << 32 | resident workgroups per CU) of the last launch shape
     static std::atomic<uint64_t> occ{0}, lds_set{0};
     hipError_t e = lds_limit_once(fn, lds_set);
@@ -481,7 +537,7 @@ static hipError_t launch_nw(const Src &src, uint32_t nmax, uint64_t count, hipSt
     const uint64_t cap = uint64_t(uint32_t(o)) * uint64_t(num_cus > 0 ? num_cus : 1);
     const uint32_t grid = uint32_t(count < cap ? count : cap);
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((bigmul_mfma_kernel<NW, OCC, Src, KM>), dim3(grid), dim3(64 * NW), lds_bytes, st, src);
+    hipLaunchKernelGGL((bigmul_mfma_kernel<NW, OCC, Src, KM, S1>), dim3(grid), dim3(64 * NW), lds_bytes, st, src);
     return hipGetLastError();
 }
 
@@ -493,7 +549,8 @@ static hipError_t launch_mfma(const Src &src, uint32_t nmax, uint64_t count, hip
             // one-wave workgroups: registers for 4 per SIMD when LDS holds 16
             // per CU (3, sized the same way at 2^13 bits, measured slower)
             if (mfma_layout((nmax + 7) & ~7u).total * 16 <= 160 * 1024)
-                return launch_nw<1, 4>(src, nmax, count, st, num_cus);
+                return ((nmax + 7) & ~7u) <= 128 ? launch_nw<1, 4, Src, false, true>(src, nmax, count, st, num_cus)
+                                                 : launch_nw<1, 4>(src, nmax, count, st, num_cus);
             return launch_nw<1, 1>(src, nmax, count, st, num_cus);
         case 2: return launch_nw<2, 1>(src, nmax, count, st, num_cus);
         default: return launch_nw<4, 1>(src, nmax, count, st, num_cus);
@@ -504,8 +561,10 @@ hipError_t launch_bigmul_mfma(const uint32_t *a, const uint32_t *b, uint32_t *c,
                               hipStream_t st, int num_cus) {
     if (batch == 0) return hipSuccess;
     const UniformInst src{a, b, c, n32, batch};
-    // 1017-1024 limbs: eight supertiles of 128 digit blocks, the k-major order
+    // 1017-1024 limbs (eight supertiles, 128 digit blocks) and 505-512 limbs
+    // (four supertiles, 64 digit blocks): the k-major order
     if (((n32 + 7) & ~7u) == 1024) return launch_nw<4, 3, UniformInst, true>(src, n32, batch, st, num_cus);
+    if (((n32 + 7) & ~7u) == 512) return launch_nw<2, 3, UniformInst, true>(src, n32, batch, st, num_cus);
     return launch_mfma(src, n32, batch, st, num_cus);
 }
 
