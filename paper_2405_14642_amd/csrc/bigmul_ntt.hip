@@ -1095,17 +1095,57 @@ struct LargeCoef {
 // w0 + 7: it reads coefficients 2 w0 - 8 .. 2 w0 + 15 (six groups of four,
 // all issued before use) and recomputes the words below its group, so both
 // of its output runs, Lw[w0 ..] and Hw[w0 ..], are aligned 8-word stores.
+// A workgroup covers one tile of kLargeTileWords words and also records how
+// the tile's part of Lw + Hw passes a carry (the status read by
+// large_ntt_add_kernel): bit 0 = it carries out by itself, bit 1 = every
+// word of its sum is all-ones (it carries out exactly when a carry comes in).
+constexpr uint32_t kLargeTileWords = 8 * 256;
+
+// Tile status from the threads' 8-word sums (carry out g, all-ones p), and
+// the carry into each thread given the carry cin into the tile.  summary:
+// 4 LDS words.  Returns the carry into the calling thread.
+__device__ __forceinline__ uint32_t tile_carries(uint32_t g, bool p, uint32_t cin, uint32_t *summary,
+                                                 uint8_t *status) {
+    const uint32_t lane = lane_id(), w = wave_in_block();
+    const uint64_t G = ballot(g != 0), P = ballot(p);
+    const WaveCarry w0 = wave_carry(G, P, 0);
+    if (lane == 0) summary[w] = w0.out | ((P == ~0ull ? 1u : 0u) << 1);
+    __syncthreads();
+    uint32_t c = cin, tg = 0, tp = 1;
+#pragma unroll
+    for (uint32_t v = 0; v < 4; ++v) {
+        const uint32_t sv = summary[v];
+        if (v < w) c = (sv & 1u) | ((sv >> 1) & c);
+        tg = (sv & 1u) | ((sv >> 1) & tg);
+        tp &= sv >> 1;
+    }
+    if (status) *status = uint8_t(tg | (tp << 1));
+    __syncthreads();  // summary is free again
+    return uint32_t(wave_carry(G, P, c).into >> lane) & 1u;
+}
+
+// The 8 words of L + H (carry-in 0) at one thread: carry out and sum.
+__device__ __forceinline__ uint32_t fold_sum8(const uint32_t (&lw)[8], const uint32_t (&hw)[8], uint32_t (&sm)[8],
+                                              bool &ones) {
+    const uint32_t g = add_words<8>(lw, hw, sm);
+    ones = all_ones<8>(sm);
+    return g;
+}
+
 __global__ __launch_bounds__(256) void large_ntt_fold_kernel(LargeCoef coef, uint64_t nwords, uint32_t *__restrict__ Lw,
-                                                             uint32_t *__restrict__ Hw) {
-    const uint64_t ngroups = (nwords + 7) / 8;
+                                                             uint32_t *__restrict__ Hw, uint8_t *__restrict__ status) {
+    __shared__ uint32_t summary[4];
+    const uint64_t ngroups = (nwords + 7) / 8, ntiles = (nwords + kLargeTileWords - 1) / kLargeTileWords;
     const uint32_t pmax = uint32_t(2 * nwords - 4);  // last group of four coefficients
-    for (uint64_t g = uint64_t(blockIdx.x) * 256 + threadIdx.x; g < ngroups; g += uint64_t(gridDim.x) * 256) {
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t g = tile * 256 + threadIdx.x;
+        const bool act = g < ngroups;
         const uint64_t w0 = 8 * g;
         uint64_t cf[24];  // coefficient 2 w0 - 8 + i
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             const int64_t P = int64_t(2 * w0) - 8 + 4 * q;
-            const bool ok = P >= 0 && P <= int64_t(pmax);
+            const bool ok = act && P >= 0 && P <= int64_t(pmax);
             uint64_t c4[4];
             coef.four(ok ? uint32_t(P) : 0u, c4);
 #pragma unroll
@@ -1131,13 +1171,13 @@ __global__ __launch_bounds__(256) void large_ntt_fold_kernel(LargeCoef coef, uin
             lw[j] = uint32_t(S[j + 1]);
             hw[j] = w0 + uint64_t(j) >= 1 ? uint32_t(S[j] >> 32) : 0u;  // Hw[w] = floor(S_(w-1) / 2^32), Hw[0] = 0
         }
-        if (w0 + 8 <= nwords) {
+        if (act && w0 + 8 <= nwords) {
             uint4 *pl = reinterpret_cast<uint4 *>(Lw + w0), *ph = reinterpret_cast<uint4 *>(Hw + w0);
             pl[0] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
             pl[1] = make_uint4(lw[4], lw[5], lw[6], lw[7]);
             ph[0] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
             ph[1] = make_uint4(hw[4], hw[5], hw[6], hw[7]);
-        } else {
+        } else if (act) {
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 if (w0 + uint64_t(j) < nwords) {
@@ -1145,6 +1185,68 @@ __global__ __launch_bounds__(256) void large_ntt_fold_kernel(LargeCoef coef, uin
                     Hw[w0 + j] = hw[j];
                 }
         }
+        // words at or above nwords are zero (the product has nwords words)
+        uint32_t sm[8];
+        bool ones = false;
+        const uint32_t gc = fold_sum8(lw, hw, sm, ones);
+        (void)tile_carries(act ? gc : 0u, act && ones, 0u, summary, threadIdx.x == 0 ? status + tile : nullptr);
+    }
+}
+
+// product = Lw + Hw (nwords words), one tile per workgroup.  The carry into
+// tile t comes from the statuses below it: the nearest tile j < t that does
+// not merely propagate gives it (its own carry out), none gives 0.  Every
+// read of L, H and the statuses is issued before the scans that use them.
+__global__ __launch_bounds__(256) void large_ntt_add_kernel(const uint32_t *__restrict__ Lw,
+                                                            const uint32_t *__restrict__ Hw,
+                                                            const uint8_t *__restrict__ status, uint32_t *out,
+                                                            uint32_t nwords) {
+    __shared__ uint32_t summary[4];
+    __shared__ uint32_t tile_cin;
+    const uint32_t ntiles = (nwords + kLargeTileWords - 1) / kLargeTileWords;
+    const uint32_t lane = lane_id(), wave = wave_in_block();
+    const GlobalSink sink{out, nwords, (reinterpret_cast<uintptr_t>(out) & 15) == 0};
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t g = tile * 256 + threadIdx.x, w0 = 8 * g;
+        uint32_t lw[8], hw[8];
+        if (w0 + 8 <= nwords) {
+            const uint4 *pl = reinterpret_cast<const uint4 *>(Lw + w0), *ph = reinterpret_cast<const uint4 *>(Hw + w0);
+            const uint4 l0 = pl[0], l1 = pl[1], h0 = ph[0], h1 = ph[1];
+            lw[0] = l0.x; lw[1] = l0.y; lw[2] = l0.z; lw[3] = l0.w;
+            lw[4] = l1.x; lw[5] = l1.y; lw[6] = l1.z; lw[7] = l1.w;
+            hw[0] = h0.x; hw[1] = h0.y; hw[2] = h0.z; hw[3] = h0.w;
+            hw[4] = h1.x; hw[5] = h1.y; hw[6] = h1.z; hw[7] = h1.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                lw[j] = w0 + uint32_t(j) < nwords ? Lw[w0 + j] : 0u;
+                hw[j] = w0 + uint32_t(j) < nwords ? Hw[w0 + j] : 0u;
+            }
+        }
+        if (wave == 0) {
+            // tiles t - 1 - lane - 64 q, nearest first; below tile 0 nothing
+            // carries (status 0)
+            uint32_t cin = 0;
+            for (int64_t base = int64_t(tile) - 1; base >= 0; base -= 64) {
+                const int64_t j = base - int64_t(lane);
+                const uint32_t sv = j >= 0 ? status[j] : 0u;
+                const uint64_t stop = ballot((sv & 2u) == 0);
+                if (stop) {
+                    cin = __shfl(sv, int(__ffsll(static_cast<unsigned long long>(stop)) - 1)) & 1u;
+                    break;
+                }
+            }
+            if (lane == 0) tile_cin = cin;
+        }
+        uint32_t sm[8];
+        bool ones = false;
+        const uint32_t gc = fold_sum8(lw, hw, sm, ones);
+        __syncthreads();
+        const uint32_t c = tile_carries(gc, ones, tile_cin, summary, nullptr);
+        add_carry_words<8>(sm, c);
+        const uint32_t s0[4] = {sm[0], sm[1], sm[2], sm[3]}, s1[4] = {sm[4], sm[5], sm[6], sm[7]};
+        sink(2 * g, s0);
+        sink(2 * g + 1, s1);
     }
 }
 
@@ -1152,7 +1254,7 @@ namespace {
 
 struct LargeNttLayout {
     uint32_t k, M, R;
-    size_t tr, lw, hw, ascr, total;
+    size_t tr, lw, hw, st, total;
 };
 
 LargeNttLayout large_ntt_layout(uint64_t n32, uint32_t bw) {
@@ -1166,9 +1268,8 @@ LargeNttLayout large_ntt_layout(uint64_t n32, uint32_t bw) {
     s.tr = 0;
     s.lw = al(s.tr + size_t(4) * s.k * (size_t(1) << s.M) * sizeof(uint32_t));
     s.hw = al(s.lw + nwords * sizeof(uint32_t));
-    s.ascr = al(s.hw + (nwords + 1) * sizeof(uint32_t));
-    // the addition's chunk width follows out's alignment: size for the narrowest
-    s.total = al(s.ascr + large_add_scratch_bytes(large_add_tiles(nwords, 1)));
+    s.st = al(s.hw + (nwords + 1) * sizeof(uint32_t));
+    s.total = al(s.st + (nwords + kLargeTileWords - 1) / kLargeTileWords);
     return s;
 }
 
@@ -1245,13 +1346,17 @@ hipError_t launch_bigmul_large_ntt(const Ctx &c, const uint32_t *a, const uint32
     if (e == hipSuccess) e = launch_cols(s.R, K, tr, s.M, s.k, st);
     if (e == hipSuccess) e = launch_rows(s.M, K, src, tr, 2 * nrows, false, st);
     if (e != hipSuccess) return e;
-    const uint64_t nwords = 2 * n32, groups = (nwords + 7) / 8;
+    // L, H and the tile statuses, then L + H with each tile's carry-in
+    // derived from the statuses below it
+    const uint64_t nwords = 2 * n32, ntiles = (nwords + kLargeTileWords - 1) / kLargeTileWords;
+    auto *status = scratch + s.st;
     const LargeCoef coef{tr, 1u << s.M, 2 * bw, nrows, K.p[0], K.p[1], K.crt, K.crt_sh};
-    hipLaunchKernelGGL(large_ntt_fold_kernel, dim3(uint32_t(std::min<uint64_t>((groups + 255) / 256, 65536))),
-                       dim3(256), 0, st, coef, nwords, Lw, Hw);
+    const uint32_t grid = uint32_t(std::min<uint64_t>(ntiles, 65536));
+    hipLaunchKernelGGL(large_ntt_fold_kernel, dim3(grid), dim3(256), 0, st, coef, nwords, Lw, Hw, status);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_bigadd_large(Lw, Hw, out, nullptr, nwords, scratch + s.ascr, st, c.num_cus);
+    hipLaunchKernelGGL(large_ntt_add_kernel, dim3(grid), dim3(256), 0, st, Lw, Hw, status, out, uint32_t(nwords));
+    return hipGetLastError();
 }
 
 }  // namespace bi

@@ -136,10 +136,14 @@ def test_ntt_block_count_edges(B, ctx, orc, n):
     check(orc, a, b, run(B, ctx, a, b))
 
 
-def test_2_22_bits_all_ones(B, ctx, orc):
-    """A 2^22-bit product of all-ones operands: (2^N - 1)^2, every entry of
-    the two-dimensional convolution at its bound, checked in full."""
-    n = 1 << 17
+@pytest.mark.parametrize("n", [1 << 17, 1 << 18, 1 << 19])
+def test_large_all_ones(B, ctx, orc, n):
+    """Products of 2^22, 2^23 and 2^24 bits of all-ones operands: (2^N - 1)^2,
+    every entry of the two-dimensional convolution at its bound, checked in
+    full against the closed form.  In the final addition of the low and high
+    words the carry out of the lowest 2048-word tile runs through every tile
+    of the lower half (63, 127 and 255 tiles that only propagate), and so
+    does the upper half's from the middle tile."""
     a = np.full(n, 0xFFFFFFFF, dtype=np.uint32)
     got = run(B, ctx, a, a.copy())
     exp = np.concatenate([[1], np.zeros(n - 1), [0xFFFFFFFE], np.full(n - 1, 0xFFFFFFFF)]).astype(np.uint32)
