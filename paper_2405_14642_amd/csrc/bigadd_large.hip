@@ -24,6 +24,14 @@
 // the fix-up's few chunks.  A single-pass decoupled look-back scan would save
 // the summary round trip but makes workgroups spin on their predecessors.
 //
+// Up to 512 tiles (2^21 words in 16-byte chunks) two kernels do instead,
+// where the four launches' latency outweighs a second read of a and b: a
+// summary pass, then a pass that finds each tile's carry-in from the
+// summaries below it (the nearest tile that does not only propagate gives
+// its own carry out) and stores the final sum.  Measured on one 2^20 /
+// 2^24 / 2^28-bit pair: 14.0 / 13.7 / 28.0 -> 11.7 / 11.4 / 32.9 us with two
+// passes (all-ones plus one: 19.9 / 21.8 / 48.5 -> 12.0 / 11.4 / 35.4 us).
+//
 // The chunk width W (16, 8 or 4 bytes) follows the pointers' alignment; the
 // integer's length need not be a multiple of it: the missing words of the
 // last chunk read as all ones in a and zero in b (and as all ones when the
@@ -43,6 +51,7 @@ constexpr int kLargeU = 4;   // rows of 64 chunks per wave
 constexpr int kRowsPerTile = kLargeNW * kLargeU;
 constexpr int kScanThreads = 1024;
 constexpr uint64_t kMaxTileGrid = uint64_t(1) << 22;  // workgroups of the tile pass
+constexpr uint64_t kTwoPassTiles = 512;                // up to this many tiles: two passes
 
 // Summary bytes are padded to whole 16-byte words; padding is never read as
 // a tile.
@@ -72,11 +81,19 @@ __device__ __forceinline__ void store_chunk(uint32_t *p, uint64_t c, uint64_t m,
     }
 }
 
-template <int W, bool NT>
+// MODE kTileSums: store each tile's sum with carry-in 0 and its summary;
+// kTileSummary: the summary only; kTileFinal (after a kTileSummary pass):
+// take the tile's carry-in from the summaries below it, store the final sum
+// and, at the last tile, the carry out of the integer.
+enum TileMode { kTileSums, kTileSummary, kTileFinal };
+
+template <int W, bool NT, int MODE = kTileSums>
 __global__ __launch_bounds__(64 * kLargeNW) void large_add_tile_kernel(const uint32_t *a, const uint32_t *b,
                                                                        uint32_t *out, uint8_t *summary, uint64_t m,
-                                                                       uint32_t tail, uint64_t tiles) {
+                                                                       uint32_t tail, uint64_t tiles,
+                                                                       uint8_t *carry_out = nullptr) {
     __shared__ uint32_t summ[kLargeNW];
+    __shared__ uint32_t tile_cin;
     const uint32_t lane = lane_id();
     const uint32_t wave = wave_in_block();
     const uint64_t rows = (m + 63) / 64;
@@ -110,9 +127,28 @@ __global__ __launch_bounds__(64 * kLargeNW) void large_add_tile_kernel(const uin
                 allp &= (P[u] == vmask) ? 1u : 0u;
             }
         }
+        if constexpr (MODE == kTileFinal) {
+            // the nearest tile below that does not only propagate gives the
+            // carry-in (its own carry out); below tile 0 nothing carries.
+            // Lanes read tiles t - 1 - lane - 64 q, nearest first.
+            if (wave == 0) {
+                uint32_t c0 = 0;
+                for (int64_t base = int64_t(t) - 1; base >= 0; base -= 64) {
+                    const int64_t j = base - int64_t(lane);
+                    const uint32_t sv = j >= 0 ? summary[j] : 0u;
+                    const uint64_t stop = ballot((sv & 2u) == 0);
+                    if (stop) {  // uniform
+                        c0 = __shfl(sv, int(__ffsll(static_cast<unsigned long long>(stop)) - 1)) & 1u;
+                        break;
+                    }
+                }
+                if (lane == 0) tile_cin = c0;
+            }
+        }
         if (lane == 0) summ[wave] = cout | (allp << 1);
         __syncthreads();
-        uint32_t cin = 0, tg = 0, tp = 1;
+        const uint32_t tcin = MODE == kTileFinal ? tile_cin : 0u;
+        uint32_t cin = tcin, tg = 0, tp = 1;
 #pragma unroll
         for (int v = 0; v < kLargeNW; ++v) {
             const uint32_t sv = summ[v];
@@ -120,19 +156,25 @@ __global__ __launch_bounds__(64 * kLargeNW) void large_add_tile_kernel(const uin
             tg = (sv & 1u) | ((sv >> 1) & tg);
             tp &= sv >> 1;
         }
+        if constexpr (MODE != kTileSummary) {
 #pragma unroll
-        for (int u = 0; u < kLargeU; ++u) {
-            if (r0 + u < rows) {  // uniform
-                const uint64_t c = (r0 + u) * 64 + lane;
-                const uint64_t valid = std::min<uint64_t>(m - (r0 + u) * 64, 64);
-                const WaveCarry wc = wave_carry(G[u], P[u], cin);
-                add_carry_words<W>(s[u], uint32_t(wc.into >> lane) & 1u);
-                if (c < m) store_chunk<W, NT>(out, c, m, tail, s[u]);
-                cin = valid >= 64 ? wc.out : uint32_t(wc.into >> valid) & 1u;
+            for (int u = 0; u < kLargeU; ++u) {
+                if (r0 + u < rows) {  // uniform
+                    const uint64_t c = (r0 + u) * 64 + lane;
+                    const uint64_t valid = std::min<uint64_t>(m - (r0 + u) * 64, 64);
+                    const WaveCarry wc = wave_carry(G[u], P[u], cin);
+                    add_carry_words<W>(s[u], uint32_t(wc.into >> lane) & 1u);
+                    if (c < m) store_chunk<W, NT>(out, c, m, tail, s[u]);
+                    cin = valid >= 64 ? wc.out : uint32_t(wc.into >> valid) & 1u;
+                }
             }
         }
-        if (threadIdx.x == 0) summary[t] = uint8_t(tg | (tp << 1));
-        __syncthreads();  // summ is rewritten by the next tile
+        if constexpr (MODE == kTileFinal) {
+            if (carry_out && t == tiles - 1 && threadIdx.x == 0) *carry_out = uint8_t(tg | (tp & tcin));
+        } else {
+            if (threadIdx.x == 0) summary[t] = uint8_t(tg | (tp << 1));
+        }
+        __syncthreads();  // summ and tile_cin are rewritten by the next tile
     }
 }
 
@@ -276,8 +318,18 @@ hipError_t launch_large_w(const uint32_t *a, const uint32_t *b, uint32_t *out, u
     // One tile per workgroup (the hardware keeps the CUs fed; a persistent
     // grid looping over tiles measured 17 % slower), looping only past 2^22.
     const uint64_t grid = std::min<uint64_t>(tiles, kMaxTileGrid);
+    if (tiles <= kTwoPassTiles) {
+        // summaries, then every tile's final sum with its carry-in found
+        // from them: two launches instead of four; a and b are read twice
+        // (the second time mostly from the caches)
+        hipLaunchKernelGGL((large_add_tile_kernel<W, false, kTileSummary>), dim3(uint32_t(grid)), dim3(64 * kLargeNW), 0,
+                           st, a, b, out, summary, m, tail, tiles, nullptr);
+        hipLaunchKernelGGL((large_add_tile_kernel<W, NT, kTileFinal>), dim3(uint32_t(grid)), dim3(64 * kLargeNW), 0, st,
+                           a, b, out, summary, m, tail, tiles, carry);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((large_add_tile_kernel<W, NT>), dim3(uint32_t(grid)), dim3(64 * kLargeNW), 0, st, a, b, out,
-                       summary, m, tail, tiles);
+                       summary, m, tail, tiles, nullptr);
     hipLaunchKernelGGL(large_add_scan_kernel, dim3(1), dim3(kScanThreads), 0, st,
                        reinterpret_cast<const uint4 *>(summary), reinterpret_cast<uint4 *>(tile_cin), carry, walk_count,
                        tiles);
