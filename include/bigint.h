@@ -132,9 +132,10 @@ bi_status bigadd_large(bi_ctx *ctx, const void *a, const void *b, void *out, uin
  * coefficients are transformed along the block (length 4 * block words)
  * and the results across the blocks (length 2k rounded up to a power of
  * two), modulo the two primes of BI_MUL_NTT; pointwise products, both
- * inverses, CRT, a fold into words and bigadd_large's kernels give the
- * product.  Scratch: 16 k (4 block words) bytes of transforms plus 17 n
- * bytes of fold and addition buffers (n = 32-bit words of an operand).
+ * inverses, CRT, a fold into low and high words (with the carry status of
+ * every 2048-word tile) and one addition kernel give the product.  Scratch:
+ * 16 k (4 block words) bytes of transforms plus about 16 n bytes of low and
+ * high words (n = 32-bit words of an operand).
  * algo BI_MUL_SCHOOL_VALU, BI_MUL_SCHOOL_MFMA, BI_MUL_NTT_PF64 or
  * BI_MUL_KARATSUBA: k^2 block products of that algorithm (block_bits 2^16,
  * 2^17 or 2^18, 0: 2^16 up to 2^20-bit operands, 2^18 above) as one ragged
