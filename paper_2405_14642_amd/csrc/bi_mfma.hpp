@@ -60,17 +60,28 @@ __device__ __forceinline__ v4i load_a(const uint8_t *lds, uint32_t oA, int32_t u
     return v4i{int(uint32_t(x0)), int(uint32_t(x0 >> 32)), int(uint32_t(x1)), int(uint32_t(x1 >> 32))};
 }
 
+// The same operand without the laundering: the compiler may read both
+// windows with one ds_read2_b64 (half the LDS rate, no address arithmetic),
+// for loops bound by instruction issue rather than by LDS bandwidth.
+__device__ __forceinline__ v4i load_a_plain(const uint8_t *lds, uint32_t oA, int32_t u) {
+    const uint32_t p0 = oA + 256 * uint32_t(u);
+    const uint64_t x0 = *reinterpret_cast<const uint64_t *>(lds + p0);
+    const uint64_t x1 = *reinterpret_cast<const uint64_t *>(lds + p0 + 64);
+    return v4i{int(uint32_t(x0)), int(uint32_t(x0 >> 32)), int(uint32_t(x1)), int(uint32_t(x1 >> 32))};
+}
+
 // MFMA steps u in [ua, ub) for supertile s0 (M bit 0) and/or s1 = s0 + 1
 // (M bit 1), which share the A operand T_u.  bb0 / bb1: this lane's B entry
 // of step 0 for s0 / s1 (the entry of step u is 16 u bytes lower).
 // acc[0] accumulates s0, acc[1] s1.
-template <int M>
+template <int M, bool PLAIN = false>
 __device__ __forceinline__ void mfma_steps(int32_t ua, int32_t ub, const uint8_t *lds, uint32_t oA,
                                            const uint8_t *bb0, const uint8_t *bb1, v16i (&acc)[2]) {
     auto ldB = [](const uint8_t *bb, int32_t u) -> v4i { return *reinterpret_cast<const v4i *>(bb - 16 * u); };
     int32_t u = ua;
     for (; u + 1 < ub; u += 2) {
-        const v4i a0 = load_a(lds, oA, u), a1 = load_a(lds, oA, u + 1);
+        const v4i a0 = PLAIN ? load_a_plain(lds, oA, u) : load_a(lds, oA, u);
+        const v4i a1 = PLAIN ? load_a_plain(lds, oA, u + 1) : load_a(lds, oA, u + 1);
         v4i p0 = {}, p1 = {}, q0 = {}, q1 = {};
         if (M & 1) { p0 = ldB(bb0, u); p1 = ldB(bb0, u + 1); }
         if (M & 2) { q0 = ldB(bb1, u); q1 = ldB(bb1, u + 1); }
@@ -80,7 +91,7 @@ __device__ __forceinline__ void mfma_steps(int32_t ua, int32_t ub, const uint8_t
         if (M & 2) acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, q1, acc[1], 0, 0, 0);
     }
     if (u < ub) {
-        const v4i a0 = load_a(lds, oA, u);
+        const v4i a0 = PLAIN ? load_a_plain(lds, oA, u) : load_a(lds, oA, u);
         if (M & 1) acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, ldB(bb0, u), acc[0], 0, 0, 0);
         if (M & 2) acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, ldB(bb1, u), acc[1], 0, 0, 0);
     }

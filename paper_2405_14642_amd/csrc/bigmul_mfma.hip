@@ -410,7 +410,15 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
                 const int32_t lo1 = has1 ? max(0, int32_t(32 * s1) - int32_t(nb) + 1) : hi0;
                 const int32_t hi1 = has1 ? min(int32_t(nb), int32_t(32 * s1 + 31)) + 1 : hi0;
                 v16i acc[2] = {};
-                mfma_steps<1>(lo0, min(lo1, hi0), lds, oA, bb0, bb1, acc);
+                if constexpr (S1) {
+                    // one supertile, whose band is never empty: its first
+                    // step starts the accumulator
+                    acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                        load_a_plain(lds, oA, lo0), *reinterpret_cast<const v4i *>(bb0 - 16 * lo0), v16i{}, 0, 0, 0);
+                    mfma_steps<1, true>(lo0 + 1, hi0, lds, oA, bb0, bb1, acc);
+                } else {
+                    mfma_steps<1>(lo0, min(lo1, hi0), lds, oA, bb0, bb1, acc);
+                }
                 if (has1) {
                     mfma_steps<3>(lo1, hi0, lds, oA, bb0, bb1, acc);
                     mfma_steps<2>(max(hi0, lo1), hi1, lds, oA, bb0, bb1, acc);
