@@ -111,8 +111,10 @@ bi_status bigadd(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t *
  * BI_EALIAS.  Pointers must be limb-aligned (BI_ELIMB); 16-byte alignment of
  * a, b and out gives the widest accesses.  Runs four kernels on `stream`
  * (tile sums with tile carry summaries, a scan of the summaries, carry
- * fix-up, a walk of tiles the carry crosses) using about 6 bytes of context
- * scratch per tile of 1024 chunks; BI_ENOMEM if that scratch cannot grow.
+ * fix-up, a walk of tiles the carry crosses), or up to 512 tiles two (the
+ * summaries, then each tile's sum with its carry-in found from the summaries
+ * below it), using about 6 bytes of context scratch per tile of 1024
+ * chunks; BI_ENOMEM if that scratch cannot grow.
  * Asynchronous like every call.
  */
 bi_status bigadd_large(bi_ctx *ctx, const void *a, const void *b, void *out, uint8_t *carry_out,
