@@ -268,6 +268,9 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
 
     Chunks x;
     if (uint64_t(blockIdx.x) < count) fetch_chunks(src.get(blockIdx.x), 64 * wave + lane, x);
+    // padded size whose zero pads the LDS holds (nothing else writes them,
+    // so they are cleared again only when the layout changes)
+    uint32_t pads_for = 0;
 
     for (uint64_t pair = blockIdx.x; pair < count; pair += gridDim.x) {
         const InstRef in = src.get(pair);
@@ -295,16 +298,19 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
                 v.w = __builtin_bswap32(x.b[0]);
                 *reinterpret_cast<uint4 *>(bpl + (c & 1u) * 16 * NBE + 16 * (kBPad + (c >> 1))) = v;
             }
-            const uint32_t zlo = kPA / 16, zhi = (lo.A0S - kPA - D) / 16;
-            for (uint32_t i = tid; i < zlo + zhi; i += T) {
-                const uint32_t q = i < zlo ? i : (kPA + D) / 16 + (i - zlo);
-                *reinterpret_cast<uint4 *>(adg + 16 * q) = make_uint4(0, 0, 0, 0);
-            }
-            const uint32_t nz = kBPad + kBTail;
-            for (uint32_t i = tid; i < 2 * nz; i += T) {
-                const uint32_t pl = i / nz, e = i - pl * nz;
-                const uint32_t ent = e < kBPad ? e : nb + e;
-                *reinterpret_cast<uint4 *>(bpl + pl * 16 * NBE + 16 * ent) = make_uint4(0, 0, 0, 0);
+            if (n32p != pads_for) {  // uniform
+                pads_for = n32p;
+                const uint32_t zlo = kPA / 16, zhi = (lo.A0S - kPA - D) / 16;
+                for (uint32_t i = tid; i < zlo + zhi; i += T) {
+                    const uint32_t q = i < zlo ? i : (kPA + D) / 16 + (i - zlo);
+                    *reinterpret_cast<uint4 *>(adg + 16 * q) = make_uint4(0, 0, 0, 0);
+                }
+                const uint32_t nz = kBPad + kBTail;
+                for (uint32_t i = tid; i < 2 * nz; i += T) {
+                    const uint32_t pl = i / nz, e = i - pl * nz;
+                    const uint32_t ent = e < kBPad ? e : nb + e;
+                    *reinterpret_cast<uint4 *>(bpl + pl * 16 * NBE + 16 * ent) = make_uint4(0, 0, 0, 0);
+                }
             }
         }
         __syncthreads();
