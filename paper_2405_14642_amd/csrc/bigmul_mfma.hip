@@ -255,12 +255,12 @@ __host__ __device__ inline uint32_t xchg_offset(const MfmaLayout &l, uint32_t nw
 // compiler's choice.
 // KM: every product has 1017-1024 limbs (n32p = 1024, NW = 4) or 505-512
 // limbs (n32p = 512, NW = 2) and takes the k-major MFMA order.
-// S1: every product fits one supertile (n32p <= 128, NW = 1): one row of
-// accumulators, words and carries.
+// S1: one supertile per wave (every product has at most NW supertiles):
+// one row of accumulators, words and carries per wave.
 template <int NW, int OCC, class Src, bool KM, bool S1 = false>
 __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
     constexpr int NT = S1 ? 1 : 2;  // rows (supertiles) a wave finalises
-    static_assert(!S1 || (NW == 1 && !KM), "one supertile takes one wave");
+    static_assert(!(S1 && KM), "the k-major order takes two supertiles per wave");
     extern __shared__ __align__(16) uint8_t lds[];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = wave_in_block();
     constexpr uint32_t T = 64 * NW;
@@ -337,11 +337,11 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
 
         // 3. MFMA.  Wave role p (rotating with the pair so that every SIMD
         //    sees the light band-edge and heavy middle supertiles) finalises
-        //    supertiles s0 = 2 p and s1 = 2 p + 1.
-        const uint32_t nst = (n32p + 127) / 128, npt = (nst + 1) / 2;
+        //    supertiles s0 = 2 p and s1 = 2 p + 1 (S1: supertile p).
+        const uint32_t nst = (n32p + 127) / 128, npt = (nst + NT - 1) / NT;
         const uint32_t r = lane & 31u, g = lane >> 5;
         const uint32_t pw = (wave + uint32_t(pair % NW)) % NW;
-        const uint32_t s0 = 2 * pw, s1 = s0 + 1;
+        const uint32_t s0 = NT * pw, s1 = s0 + 1;
         const bool has0 = pw < npt, has1 = !S1 && has0 && s1 < nst;
         const uint32_t oA = 8 * (r + kPA - 16 * g - 15);
         uint32_t Lo[2][4] = {}, Hi[2][4] = {};
@@ -417,8 +417,8 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
                 const int32_t hi1 = has1 ? min(int32_t(nb), int32_t(32 * s1 + 31)) + 1 : hi0;
                 v16i acc[2] = {};
                 if constexpr (S1) {
-                    // one supertile, whose band is never empty: its first
-                    // step starts the accumulator
+                    // one supertile, whose band is never empty (32 s0 < 2 nb):
+                    // its first step starts the accumulator
                     acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
                         load_a_plain(lds, oA, lo0), *reinterpret_cast<const v4i *>(bb0 - 16 * lo0), v16i{}, 0, 0, 0);
                     mfma_steps<1, true>(lo0 + 1, hi0, lds, oA, bb0, bb1, acc);
