@@ -69,20 +69,25 @@ constexpr uint32_t kBPad = 32;   // zero B entries before block 0
 constexpr uint32_t kBTail = 31;  // zero B entries after the last block
 
 struct MfmaLayout {  // byte offsets into the dynamic LDS block
-    uint32_t D, nb, NE, NBE;
+    uint32_t D, nb, NE, NBE, bpad;  // bpad: zero B entries before block 0
     uint32_t a0, A0S, bpl, sum, total;
 };
 
-__host__ __device__ inline MfmaLayout mfma_layout(uint32_t n32p) {
+// one: products of a single supertile (n32p <= 128, one wave), whose B reads
+// cover blocks -16 .. 31 and whose A reads stay below window D + 57: a
+// layout of 6.8 KB at 128 limbs (six workgroups per SIMD) instead of 8.1.
+__host__ __device__ inline MfmaLayout mfma_layout(uint32_t n32p, bool one = false) {
     MfmaLayout l;
     l.D = 4 * n32p;
     l.nb = l.D / 32;
-    // 8-byte windows: the MFMA loop reads entries below D + 89
-    l.NE = (l.D + 89 + 31) & ~31u;
+    // 8-byte windows: the MFMA loop reads entries below D + 89 (D + 57 with
+    // one supertile)
+    l.NE = ((one ? l.D + 57 : l.D + 89) + 31) & ~31u;
     // digits of a with kPA zero bytes before and zeros up to NE + 16
     l.a0 = 8 * l.NE;
     l.A0S = (l.NE + 16 + 15) & ~15u;
-    l.NBE = kBPad + l.nb + kBTail;
+    l.bpad = one ? 16u : kBPad;
+    l.NBE = one ? 48u : kBPad + l.nb + kBTail;
     l.bpl = l.a0 + l.A0S;
     l.sum = l.bpl + 2 * 16 * l.NBE;
     l.total = l.sum + 3 * 16;
@@ -275,8 +280,8 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
     for (uint64_t pair = blockIdx.x; pair < count; pair += gridDim.x) {
         const InstRef in = src.get(pair);
         const uint32_t n32 = in.n, n32p = (n32 + 7) & ~7u;
-        const MfmaLayout lo = mfma_layout(n32p);
-        const uint32_t D = lo.D, nb = lo.nb, NE = lo.NE, NBE = lo.NBE;
+        const MfmaLayout lo = mfma_layout(n32p, S1 && NW == 1);
+        const uint32_t D = lo.D, nb = lo.nb, NE = lo.NE, NBE = lo.NBE, bpad = lo.bpad;
         uint8_t *bpl = lds + lo.bpl;
         uint32_t *summary = reinterpret_cast<uint32_t *>(lds + lo.sum);
         const uint32_t nchunks = n32p / 4;
@@ -296,7 +301,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
                 v.y = __builtin_bswap32(x.b[2]);
                 v.z = __builtin_bswap32(x.b[1]);
                 v.w = __builtin_bswap32(x.b[0]);
-                *reinterpret_cast<uint4 *>(bpl + (c & 1u) * 16 * NBE + 16 * (kBPad + (c >> 1))) = v;
+                *reinterpret_cast<uint4 *>(bpl + (c & 1u) * 16 * NBE + 16 * (bpad + (c >> 1))) = v;
             }
             if (n32p != pads_for) {  // uniform
                 pads_for = n32p;
@@ -305,10 +310,10 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
                     const uint32_t q = i < zlo ? i : (kPA + D) / 16 + (i - zlo);
                     *reinterpret_cast<uint4 *>(adg + 16 * q) = make_uint4(0, 0, 0, 0);
                 }
-                const uint32_t nz = kBPad + kBTail;
+                const uint32_t nz = NBE - nb;
                 for (uint32_t i = tid; i < 2 * nz; i += T) {
                     const uint32_t pl = i / nz, e = i - pl * nz;
-                    const uint32_t ent = e < kBPad ? e : nb + e;
+                    const uint32_t ent = e < bpad ? e : nb + e;
                     *reinterpret_cast<uint4 *>(bpl + pl * 16 * NBE + 16 * ent) = make_uint4(0, 0, 0, 0);
                 }
             }
@@ -361,7 +366,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
                     const uint32_t m = w - n32p, cc = m >> 2;
                     const uint32_t aw = *reinterpret_cast<const uint32_t *>(adg + kPA + 4 * m);
                     const uint32_t bw = *reinterpret_cast<const uint32_t *>(
-                        bpl + (cc & 1u) * 16 * NBE + 16 * (kBPad + (cc >> 1)) + 4 * (3 - (m & 3u)));
+                        bpl + (cc & 1u) * 16 * NBE + 16 * (bpad + (cc >> 1)) + 4 * (3 - (m & 3u)));
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
                         c[e] += int32_t(tA) * sbyte(bw, 3 - e) + int32_t(tB) * sbyte(aw, e);
@@ -378,7 +383,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
             // pw % 2; all eight supertiles exist (has0 = has1 = true)
             static_assert(NW == 2 || NW == 4, "the k-major order takes two or four waves");
             const uint32_t grp = pw >> 1, q = pw & 1u;
-            const uint8_t *bbs = bpl + g * 16 * NBE + 16 * (32 * 4 * grp + r + kBPad);
+            const uint8_t *bbs = bpl + g * 16 * NBE + 16 * (32 * 4 * grp + r + bpad);
             v16i acc[4] = {};
             if constexpr (NW == 2) {
                 if (q == 0) mfma_kmajor_512<0>(lds, oA, bbs, 0, acc);
@@ -409,7 +414,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void bigmul_mfma_kernel(Src src) {
             }
         } else {
             if (has0) {
-                const uint8_t *bb0 = bpl + g * 16 * NBE + 16 * (32 * s0 + r + kBPad);
+                const uint8_t *bb0 = bpl + g * 16 * NBE + 16 * (32 * s0 + r + bpad);
                 const uint8_t *bb1 = bb0 + 16 * 32;
                 const int32_t lo0 = max(0, int32_t(32 * s0) - int32_t(nb) + 1);
                 const int32_t hi0 = min(int32_t(nb), int32_t(32 * s0 + 31)) + 1;
@@ -525,15 +530,15 @@ static uint32_t mfma_waves(uint32_t nmax) {
 
 // Dynamic LDS bytes of a launch whose products have at most nmax limbs:
 // the largest layout, with the partial-sum exchange where it lies past it.
-template <int NW, bool KM>
+template <int NW, bool KM, bool S1 = false>
 static uint32_t mfma_lds_bytes(uint32_t nmax) {
-    const MfmaLayout l = mfma_layout((nmax + 7) & ~7u);
+    const MfmaLayout l = mfma_layout((nmax + 7) & ~7u, S1 && NW == 1);
     return KM ? std::max(l.total, xchg_offset(l, NW) + NW * 4096u) : l.total;
 }
 
 template <int NW, int OCC, class Src, bool KM = false, bool S1 = false>
 static hipError_t launch_nw(const Src &src, uint32_t nmax, uint64_t count, hipStream_t st, int num_cus) {
-    const uint32_t lds_bytes = mfma_lds_bytes<NW, KM>(nmax);
+    const uint32_t lds_bytes = mfma_lds_bytes<NW, KM, S1>(nmax);
     const void *fn = reinterpret_cast<const void *>(&bigmul_mfma_kernel<NW, OCC, Src, KM, S1>);
     // (LDS bytes << 32 | resident workgroups per CU) of the last launch shape
     static std::atomic<uint64_t> occ{0}, lds_set{0};
