@@ -74,6 +74,9 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU baseline budget")
     p.add_argument("--sizes", default="", help="comma-separated subset of sizes in bits (profiling runs)")
     p.add_argument("--algos", default="valu,mfma,ntt,ntt64,kara", help="multiplication algorithms to time")
+    p.add_argument("--graph-replays", action="store_true",
+                   help="NTT sizes: also time the best call per size as HIP-graph replays (off by default: a "
+                        "capture in the process measured the stream workload's host-binned queue slower)")
     return p.parse_args()
 
 
@@ -388,7 +391,7 @@ def bench_mul(args, kind):
             results[str(bits)]["best"] = best[0]
             step_ms += best[1] / 1e3
             step_pairs += batch
-            if kind == "ntt":
+            if kind == "ntt" and args.graph_replays:
                 results[str(bits)]["graph"] = graph_replay_timing(ctx, B, A, Bt, out, ALGO_IDS[best[0]], args.steps)
         del A, Bt, out
     ctx.close()
